@@ -1,0 +1,247 @@
+/*
+ * hubbard_chfsi.h - C ABI of the MI355X (gfx950) library for the hot path of
+ * real-space Hubbard-corrected DFT (arXiv:2507.23612): Chebyshev-filtered
+ * subspace iteration of the operator
+ *
+ *   H[D] = -1/2 Delta_h + V_loc + sum_I chi_I Gamma_I chi_I^H dV
+ *          + sum_{I in U} Phi_I U_I (1/2 - D_I) Phi_I^H dV
+ *
+ * on a uniform periodic grid (Sec. II.B), with the Dudarev energy
+ * E_U = sum_{sigma I} U_I/2 Tr(D - D^2) (Sec. II.A, Eq. E_U), occupation
+ * matrices D (Eq. orbital_occup_ext) and the Hubbard potential derived from
+ * them (Sec. II.A potential section, Eq. DerED).
+ *
+ * Conventions
+ *   - grid node (i,j,k) is at (i h1, j h2, k h3), 0-based, h_a = L_a / n_a;
+ *     linear index i + n1*(j + n2*k) (x fastest); quadrature weight
+ *     dV = h1 h2 h3 (trapezoidal rule, Sec. II.B);
+ *   - a block of ncol states is column-major nd x ncol with leading
+ *     dimension ld >= nd: state j starts at element j*ld.  Real blocks hold
+ *     double (FP64 mode) or float (mixed mode); blocks at k != 0 hold
+ *     interleaved complex values of the same precision;
+ *   - orbitals are normalised as dV sum |psi|^2 = 1 (bohr^-3/2); energies are
+ *     in hartree; lengths in bohr; k-points are Cartesian, bohr^-1;
+ *   - occupation matrices are passed as [nspin][n_hubbard_atoms][5][5]
+ *     row-major doubles (real: every k-point set used here is closed under
+ *     k -> -k, which makes D real).
+ *
+ * Ownership and threading
+ *   - every host array passed to a call is read during the call only and
+ *     copied where it must persist; the caller keeps ownership;
+ *   - device memory comes from the caller: hcu_workspace_size() tells how many
+ *     bytes the context needs, hcu_bind() hands over one device buffer and
+ *     the HIP stream all work is queued on.  The library does not free it;
+ *   - device pointers passed to compute calls must be valid on the bound
+ *     device and stream; calls return once the work is queued unless stated;
+ *   - a context is not thread-safe; distinct contexts are independent.
+ *
+ * Errors
+ *   - every call returns an hcu_status; HCU_OK = 0.  Arguments are validated
+ *     on the host before any device work is queued; on error nothing is
+ *     queued and hcu_last_error(ctx) describes the problem.  No C++
+ *     exception crosses this interface.
+ */
+#ifndef HUBBARD_CHFSI_H
+#define HUBBARD_CHFSI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hcu_status {
+  HCU_OK = 0,
+  HCU_INVALID_ARG = 1,    /* a size, pointer or option is invalid          */
+  HCU_OOM = 2,            /* bound workspace too small                     */
+  HCU_NOT_SPD = 3,        /* Gram matrix of the filtered block not SPD     */
+  HCU_NOT_CONVERGED = 4,  /* SCF reached max_iter (state stays usable)     */
+  HCU_NAN = 5,            /* non-finite value in inputs or results         */
+  HCU_DEVICE = 6,         /* HIP / rocSOLVER reported an error             */
+  HCU_NOT_BOUND = 7       /* compute call before hcu_bind()                */
+} hcu_status;
+
+typedef enum hcu_precision {
+  HCU_FP64 = 0,   /* every step in double                                     */
+  HCU_MIXED = 1   /* filter stencil and blocks in FP32; projector and RR
+                     contractions on FP32 MFMA with FP32 accumulation;
+                     Cholesky, subspace eigensolve, occupations, D, E_U in FP64 */
+} hcu_precision;
+
+#define HCU_MAX_KB 4
+
+/* One species (Sec. II.B: atom-centred functions = real Y_lm x radial, cut
+ * where the radial value drops below `threshold` and not stored beyond). */
+typedef struct hcu_species {
+  double vloc_depth;            /* V_loc = -depth exp(-r^2/(2 width^2)), Ha  */
+  double vloc_width;            /* bohr                                      */
+  int    n_kb;                  /* number of KB channels (<= HCU_MAX_KB)     */
+  int    kb_l[HCU_MAX_KB];      /* channel angular momentum, 0 or 1          */
+  double kb_gamma[HCU_MAX_KB];  /* channel energy, Ha                        */
+  double kb_width;              /* radial N r^l exp(-r^2/(2 w^2)), bohr      */
+  int    hub_l;                 /* Hubbard manifold l (0..2), -1 = none      */
+  double hub_U;                 /* effective U, Ha                           */
+  int    hub_power;             /* Hubbard radial N r^p exp(-alpha r)        */
+  double hub_alpha;             /* bohr^-1                                   */
+  double threshold;             /* truncation value, bohr^-3/2 (> 0)         */
+} hcu_species;
+
+/* The problem statement (Sec. II.B grid and stencil; Sec. II.A atoms,
+ * orbitals, U, spins and k-points). */
+typedef struct hcu_problem {
+  double L[3];                  /* orthorhombic cell lengths, bohr           */
+  int    n[3];                  /* grid points per axis (each >= 2; a stencil
+                                   wider than the cell wraps several times)  */
+  int    n0;                    /* half stencil order: FD order is 2*n0      */
+  int    nspin;                 /* 1 (unpolarised) or 2                      */
+  int    nk;                    /* number of k-points                        */
+  const double* kpts;           /* [nk][3], Cartesian bohr^-1                */
+  const double* kw;             /* [nk], weights summing to 1                */
+  int    natom;
+  const int*    atom_species;   /* [natom] index into species                */
+  const double* pos;            /* [natom][3], bohr                          */
+  int    nspecies;
+  const hcu_species* species;   /* [nspecies]                                */
+  int    ns;                    /* states per (spin, k)                      */
+  double nelec;                 /* electrons in the cell                     */
+  double kT;                    /* Fermi-Dirac smearing, Ha (> 0)            */
+  int    degree;                /* Chebyshev filter degree (>= 1)            */
+  int    precision;             /* hcu_precision                             */
+  int    lowdin;                /* 1: Loewdin-orthonormalise Hubbard orbitals
+                                   per atom (O^-1/2, O = Phi^H Phi dV)       */
+} hcu_problem;
+
+typedef struct hcu_scf_opts {
+  int    max_iter;              /* SCF iterations (>= 1)                     */
+  int    first_passes;          /* filter + Rayleigh-Ritz passes, 1st iter   */
+  int    lanczos_steps;         /* steps of the spectral upper bound         */
+  int    pulay_history;         /* Pulay mixing history (>= 1)               */
+  double pulay_beta;            /* mixing parameter                          */
+  double tol_d;                 /* stop when |D_out - D_in|_F < tol_d ...    */
+  double tol_f;                 /* ... and |F_n - F_{n-1}| / natom < tol_f   */
+  int    fixed_iterations;      /* > 0: run exactly this many, no test       */
+  int    verbose;               /* 1: one line per iteration on stderr       */
+} hcu_scf_opts;
+
+typedef struct hcu_scf_report {
+  int    iterations;
+  int    converged;
+  double F;                     /* Mermin free energy of the model, Ha       */
+  double E_U;                   /* Hubbard energy, both spin channels        */
+  double e_band;
+  double residual;              /* last |D_out - D_in|_F                     */
+  double seconds;               /* wall time of the SCF loop                 */
+  double filter_seconds;        /* of which: filters + H Y of Rayleigh-Ritz  */
+  double hx_columns;            /* number of single-column H applications    */
+} hcu_scf_report;
+
+typedef struct hcu_energies {
+  double F;                     /* e_band - dc + E_U - kT S                  */
+  double e_band;                /* g_s sum_k w_k sum_j f_j lambda_j          */
+  double dc;                    /* sum Tr(M(D_in) D_out) over spins, atoms   */
+  double E_U;                   /* sum_sigma sum_I U/2 Tr(D - D^2)           */
+  double ts;                    /* kT S                                      */
+  double mu;                    /* Fermi level                               */
+} hcu_energies;
+
+typedef struct hcu_ctx hcu_ctx;
+
+/* Create a context from the problem statement: validates it, builds the
+ * per-atom support lists (grid nodes within the truncation radius of any
+ * periodic image) and sizes the device workspace.  Host arrays are copied.
+ * Errors: HCU_INVALID_ARG (bad sizes, species, l > 2, n0 outside 1..6, ...). */
+hcu_status hcu_create(const hcu_problem* p, hcu_ctx** out);
+
+/* Free the context (not the bound device buffer). NULL is ignored. */
+void hcu_destroy(hcu_ctx* ctx);
+
+/* Text of the last error on this context (valid until the next call). */
+const char* hcu_last_error(const hcu_ctx* ctx);
+
+/* Device bytes the context needs (orbital blocks for every spin and k-point,
+ * three filter/Rayleigh-Ritz work blocks, tables, small dense buffers). */
+hcu_status hcu_workspace_size(const hcu_ctx* ctx, size_t* bytes);
+
+/* Bind `bytes` of device memory at `dev_ptr` (256-byte aligned) and the HIP
+ * stream `stream` (NULL = default stream); evaluates V_loc and every atom-
+ * centred function on the grid (Sec. II.B) on the device.  Errors:
+ * HCU_OOM if bytes < hcu_workspace_size(), HCU_DEVICE on a HIP error. */
+hcu_status hcu_bind(hcu_ctx* ctx, void* dev_ptr, size_t bytes, void* stream);
+
+/* Hubbard occupation matrices D_in (host, [nspin][nhub][5][5] row-major;
+ * rows/cols beyond 2l+1 ignored for l < 2) defining H[D] (Sec. II.A). */
+hcu_status hcu_set_hubbard_occupation(hcu_ctx* ctx, const double* D);
+
+/* Number of atoms carrying a Hubbard manifold (in atom order). */
+int hcu_num_hubbard_atoms(const hcu_ctx* ctx);
+
+/* Copy a start block X0 (device, nd x ns, ld = nd, the context precision)
+ * and a Lanczos start vector v0 (device, nd, same precision) for spin
+ * `spin`, k-point `ik`.  These are the random draws of the method; the
+ * caller supplies them so runs are reproducible. */
+hcu_status hcu_set_start(hcu_ctx* ctx, int spin, int ik, const void* X0, const void* v0);
+
+/* Y = H[D] X for ncol states (device pointers, column-major, leading
+ * dimension ld >= nd, context precision; X and Y must not overlap).
+ * Includes kinetic stencil of order 2 n0 with Bloch wrap, V_loc, KB and
+ * Hubbard terms (Sec. II.A potential; Sec. II.B implementation).
+ * Errors: HCU_INVALID_ARG (spin/ik out of range, ncol < 1 or > ns, ld < nd). */
+hcu_status hcu_apply_h(hcu_ctx* ctx, int spin, int ik, const void* X, void* Y,
+                       int ncol, int64_t ld);
+
+/* Scaled degree-m Chebyshev filter Y = p_m(H) X on [a, b] normalised at aL
+ * (the filter of Chebyshev-filtered subspace iteration, Sec. II.B).  Uses the
+ * context's work blocks, so ncol <= ns.  Errors as hcu_apply_h, plus
+ * HCU_INVALID_ARG unless aL < a < b and m >= 1. */
+hcu_status hcu_cheb_filter(hcu_ctx* ctx, int spin, int ik, const void* X, void* Y,
+                           int ncol, int64_t ld, int m, double a, double b, double aL);
+
+/* One filter + Rayleigh-Ritz pass on the context's orbitals of (spin, ik)
+ * with the context's current bounds (set by hcu_lanczos_bounds or a previous
+ * pass): X <- Y C with S = Y^H Y dV, Hs = Y^H H Y dV, Hs C = S C diag(lam).
+ * Errors: HCU_NOT_SPD when S is not positive definite. */
+hcu_status hcu_chfsi_pass(hcu_ctx* ctx, int spin, int ik);
+
+/* k-step Lanczos on the start vector: sets the bounds of (spin, ik) to
+ * b = theta_max + |beta_k|, aL = theta_min, a = aL + (b - aL)/10. */
+hcu_status hcu_lanczos_bounds(hcu_ctx* ctx, int spin, int ik, int steps,
+                              double* theta_min, double* upper);
+
+/* Rayleigh-Ritz contractions alone (the matrices of the projected problem):
+ * S = Y^H Y dV and Hs = Y^H HY dV for ncol <= ns states (device blocks,
+ * leading dimension ld >= nd); results to host, ncol x ncol column-major
+ * doubles (complex: interleaved).  Diagonal tiles are symmetrised. */
+hcu_status hcu_gram(hcu_ctx* ctx, const void* Y, const void* HY, int ncol, int64_t ld, double* S, double* Hs);
+
+/* Subspace rotation X = Y C (device blocks, ld >= nd; C host, ncol x ncol
+ * column-major doubles, complex interleaved at k != 0). */
+hcu_status hcu_rotate(hcu_ctx* ctx, const void* Y, const double* C, void* X, int ncol, int64_t ld);
+
+/* Full SCF loop (Sec. II.B): per iteration, filter + Rayleigh-Ritz for every
+ * (spin, k) (first iteration: first_passes), Fermi level, occupations, D_out,
+ * E_U, free energy, Pulay mixing of D.  Errors: HCU_NOT_CONVERGED when
+ * max_iter is reached without meeting the tolerances (results stay valid),
+ * HCU_NOT_SPD, HCU_NAN. */
+hcu_status hcu_scf(hcu_ctx* ctx, const hcu_scf_opts* opts, hcu_scf_report* rep);
+
+/* Occupations, energies and D_out of the current orbitals (used by hcu_scf;
+ * callable after hcu_chfsi_pass on every (spin, k)). */
+hcu_status hcu_update_occupations(hcu_ctx* ctx);
+
+/* Results (host outputs, caller-owned buffers). */
+hcu_status hcu_get_eigenvalues(const hcu_ctx* ctx, double* eig);    /* [nspin][nk][ns] */
+hcu_status hcu_get_occupations(const hcu_ctx* ctx, double* occ);    /* [nspin][nk][ns] */
+hcu_status hcu_get_hubbard_occupation(const hcu_ctx* ctx, double* D);   /* D_out */
+hcu_status hcu_get_energies(const hcu_ctx* ctx, hcu_energies* e);
+/* Orbitals of (spin, ik) into dst (device if on_device, else host), nd x ns
+ * column-major in the context precision (complex interleaved at k != 0). */
+hcu_status hcu_get_orbitals(hcu_ctx* ctx, int spin, int ik, void* dst, int on_device);
+/* Density rho[sigma][nd] (host, double): total for nspin = 1, spin densities
+ * for nspin = 2; rho = (2/nspin) sum_k w_k sum_j f_j |x_j|^2. */
+hcu_status hcu_get_density(hcu_ctx* ctx, double* rho);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HUBBARD_CHFSI_H */

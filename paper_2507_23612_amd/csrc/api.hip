@@ -1,0 +1,835 @@
+// C ABI of the library: context, workspace, operator, Chebyshev filter,
+// Rayleigh-Ritz pass, Lanczos bound and the SCF loop of real-space DFT+U
+// (arXiv:2507.23612, Sec. II.B: ChFSI ground state, Pulay mixing of the
+// occupation matrices, D updated every SCF iteration).
+#include "common.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+using namespace hcu;
+
+struct hcu_ctx : public Ctx {};
+
+namespace {
+
+struct Bump {
+  char* base;
+  size_t off = 0;
+  template <typename P>
+  void take(P*& ptr, size_t bytes) {
+    off = (off + 255) & ~size_t(255);
+    ptr = base ? reinterpret_cast<P*>(base + off) : nullptr;
+    off += std::max<size_t>(bytes, 1);
+  }
+};
+
+size_t esize(const Ctx& c) { return (c.mixed ? 4 : 8) * (c.any_complex ? 2 : 1); }
+
+size_t layout(Ctx& c, char* base) {
+  Bump b{base};
+  const size_t es = esize(c);
+  const int nsk = c.p.nspin * c.p.nk;
+  const int64_t nnz = c.csr_ptr.empty() ? 0 : c.csr_ptr[c.nd];
+  const int ns = c.p.ns;
+  const int nh = (int)c.hub_atoms.size();
+  const int cp = c.any_complex ? 2 : 1;
+  b.take(c.d_V, sizeof(double) * c.nd);
+  if (c.mixed) b.take(c.d_Vf, sizeof(float) * c.nd);
+  b.take(c.d_supp, sizeof(int) * c.supp.size());
+  b.take(c.d_csr_ptr, sizeof(int) * (c.nd + 1));
+  b.take(c.d_csr_col, sizeof(int) * nnz);
+  b.take(c.d_csr_src, sizeof(int64_t) * nnz);
+  b.take(c.d_blocks, sizeof(BlockDesc) * c.blocks.size());
+  b.take(c.d_nm_lists, sizeof(int) * c.blocks.size());
+  b.take(c.d_hub_blocks, sizeof(int) * nh);
+  c.d_cscv.assign(c.p.nk, nullptr);
+  c.d_csrv.assign(c.p.nk, nullptr);
+  for (int k = 0; k < c.p.nk; ++k) {
+    b.take(c.d_cscv[k], es * c.nval);
+    b.take(c.d_csrv[k], es * nnz);
+  }
+  c.d_coup.assign(c.p.nspin, nullptr);
+  for (int s = 0; s < c.p.nspin; ++s) b.take(c.d_coup[s], sizeof(double) * c.coup_size);
+  c.d_X.assign(nsk, nullptr);
+  c.d_v0.assign(nsk, nullptr);
+  c.d_PX.assign(nsk, nullptr);
+  for (int i = 0; i < nsk; ++i) {
+    b.take(c.d_X[i], es * (size_t)c.nd * ns);
+    b.take(c.d_v0[i], es * (size_t)c.nd);
+    b.take(c.d_PX[i], es * (size_t)ns * c.nproj);
+  }
+  for (int w = 0; w < 3; ++w) b.take(c.d_W[w], es * (size_t)c.nd * ns);
+  b.take(c.d_P, es * (size_t)ns * c.nproj);
+  b.take(c.d_Q, es * (size_t)ns * c.nproj);
+  b.take(c.d_PY, es * (size_t)ns * c.nproj);
+  c.part_elems = c.any_complex ? gram_partial_elems_c(ns, c.nd) : gram_partial_elems(ns, c.nd);
+  b.take(c.d_part, sizeof(double) * c.part_elems);
+  b.take(c.d_tiles, sizeof(int2) * gram_tiles(ns, c.any_complex).size());
+  b.take(c.d_S, sizeof(double) * (size_t)ns * ns * cp);
+  b.take(c.d_Hs, sizeof(double) * (size_t)ns * ns * cp);
+  b.take(c.d_C, sizeof(double) * (size_t)ns * ns * cp);
+  b.take(c.d_Cb, es * (size_t)ns * ns);
+  b.take(c.d_lam, sizeof(double) * (size_t)nsk * ns);
+  b.take(c.d_occ, sizeof(double) * (size_t)nsk * ns);
+  b.take(c.d_E, sizeof(double) * (size_t)ns * 2);
+  b.take(c.d_info, sizeof(int) * 4);
+  b.take(c.d_D, sizeof(double) * (size_t)c.p.nspin * nh * 25);
+  size_t red = std::max<size_t>(16384 * sizeof(double), sizeof(double) * 8 * (size_t)c.p.natom);
+  red = std::max(red, sizeof(int) * c.blocks.size());
+  b.take(c.d_red, red);
+  b.take(c.d_scal, sizeof(double) * (64 + nsk + nh + c.p.nspin + 8));
+  b.take(c.d_rho, sizeof(double) * (size_t)c.p.nspin * c.nd);
+  b.take(c.d_vec, es * (size_t)c.nd * 4);
+  return b.off;
+}
+
+hcu_status check_ctx(const hcu_ctx* ctx) {
+  if (!ctx) return HCU_INVALID_ARG;
+  if (!ctx->bound) { const_cast<hcu_ctx*>(ctx)->err = "context not bound to device memory"; return HCU_NOT_BOUND; }
+  return HCU_OK;
+}
+
+hcu_status fail(Ctx& c, hcu_status s, const std::string& msg) {
+  c.err = msg;
+  return s;
+}
+
+// coupling matrices of every block for one spin: diag(gamma) for KB, U(1/2 - D_in) for Hubbard
+hcu_status upload_coupling(Ctx& c) {
+  const int nh = (int)c.hub_atoms.size();
+  for (int s = 0; s < c.p.nspin; ++s) {
+    std::vector<double> cp(std::max(c.coup_size, 1), 0.0);
+    for (const BlockDesc& b : c.blocks) {
+      double* M = cp.data() + b.coup_off;
+      if (b.type == 0) {
+        int m0 = 0;
+        for (int ch = 0; ch < b.nchan; ++ch) {
+          const int nmc = 2 * b.chan_l[ch] + 1;
+          for (int m = 0; m < nmc; ++m) M[(m0 + m) * b.nm + m0 + m] = b.chan_gamma[ch];
+          m0 += nmc;
+        }
+      } else {
+        const double U = c.hub_U[b.hub];
+        const double* D = c.D_in.data() + ((size_t)s * nh + b.hub) * 25;
+        for (int i = 0; i < b.nm; ++i)
+          for (int j = 0; j < b.nm; ++j) M[i * b.nm + j] = U * ((i == j ? 0.5 : 0.0) - D[i * 5 + j]);
+      }
+    }
+    HCU_HIP(hipMemcpyAsync(c.d_coup[s], cp.data(), sizeof(double) * c.coup_size, hipMemcpyHostToDevice, c.stream));
+    HCU_HIP(hipStreamSynchronize(c.stream));   // cp is released at the end of this iteration
+  }
+  return HCU_OK;
+}
+
+// Symmetric tridiagonal eigenvalues (small, host): cyclic Jacobi on the dense
+// matrix.
+void small_sym_eigvals(std::vector<double> A, int n, std::vector<double>& ev) {
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += A[i * n + j] * A[i * n + j];
+    if (off < 1e-30) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double apq = A[p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        double th = (A[q * n + q] - A[p * n + p]) / (2 * apq);
+        double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1));
+        double cs = 1 / std::sqrt(t * t + 1), sn = t * cs;
+        for (int r = 0; r < n; ++r) {
+          double arp = A[r * n + p], arq = A[r * n + q];
+          A[r * n + p] = cs * arp - sn * arq;
+          A[r * n + q] = sn * arp + cs * arq;
+        }
+        for (int r = 0; r < n; ++r) {
+          double apr = A[p * n + r], aqr = A[q * n + r];
+          A[p * n + r] = cs * apr - sn * aqr;
+          A[q * n + r] = sn * apr + cs * aqr;
+        }
+      }
+  }
+  ev.resize(n);
+  for (int i = 0; i < n; ++i) ev[i] = A[i * n + i];
+  std::sort(ev.begin(), ev.end());
+}
+
+// ------------------------------------------------------------------ typed steps
+template <typename T>
+void apply_h_t(Ctx& c, int spin, int ik, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncol) {
+  const T* Q = nullptr;
+  if (c.nproj > 0) {
+    launch_project<T>(c, X, ncol, ldx, (const T*)c.d_cscv[ik], c.d_coup[spin], (T*)c.d_P, (T*)c.d_Q, c.stream);
+    Q = (const T*)c.d_Q;
+  }
+  launch_stencil<T>(c, ik, X, ldx, nullptr, 0, Y, ldy, ncol, Q, (const T*)c.d_csrv[ik], 1.0, 0.0, 0.0, c.stream);
+}
+
+// returns the index of the work block that holds the filtered block
+template <typename T>
+int filter_t(Ctx& c, int spin, int ik, const T* X, int64_t ldx, int ncol, int m, double a, double b, double aL) {
+  const double e = (b - a) / 2, cc = (b + a) / 2;
+  double sigma = e / (aL - cc);
+  const double tau = 2.0 / sigma;
+  const int64_t nd = c.nd;
+  const T* Q = nullptr;
+  const T* csrv = (const T*)c.d_csrv[ik];
+  auto project = [&](const T* Y, int64_t ld) {
+    if (c.nproj > 0) {
+      launch_project<T>(c, Y, ncol, ld, (const T*)c.d_cscv[ik], c.d_coup[spin], (T*)c.d_P, (T*)c.d_Q, c.stream);
+      Q = (const T*)c.d_Q;
+    }
+  };
+  project(X, ldx);
+  launch_stencil<T>(c, ik, X, ldx, nullptr, 0, (T*)c.d_W[0], nd, ncol, Q, csrv, sigma / e, cc, 0.0, c.stream);
+  const T* prev = X;
+  int64_t ldp = ldx;
+  int cur = 0;
+  for (int i = 2; i <= m; ++i) {
+    const double s2 = 1.0 / (tau - sigma);
+    const int out = (cur + 1) % 3;
+    project((const T*)c.d_W[cur], nd);
+    launch_stencil<T>(c, ik, (const T*)c.d_W[cur], nd, prev, ldp, (T*)c.d_W[out], nd, ncol, Q, csrv,
+                      2.0 * s2 / e, cc, sigma * s2, c.stream);
+    prev = (const T*)c.d_W[cur];
+    ldp = nd;
+    cur = out;
+    sigma = s2;
+  }
+  return cur;
+}
+
+template <typename T>
+hcu_status pass_t(Ctx& c, int spin, int ik, double* filter_ms) {
+  const int sk = sk_index(c, spin, ik);
+  const int ns = c.p.ns;
+  const int64_t nd = c.nd;
+  T* X = (T*)c.d_X[sk];
+  const double a = c.bounds[3 * sk], b = c.bounds[3 * sk + 1], aL = c.bounds[3 * sk + 2];
+  hipEvent_t e0, e1;
+  HCU_HIP(hipEventCreate(&e0));
+  HCU_HIP(hipEventCreate(&e1));
+  HCU_HIP(hipEventRecord(e0, c.stream));
+  const int iy = filter_t<T>(c, spin, ik, X, nd, ns, c.p.degree, a, b, aL);
+  const int ih = (iy + 1) % 3;
+  T* Y = (T*)c.d_W[iy];
+  T* HY = (T*)c.d_W[ih];
+  apply_h_t<T>(c, spin, ik, Y, nd, HY, nd, ns);
+  HCU_HIP(hipEventRecord(e1, c.stream));
+  if (c.nproj > 0)
+    HCU_HIP(hipMemcpyAsync(c.d_PY, c.d_P, esize(c) * (size_t)ns * c.nproj, hipMemcpyDeviceToDevice, c.stream));
+  launch_gram2<T>(c, Y, HY, ns, nd, c.d_S, c.d_Hs, c.stream);
+  HCU_HIP(hipGetLastError());
+  rocblas_status rs;
+  const bool cp = sizeof(T) > sizeof(typename real_of<T>::type);
+  if (cp)
+    rs = rocsolver_zhegvd(c.blas, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, ns,
+                          (rocblas_double_complex*)c.d_Hs, ns, (rocblas_double_complex*)c.d_S, ns,
+                          c.d_lam + (size_t)sk * ns, c.d_E, c.d_info);
+  else
+    rs = rocsolver_dsygvd(c.blas, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, ns, c.d_Hs, ns,
+                          c.d_S, ns, c.d_lam + (size_t)sk * ns, c.d_E, c.d_info);
+  if (rs != rocblas_status_success) return fail(c, HCU_DEVICE, "rocsolver generalized eigensolve failed");
+  launch_convert_c<T>(c.d_Hs, (T*)c.d_Cb, ns, cp ? 1 : 0, c.stream);
+  launch_rotate<T>(c, Y, nd, (const T*)c.d_Cb, X, ns, c.stream);
+  if (c.nproj > 0) launch_rotate_proj<T>(c, (const T*)c.d_PY, (const T*)c.d_Cb, (T*)c.d_PX[sk], ns, c.stream);
+  HCU_HIP(hipGetLastError());
+  int info = 0;
+  HCU_HIP(hipMemcpyAsync(&info, c.d_info, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+  std::vector<double> lam(ns);
+  HCU_HIP(hipMemcpyAsync(lam.data(), c.d_lam + (size_t)sk * ns, sizeof(double) * ns, hipMemcpyDeviceToHost, c.stream));
+  HCU_HIP(hipStreamSynchronize(c.stream));
+  float ms = 0;
+  hipEventElapsedTime(&ms, e0, e1);
+  if (filter_ms) *filter_ms += ms;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (info != 0) {
+    return fail(c, HCU_NOT_SPD, "generalized eigensolve failed (info=" + std::to_string(info) +
+                                    "): Gram matrix not positive definite or no convergence");
+  }
+  for (int i = 0; i < ns; ++i)
+    if (!std::isfinite(lam[i])) return fail(c, HCU_NAN, "non-finite Ritz value");
+  c.bounds[3 * sk] = lam[ns - 1];
+  c.bounds[3 * sk + 2] = lam[0];
+  return HCU_OK;
+}
+
+template <typename T>
+hcu_status lanczos_t(Ctx& c, int spin, int ik, int steps, double* th_min, double* upper) {
+  const int sk = sk_index(c, spin, ik);
+  const int64_t nd = c.nd;
+  T* v = (T*)c.d_vec;
+  T* w = v + nd;
+  T* vp = w + nd;
+  double* dres = c.d_scal + 8;
+  double hres[2];
+  auto dot = [&](const T* x, const T* y) -> double {
+    launch_dot<T>(c, x, y, nd, dres, c.stream);
+    hipMemcpyAsync(hres, dres, 2 * sizeof(double), hipMemcpyDeviceToHost, c.stream);
+    hipStreamSynchronize(c.stream);
+    return hres[0];
+  };
+  HCU_HIP(hipMemcpyAsync(v, c.d_v0[sk], esize(c) * nd, hipMemcpyDeviceToDevice, c.stream));
+  double nrm = std::sqrt(dot(v, v));
+  if (!(nrm > 0)) return fail(c, HCU_INVALID_ARG, "Lanczos start vector is zero");
+  launch_scale_copy<T>(v, v, 1.0 / nrm, nd, c.stream);
+  HCU_HIP(hipMemsetAsync(vp, 0, esize(c) * nd, c.stream));
+  std::vector<double> al, be;
+  double bprev = 0;
+  for (int j = 0; j < steps; ++j) {
+    apply_h_t<T>(c, spin, ik, v, nd, w, nd, 1);
+    const double alpha = dot(v, w);
+    launch_axpby<T>(c, w, v, -alpha, 0.0, 1.0, nd, c.stream);
+    if (j > 0) launch_axpby<T>(c, w, vp, -bprev, 0.0, 1.0, nd, c.stream);
+    const double beta = std::sqrt(dot(w, w));
+    al.push_back(alpha);
+    be.push_back(beta);
+    if (beta == 0.0) break;
+    HCU_HIP(hipMemcpyAsync(vp, v, esize(c) * nd, hipMemcpyDeviceToDevice, c.stream));
+    launch_scale_copy<T>(v, w, 1.0 / beta, nd, c.stream);
+    bprev = beta;
+  }
+  HCU_HIP(hipStreamSynchronize(c.stream));
+  const int n = (int)al.size();
+  std::vector<double> Tm(n * n, 0.0), ev;
+  for (int i = 0; i < n; ++i) {
+    Tm[i * n + i] = al[i];
+    if (i + 1 < n) Tm[i * n + i + 1] = Tm[(i + 1) * n + i] = be[i];
+  }
+  small_sym_eigvals(Tm, n, ev);
+  const double tmin = ev.front(), bnd = ev.back() + std::fabs(be.back());
+  if (!std::isfinite(tmin) || !std::isfinite(bnd)) return fail(c, HCU_NAN, "non-finite Lanczos bound");
+  c.bounds[3 * sk] = tmin + (bnd - tmin) / 10.0;
+  c.bounds[3 * sk + 1] = bnd;
+  c.bounds[3 * sk + 2] = tmin;
+  if (th_min) *th_min = tmin;
+  if (upper) *upper = bnd;
+  return HCU_OK;
+}
+
+template <typename T>
+hcu_status occupations_t(Ctx& c) {
+  const int nsk = c.p.nspin * c.p.nk;
+  const int nh = (int)c.hub_atoms.size();
+  std::vector<double> aux(nsk + nh + c.p.nspin);
+  for (int s = 0; s < c.p.nspin; ++s)
+    for (int k = 0; k < c.p.nk; ++k) aux[s * c.p.nk + k] = c.kw[k];
+  for (int h = 0; h < nh; ++h) aux[nsk + h] = c.hub_U[h];
+  for (int s = 0; s < c.p.nspin; ++s) {
+    double* p = c.d_coup[s];
+    std::memcpy(&aux[nsk + nh + s], &p, sizeof(double*));
+  }
+  HCU_HIP(hipMemcpyAsync(c.d_scal + 64, aux.data(), sizeof(double) * aux.size(), hipMemcpyHostToDevice, c.stream));
+  launch_fermi(c, c.stream);
+  for (int s = 0; s < c.p.nspin; ++s)
+    for (int k = 0; k < c.p.nk; ++k) launch_occupation_matrix<T>(c, s, k, (const T*)c.d_PX[sk_index(c, s, k)], c.stream);
+  launch_energies(c, nullptr, c.stream);
+  HCU_HIP(hipGetLastError());
+  c.lam.resize((size_t)nsk * c.p.ns);
+  c.occ.resize(c.lam.size());
+  c.D_out.assign((size_t)c.p.nspin * nh * 25, 0.0);
+  double sc[8];
+  HCU_HIP(hipMemcpyAsync(c.lam.data(), c.d_lam, sizeof(double) * c.lam.size(), hipMemcpyDeviceToHost, c.stream));
+  HCU_HIP(hipMemcpyAsync(c.occ.data(), c.d_occ, sizeof(double) * c.occ.size(), hipMemcpyDeviceToHost, c.stream));
+  if (nh > 0)
+    HCU_HIP(hipMemcpyAsync(c.D_out.data(), c.d_D, sizeof(double) * c.D_out.size(), hipMemcpyDeviceToHost, c.stream));
+  HCU_HIP(hipMemcpyAsync(sc, c.d_scal, sizeof(sc), hipMemcpyDeviceToHost, c.stream));
+  HCU_HIP(hipStreamSynchronize(c.stream));
+  c.en.mu = sc[0];
+  c.en.e_band = sc[1];
+  c.en.dc = sc[2];
+  c.en.E_U = sc[3];
+  c.en.ts = sc[4];
+  c.en.F = sc[5];
+  c.have_results = true;
+  if (!std::isfinite(c.en.F)) return fail(c, HCU_NAN, "non-finite free energy");
+  return HCU_OK;
+}
+
+template <typename T>
+hcu_status density_t(Ctx& c, double* rho) {
+  HCU_HIP(hipMemsetAsync(c.d_rho, 0, sizeof(double) * c.p.nspin * c.nd, c.stream));
+  const double g = c.p.nspin == 1 ? 2.0 : 1.0;
+  for (int s = 0; s < c.p.nspin; ++s)
+    for (int k = 0; k < c.p.nk; ++k) {
+      const int sk = sk_index(c, s, k);
+      launch_density<T>(c, (const T*)c.d_X[sk], c.nd, c.d_occ + (size_t)sk * c.p.ns, g * c.kw[k],
+                        c.d_rho + (size_t)s * c.nd, c.stream);
+    }
+  HCU_HIP(hipMemcpyAsync(rho, c.d_rho, sizeof(double) * c.p.nspin * c.nd, hipMemcpyDeviceToHost, c.stream));
+  HCU_HIP(hipStreamSynchronize(c.stream));
+  return HCU_OK;
+}
+
+#define DISPATCH(c, FN, ...)                                                          \
+  ((c).any_complex ? ((c).mixed ? FN<cplx<float>>(__VA_ARGS__) : FN<cplx<double>>(__VA_ARGS__)) \
+                   : ((c).mixed ? FN<float>(__VA_ARGS__) : FN<double>(__VA_ARGS__)))
+
+// Pulay (Anderson) mixing on the upper triangles of D (Sec. II.B mixing).
+struct Pulay {
+  int h;
+  double beta;
+  std::vector<std::vector<double>> xs, fs;
+  std::vector<double> step(const std::vector<double>& x, const std::vector<double>& f) {
+    xs.push_back(x);
+    fs.push_back(f);
+    if ((int)xs.size() > h + 1) { xs.erase(xs.begin()); fs.erase(fs.begin()); }
+    const size_t n = x.size();
+    std::vector<double> out(n);
+    if (xs.size() == 1) {
+      for (size_t i = 0; i < n; ++i) out[i] = x[i] + beta * f[i];
+      return out;
+    }
+    const int m = (int)xs.size() - 1;
+    // least squares min |f - dF g| via modified Gram-Schmidt QR of dF (n x m)
+    std::vector<std::vector<double>> dF(m, std::vector<double>(n)), dX(m, std::vector<double>(n));
+    for (int j = 0; j < m; ++j)
+      for (size_t i = 0; i < n; ++i) { dF[j][i] = fs[j + 1][i] - fs[j][i]; dX[j][i] = xs[j + 1][i] - xs[j][i]; }
+    std::vector<std::vector<double>> Qm = dF;
+    std::vector<double> Rm(m * m, 0.0);
+    std::vector<int> keep(m, 1);
+    for (int j = 0; j < m; ++j) {
+      for (int k = 0; k < j; ++k) {
+        if (!keep[k]) continue;
+        double d = 0;
+        for (size_t i = 0; i < n; ++i) d += Qm[k][i] * Qm[j][i];
+        Rm[k * m + j] = d;
+        for (size_t i = 0; i < n; ++i) Qm[j][i] -= d * Qm[k][i];
+      }
+      double nr = 0, n0 = 0;
+      for (size_t i = 0; i < n; ++i) { nr += Qm[j][i] * Qm[j][i]; n0 += dF[j][i] * dF[j][i]; }
+      nr = std::sqrt(nr);
+      if (nr <= 1e-12 * std::sqrt(n0) || nr == 0.0) { keep[j] = 0; continue; }
+      Rm[j * m + j] = nr;
+      for (size_t i = 0; i < n; ++i) Qm[j][i] /= nr;
+    }
+    std::vector<double> g(m, 0.0), rhs(m, 0.0);
+    for (int j = 0; j < m; ++j) {
+      if (!keep[j]) continue;
+      double d = 0;
+      for (size_t i = 0; i < n; ++i) d += Qm[j][i] * f[i];
+      rhs[j] = d;
+    }
+    for (int j = m - 1; j >= 0; --j) {
+      if (!keep[j]) continue;
+      double v = rhs[j];
+      for (int k = j + 1; k < m; ++k) if (keep[k]) v -= Rm[j * m + k] * g[k];
+      g[j] = v / Rm[j * m + j];
+    }
+    for (size_t i = 0; i < n; ++i) {
+      double xb = x[i], fb = f[i];
+      for (int j = 0; j < m; ++j) { xb -= dX[j][i] * g[j]; fb -= dF[j][i] * g[j]; }
+      out[i] = xb + beta * fb;
+    }
+    return out;
+  }
+};
+
+std::vector<double> d_to_vec(const Ctx& c, const std::vector<double>& D) {
+  std::vector<double> v;
+  const int nh = (int)c.hub_atoms.size();
+  for (int s = 0; s < c.p.nspin; ++s)
+    for (int h = 0; h < nh; ++h) {
+      const int nm = 2 * c.hub_l[h] + 1;
+      const double* d = D.data() + ((size_t)s * nh + h) * 25;
+      for (int i = 0; i < nm; ++i)
+        for (int j = i; j < nm; ++j) v.push_back(d[i * 5 + j]);
+    }
+  return v;
+}
+
+void vec_to_d(const Ctx& c, const std::vector<double>& v, std::vector<double>& D) {
+  const int nh = (int)c.hub_atoms.size();
+  size_t pos = 0;
+  for (int s = 0; s < c.p.nspin; ++s)
+    for (int h = 0; h < nh; ++h) {
+      const int nm = 2 * c.hub_l[h] + 1;
+      double* d = D.data() + ((size_t)s * nh + h) * 25;
+      for (int i = 0; i < nm; ++i)
+        for (int j = i; j < nm; ++j) { d[i * 5 + j] = v[pos]; d[j * 5 + i] = v[pos]; ++pos; }
+    }
+}
+
+
+template <typename T>
+hcu_status apply_h_v(Ctx& c, int spin, int ik, const void* X, void* Y, int ncol, int64_t ld) {
+  apply_h_t<T>(c, spin, ik, (const T*)X, ld, (T*)Y, ld, ncol);
+  HCU_HIP(hipGetLastError());
+  return HCU_OK;
+}
+
+template <typename T>
+hcu_status filter_v(Ctx& c, int spin, int ik, const void* X, void* Y, int ncol, int64_t ld, int m, double a,
+                    double b, double aL) {
+  const int w = filter_t<T>(c, spin, ik, (const T*)X, ld, ncol, m, a, b, aL);
+  HCU_HIP(hipMemcpy2DAsync(Y, sizeof(T) * ld, c.d_W[w], sizeof(T) * c.nd, sizeof(T) * c.nd, ncol,
+                           hipMemcpyDeviceToDevice, c.stream));
+  HCU_HIP(hipGetLastError());
+  return HCU_OK;
+}
+
+template <typename T>
+hcu_status gram_v(Ctx& c, const void* Y, const void* HY, int ncol, int64_t ld, double* S, double* Hs) {
+  launch_gram2<T>(c, (const T*)Y, (const T*)HY, ncol, ld, c.d_S, c.d_Hs, c.stream);
+  HCU_HIP(hipGetLastError());
+  const size_t nb = sizeof(double) * (size_t)ncol * ncol * (c.any_complex ? 2 : 1);
+  HCU_HIP(hipMemcpyAsync(S, c.d_S, nb, hipMemcpyDeviceToHost, c.stream));
+  HCU_HIP(hipMemcpyAsync(Hs, c.d_Hs, nb, hipMemcpyDeviceToHost, c.stream));
+  HCU_HIP(hipStreamSynchronize(c.stream));
+  return HCU_OK;
+}
+
+template <typename T>
+hcu_status rotate_v(Ctx& c, const void* Y, const double* C, void* X, int ncol, int64_t ld) {
+  const size_t nb = sizeof(double) * (size_t)ncol * ncol * (c.any_complex ? 2 : 1);
+  HCU_HIP(hipMemcpyAsync(c.d_C, C, nb, hipMemcpyHostToDevice, c.stream));
+  launch_convert_c<T>(c.d_C, (T*)c.d_Cb, ncol, c.any_complex ? 1 : 0, c.stream);
+  launch_rotate<T>(c, (const T*)Y, ld, (const T*)c.d_Cb, (T*)X, ncol, c.stream);
+  HCU_HIP(hipGetLastError());
+  HCU_HIP(hipStreamSynchronize(c.stream));
+  return HCU_OK;
+}
+
+template <typename T>
+hcu_status get_orbitals_v(Ctx& c, int sk, void* dst, int on_device) {
+  HCU_HIP(hipMemcpyAsync(dst, c.d_X[sk], sizeof(T) * (size_t)c.nd * c.p.ns,
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c.stream));
+  HCU_HIP(hipStreamSynchronize(c.stream));
+  return HCU_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+hcu_status hcu_create(const hcu_problem* p, hcu_ctx** out) {
+  if (!p || !out) return HCU_INVALID_ARG;
+  *out = nullptr;
+  hcu_ctx* c = new (std::nothrow) hcu_ctx();
+  if (!c) return HCU_OOM;
+  auto bad = [&](const char* msg) { c->err = msg; *out = c; return HCU_INVALID_ARG; };
+  c->p = *p;
+  if (p->n0 < 1 || p->n0 > kMaxR) return bad("n0 must be in 1..6");
+  for (int a = 0; a < 3; ++a) {
+    if (p->n[a] < 2) return bad("each n_a must be >= 2");
+    if (!(p->L[a] > 0)) return bad("cell lengths must be positive");
+  }
+  if ((int64_t)p->n[0] * p->n[1] * p->n[2] > (int64_t)1 << 30) return bad("grid too large");
+  if (p->nspin != 1 && p->nspin != 2) return bad("nspin must be 1 or 2");
+  if (p->nk < 1 || !p->kpts || !p->kw) return bad("need nk >= 1 k-points and weights");
+  if (p->natom < 0 || (p->natom > 0 && (!p->atom_species || !p->pos))) return bad("bad atom arrays");
+  if (p->nspecies < 0 || (p->nspecies > 0 && !p->species)) return bad("bad species array");
+  if (p->ns < 1) return bad("ns must be >= 1");
+  if (!(p->kT > 0)) return bad("kT must be positive");
+  if (p->degree < 1) return bad("degree must be >= 1");
+  if (p->precision != HCU_FP64 && p->precision != HCU_MIXED) return bad("unknown precision");
+  const double gs = p->nspin == 1 ? 2.0 : 1.0;
+  if (!(p->nelec > 0) || p->nelec >= gs * p->ns * p->nspin) return bad("nelec must be in (0, states available)");
+  c->kpts.assign(p->kpts, p->kpts + 3 * p->nk);
+  c->kw.assign(p->kw, p->kw + p->nk);
+  c->pos.assign(p->pos, p->pos + 3 * p->natom);
+  c->atom_species.assign(p->atom_species, p->atom_species + p->natom);
+  c->species.assign(p->species, p->species + p->nspecies);
+  double wsum = 0;
+  for (double w : c->kw) wsum += w;
+  if (std::fabs(wsum - 1.0) > 1e-12) return bad("k-point weights must sum to 1");
+  for (int a = 0; a < p->natom; ++a)
+    if (c->atom_species[a] < 0 || c->atom_species[a] >= p->nspecies) return bad("atom species index out of range");
+  for (const hcu_species& s : c->species) {
+    if (s.n_kb < 0 || s.n_kb > HCU_MAX_KB) return bad("n_kb out of range");
+    for (int ch = 0; ch < s.n_kb; ++ch)
+      if (s.kb_l[ch] < 0 || s.kb_l[ch] > 1) return bad("KB channels must have l = 0 or 1");
+    if (s.hub_l > 2 || s.hub_l < -1) return bad("hub_l must be -1..2");
+    if (!(s.threshold > 0)) return bad("threshold must be positive");
+    if (s.n_kb > 0 && !(s.kb_width > 0)) return bad("kb_width must be positive");
+    if (s.hub_l >= 0 && !(s.hub_alpha > 0)) return bad("hub_alpha must be positive");
+    if (!(s.vloc_width > 0)) return bad("vloc_width must be positive");
+  }
+  c->nd = p->n[0] * p->n[1] * p->n[2];
+  for (int a = 0; a < 3; ++a) c->h[a] = p->L[a] / p->n[a];
+  c->dv = c->h[0] * c->h[1] * c->h[2];
+  c->mixed = p->precision == HCU_MIXED;
+  c->any_complex = false;
+  for (int k = 0; k < p->nk; ++k)
+    if (k_complex(*c, k)) c->any_complex = true;
+  c->p.kpts = nullptr; c->p.kw = nullptr; c->p.pos = nullptr; c->p.atom_species = nullptr; c->p.species = nullptr;
+  hcu_status s = build_structure(*c);
+  if (s != HCU_OK) { *out = c; return s; }
+  for (int nm = 0; nm <= kMaxNm; ++nm) c->nm_count[nm] = 0;
+  for (const BlockDesc& b : c->blocks) c->nm_count[b.nm]++;
+  int off = 0;
+  for (int nm = 0; nm <= kMaxNm; ++nm) { c->nm_offset[nm] = off; off += c->nm_count[nm]; }
+  c->D_in.assign((size_t)p->nspin * c->hub_atoms.size() * 25, 0.0);
+  c->bounds.assign((size_t)3 * p->nspin * p->nk, 0.0);
+  c->ws_bytes = layout(*c, nullptr);
+  *out = c;
+  return HCU_OK;
+}
+
+void hcu_destroy(hcu_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->blas) rocblas_destroy_handle(ctx->blas);
+  delete ctx;
+}
+
+const char* hcu_last_error(const hcu_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+hcu_status hcu_workspace_size(const hcu_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return HCU_INVALID_ARG;
+  *bytes = ctx->ws_bytes;
+  return HCU_OK;
+}
+
+int hcu_num_hubbard_atoms(const hcu_ctx* ctx) { return ctx ? (int)ctx->hub_atoms.size() : -1; }
+
+hcu_status hcu_bind(hcu_ctx* ctx, void* dev_ptr, size_t bytes, void* stream) {
+  if (!ctx) return HCU_INVALID_ARG;
+  Ctx& c = *ctx;
+  if (!dev_ptr) return fail(c, HCU_INVALID_ARG, "null workspace");
+  if (((uintptr_t)dev_ptr) % 256) return fail(c, HCU_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (bytes < c.ws_bytes) return fail(c, HCU_OOM, "workspace smaller than hcu_workspace_size()");
+  c.ws = (char*)dev_ptr;
+  c.stream = (hipStream_t)stream;
+  layout(c, c.ws);
+  if (!c.blas) {
+    if (rocblas_create_handle(&c.blas) != rocblas_status_success) return fail(c, HCU_DEVICE, "rocblas handle");
+  }
+  rocblas_set_stream(c.blas, c.stream);
+  // per-count block lists and Hubbard block indices
+  std::vector<int> lists, hb;
+  for (int nm = 0; nm <= kMaxNm; ++nm)
+    for (int i = 0; i < (int)c.blocks.size(); ++i)
+      if (c.blocks[i].nm == nm) lists.push_back(i);
+  for (int i = 0; i < (int)c.blocks.size(); ++i)
+    if (c.blocks[i].type == 1) hb.push_back(i);
+  if (!lists.empty())
+    HCU_HIP(hipMemcpyAsync(c.d_nm_lists, lists.data(), sizeof(int) * lists.size(), hipMemcpyHostToDevice, c.stream));
+  if (!hb.empty())
+    HCU_HIP(hipMemcpyAsync(c.d_hub_blocks, hb.data(), sizeof(int) * hb.size(), hipMemcpyHostToDevice, c.stream));
+  const std::vector<int2> tiles = gram_tiles(c.p.ns, c.any_complex);
+  HCU_HIP(hipMemcpyAsync(c.d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice, c.stream));
+  hcu_status s = device_tables(c);
+  if (s != HCU_OK) return s;
+  c.bound = true;
+  s = upload_coupling(c);
+  if (s != HCU_OK) return s;
+  HCU_HIP(hipStreamSynchronize(c.stream));
+  return HCU_OK;
+}
+
+hcu_status hcu_set_hubbard_occupation(hcu_ctx* ctx, const double* D) {
+  hcu_status s = check_ctx(ctx);
+  if (s != HCU_OK) return s;
+  Ctx& c = *ctx;
+  if (!D && !c.hub_atoms.empty()) return fail(c, HCU_INVALID_ARG, "null D");
+  for (size_t i = 0; i < c.D_in.size(); ++i) {
+    if (!std::isfinite(D[i])) return fail(c, HCU_NAN, "non-finite D");
+    c.D_in[i] = D[i];
+  }
+  s = upload_coupling(c);
+  if (s != HCU_OK) return s;
+  HCU_HIP(hipStreamSynchronize(c.stream));
+  return HCU_OK;
+}
+
+hcu_status hcu_set_start(hcu_ctx* ctx, int spin, int ik, const void* X0, const void* v0) {
+  hcu_status s = check_ctx(ctx);
+  if (s != HCU_OK) return s;
+  Ctx& c = *ctx;
+  if (spin < 0 || spin >= c.p.nspin || ik < 0 || ik >= c.p.nk) return fail(c, HCU_INVALID_ARG, "spin/k out of range");
+  if (!X0 || !v0) return fail(c, HCU_INVALID_ARG, "null start block");
+  const int sk = sk_index(c, spin, ik);
+  HCU_HIP(hipMemcpyAsync(c.d_X[sk], X0, esize(c) * (size_t)c.nd * c.p.ns, hipMemcpyDeviceToDevice, c.stream));
+  HCU_HIP(hipMemcpyAsync(c.d_v0[sk], v0, esize(c) * (size_t)c.nd, hipMemcpyDeviceToDevice, c.stream));
+  HCU_HIP(hipStreamSynchronize(c.stream));
+  return HCU_OK;
+}
+
+hcu_status hcu_apply_h(hcu_ctx* ctx, int spin, int ik, const void* X, void* Y, int ncol, int64_t ld) {
+  hcu_status s = check_ctx(ctx);
+  if (s != HCU_OK) return s;
+  Ctx& c = *ctx;
+  if (spin < 0 || spin >= c.p.nspin || ik < 0 || ik >= c.p.nk) return fail(c, HCU_INVALID_ARG, "spin/k out of range");
+  if (ncol < 1 || ncol > c.p.ns) return fail(c, HCU_INVALID_ARG, "ncol must be in 1..ns");
+  if (ld < c.nd) return fail(c, HCU_INVALID_ARG, "ld < nd");
+  if (!X || !Y || X == Y) return fail(c, HCU_INVALID_ARG, "bad X/Y pointers");
+  return DISPATCH(c, apply_h_v, c, spin, ik, X, Y, ncol, ld);
+}
+
+hcu_status hcu_cheb_filter(hcu_ctx* ctx, int spin, int ik, const void* X, void* Y, int ncol, int64_t ld, int m,
+                           double a, double b, double aL) {
+  hcu_status s = check_ctx(ctx);
+  if (s != HCU_OK) return s;
+  Ctx& c = *ctx;
+  if (spin < 0 || spin >= c.p.nspin || ik < 0 || ik >= c.p.nk) return fail(c, HCU_INVALID_ARG, "spin/k out of range");
+  if (ncol < 1 || ncol > c.p.ns) return fail(c, HCU_INVALID_ARG, "ncol must be in 1..ns");
+  if (ld < c.nd) return fail(c, HCU_INVALID_ARG, "ld < nd");
+  if (!X || !Y || X == Y) return fail(c, HCU_INVALID_ARG, "bad X/Y pointers");
+  if (m < 1 || !(aL < a) || !(a < b)) return fail(c, HCU_INVALID_ARG, "need m >= 1 and aL < a < b");
+  return DISPATCH(c, filter_v, c, spin, ik, X, Y, ncol, ld, m, a, b, aL);
+}
+
+hcu_status hcu_gram(hcu_ctx* ctx, const void* Y, const void* HY, int ncol, int64_t ld, double* S, double* Hs) {
+  hcu_status s = check_ctx(ctx);
+  if (s != HCU_OK) return s;
+  Ctx& c = *ctx;
+  if (ncol < 1 || ncol > c.p.ns) return fail(c, HCU_INVALID_ARG, "ncol must be in 1..ns");
+  if (ld < c.nd) return fail(c, HCU_INVALID_ARG, "ld < nd");
+  if (!Y || !HY || !S || !Hs) return fail(c, HCU_INVALID_ARG, "null pointer");
+  return DISPATCH(c, gram_v, c, Y, HY, ncol, ld, S, Hs);
+}
+
+hcu_status hcu_rotate(hcu_ctx* ctx, const void* Y, const double* C, void* X, int ncol, int64_t ld) {
+  hcu_status s = check_ctx(ctx);
+  if (s != HCU_OK) return s;
+  Ctx& c = *ctx;
+  if (ncol < 1 || ncol > c.p.ns) return fail(c, HCU_INVALID_ARG, "ncol must be in 1..ns");
+  if (ld < c.nd) return fail(c, HCU_INVALID_ARG, "ld < nd");
+  if (!Y || !C || !X || X == Y) return fail(c, HCU_INVALID_ARG, "bad pointers");
+  return DISPATCH(c, rotate_v, c, Y, C, X, ncol, ld);
+}
+
+hcu_status hcu_lanczos_bounds(hcu_ctx* ctx, int spin, int ik, int steps, double* theta_min, double* upper) {
+  hcu_status s = check_ctx(ctx);
+  if (s != HCU_OK) return s;
+  Ctx& c = *ctx;
+  if (spin < 0 || spin >= c.p.nspin || ik < 0 || ik >= c.p.nk) return fail(c, HCU_INVALID_ARG, "spin/k out of range");
+  if (steps < 1 || steps > 200) return fail(c, HCU_INVALID_ARG, "steps must be in 1..200");
+  return DISPATCH(c, lanczos_t, c, spin, ik, steps, theta_min, upper);
+}
+
+hcu_status hcu_chfsi_pass(hcu_ctx* ctx, int spin, int ik) {
+  hcu_status s = check_ctx(ctx);
+  if (s != HCU_OK) return s;
+  Ctx& c = *ctx;
+  if (spin < 0 || spin >= c.p.nspin || ik < 0 || ik >= c.p.nk) return fail(c, HCU_INVALID_ARG, "spin/k out of range");
+  const int sk = sk_index(c, spin, ik);
+  if (!(c.bounds[3 * sk + 1] > c.bounds[3 * sk])) return fail(c, HCU_INVALID_ARG, "bounds not set (run hcu_lanczos_bounds)");
+  return DISPATCH(c, pass_t, c, spin, ik, (double*)nullptr);
+}
+
+hcu_status hcu_update_occupations(hcu_ctx* ctx) {
+  hcu_status s = check_ctx(ctx);
+  if (s != HCU_OK) return s;
+  Ctx& c = *ctx;
+  return DISPATCH(c, occupations_t, c);
+}
+
+hcu_status hcu_scf(hcu_ctx* ctx, const hcu_scf_opts* o, hcu_scf_report* rep) {
+  hcu_status s = check_ctx(ctx);
+  if (s != HCU_OK) return s;
+  Ctx& c = *ctx;
+  if (!o || !rep) return fail(c, HCU_INVALID_ARG, "null options/report");
+  if (o->max_iter < 1 || o->first_passes < 1 || o->lanczos_steps < 1 || o->pulay_history < 1)
+    return fail(c, HCU_INVALID_ARG, "bad SCF options");
+  std::memset(rep, 0, sizeof(*rep));
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int sp = 0; sp < c.p.nspin; ++sp)
+    for (int k = 0; k < c.p.nk; ++k) {
+      s = DISPATCH(c, lanczos_t, c, sp, k, o->lanczos_steps, (double*)nullptr, (double*)nullptr);
+      if (s != HCU_OK) return s;
+    }
+  Pulay mix{o->pulay_history, o->pulay_beta, {}, {}};
+  const int natom = std::max(c.p.natom, 1);
+  double F_old = 0;
+  bool have_old = false;
+  double filt_ms = 0;
+  hcu_status final_status = HCU_NOT_CONVERGED;
+  int it = 0;
+  for (it = 0; it < o->max_iter; ++it) {
+    const int passes = it == 0 ? o->first_passes : 1;
+    for (int sp = 0; sp < c.p.nspin; ++sp)
+      for (int k = 0; k < c.p.nk; ++k)
+        for (int ps = 0; ps < passes; ++ps) {
+          s = DISPATCH(c, pass_t, c, sp, k, &filt_ms);
+          if (s != HCU_OK) return s;
+          rep->hx_columns += (double)c.p.ns * (c.p.degree + 1);
+        }
+    s = DISPATCH(c, occupations_t, c);
+    if (s != HCU_OK) return s;
+    double res = 0;
+    for (size_t i = 0; i < c.D_in.size(); ++i) res += (c.D_out[i] - c.D_in[i]) * (c.D_out[i] - c.D_in[i]);
+    res = std::sqrt(res);
+    const double dF = have_old ? std::fabs(c.en.F - F_old) / natom : INFINITY;
+    if (o->verbose)
+      std::fprintf(stderr, "[hcu scf] it=%d F=%.12f E_U=%.6e res=%.3e dF=%.3e\n", it, c.en.F, c.en.E_U, res, dF);
+    F_old = c.en.F;
+    have_old = true;
+    rep->residual = res;
+    if (o->fixed_iterations > 0) {
+      if (it + 1 >= o->fixed_iterations) { final_status = HCU_OK; ++it; break; }
+    } else if (res < o->tol_d && dF < o->tol_f) {
+      final_status = HCU_OK;
+      rep->converged = 1;
+      ++it;
+      break;
+    }
+    std::vector<double> x = d_to_vec(c, c.D_in), xo = d_to_vec(c, c.D_out), f(x.size());
+    for (size_t i = 0; i < x.size(); ++i) f[i] = xo[i] - x[i];
+    std::vector<double> xn = mix.step(x, f);
+    vec_to_d(c, xn, c.D_in);
+    s = upload_coupling(c);
+    if (s != HCU_OK) return s;
+  }
+  rep->iterations = it;
+  rep->F = c.en.F;
+  rep->E_U = c.en.E_U;
+  rep->e_band = c.en.e_band;
+  rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  rep->filter_seconds = filt_ms * 1e-3;
+  if (final_status != HCU_OK) c.err = "SCF did not converge within max_iter";
+  return final_status;
+}
+
+hcu_status hcu_get_eigenvalues(const hcu_ctx* ctx, double* eig) {
+  if (!ctx || !eig) return HCU_INVALID_ARG;
+  if (!ctx->have_results) return HCU_INVALID_ARG;
+  std::memcpy(eig, ctx->lam.data(), sizeof(double) * ctx->lam.size());
+  return HCU_OK;
+}
+
+hcu_status hcu_get_occupations(const hcu_ctx* ctx, double* occ) {
+  if (!ctx || !occ) return HCU_INVALID_ARG;
+  if (!ctx->have_results) return HCU_INVALID_ARG;
+  std::memcpy(occ, ctx->occ.data(), sizeof(double) * ctx->occ.size());
+  return HCU_OK;
+}
+
+hcu_status hcu_get_hubbard_occupation(const hcu_ctx* ctx, double* D) {
+  if (!ctx || (!D && !ctx->D_out.empty())) return HCU_INVALID_ARG;
+  if (!ctx->have_results) return HCU_INVALID_ARG;
+  std::memcpy(D, ctx->D_out.data(), sizeof(double) * ctx->D_out.size());
+  return HCU_OK;
+}
+
+hcu_status hcu_get_energies(const hcu_ctx* ctx, hcu_energies* e) {
+  if (!ctx || !e) return HCU_INVALID_ARG;
+  if (!ctx->have_results) return HCU_INVALID_ARG;
+  *e = ctx->en;
+  return HCU_OK;
+}
+
+hcu_status hcu_get_orbitals(hcu_ctx* ctx, int spin, int ik, void* dst, int on_device) {
+  hcu_status s = check_ctx(ctx);
+  if (s != HCU_OK) return s;
+  Ctx& c = *ctx;
+  if (spin < 0 || spin >= c.p.nspin || ik < 0 || ik >= c.p.nk || !dst) return fail(c, HCU_INVALID_ARG, "bad arguments");
+  return DISPATCH(c, get_orbitals_v, c, sk_index(c, spin, ik), dst, on_device);
+}
+
+hcu_status hcu_get_density(hcu_ctx* ctx, double* rho) {
+  hcu_status s = check_ctx(ctx);
+  if (s != HCU_OK) return s;
+  Ctx& c = *ctx;
+  if (!rho) return fail(c, HCU_INVALID_ARG, "null rho");
+  if (!c.have_results) return fail(c, HCU_INVALID_ARG, "no occupations yet");
+  return DISPATCH(c, density_t, c, rho);
+}
+
+}  // extern "C"

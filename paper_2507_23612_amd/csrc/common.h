@@ -1,0 +1,221 @@
+// Internal declarations of the hubbard_chfsi library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hubbard_chfsi.h"
+
+namespace hcu {
+
+constexpr int kMaxR = 6;        // largest half stencil order handled (FD order 12)
+constexpr int kMaxNm = 9;       // functions per projector block (l <= 1 KB: 1+3+... ; Hubbard 2l+1 <= 5)
+
+// ---------------------------------------------------------------- complex
+// Interleaved complex with the arithmetic the kernels need.
+template <typename R>
+struct cplx {
+  R re, im;
+  __host__ __device__ cplx() : re(0), im(0) {}
+  __host__ __device__ cplx(R r) : re(r), im(0) {}
+  __host__ __device__ cplx(R r, R i) : re(r), im(i) {}
+};
+template <typename R> __host__ __device__ inline cplx<R> operator+(cplx<R> a, cplx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R> __host__ __device__ inline cplx<R> operator-(cplx<R> a, cplx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R> __host__ __device__ inline cplx<R> operator*(cplx<R> a, cplx<R> b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+template <typename R> __host__ __device__ inline cplx<R> operator*(R s, cplx<R> a) { return {s * a.re, s * a.im}; }
+template <typename R> __host__ __device__ inline cplx<R>& operator+=(cplx<R>& a, cplx<R> b) { a.re += b.re; a.im += b.im; return a; }
+
+template <typename T> struct real_of { using type = T; };
+template <typename R> struct real_of<cplx<R>> { using type = R; };
+
+template <typename T> __host__ __device__ inline T conj_(T a) { return a; }
+template <typename R> __host__ __device__ inline cplx<R> conj_(cplx<R> a) { return {a.re, -a.im}; }
+template <typename T> __host__ __device__ inline typename real_of<T>::type abs2_(T a) { return a * a; }
+template <typename R> __host__ __device__ inline R abs2_(cplx<R> a) { return a.re * a.re + a.im * a.im; }
+// a * conj(b) accumulate helpers
+template <typename T> __host__ __device__ inline T mul_conj(T a, T b) { return a * b; }
+template <typename R> __host__ __device__ inline cplx<R> mul_conj(cplx<R> a, cplx<R> b) { return a * conj_(b); }
+template <typename T> __host__ __device__ inline T make_scalar(double re, double im) { (void)im; return T(re); }
+template <> __host__ __device__ inline cplx<double> make_scalar<cplx<double>>(double re, double im) { return {re, im}; }
+template <> __host__ __device__ inline cplx<float> make_scalar<cplx<float>>(double re, double im) { return {float(re), float(im)}; }
+
+// ---------------------------------------------------------------- context
+struct BlockDesc {            // one projector block: the KB channels or the Hubbard manifold of one atom
+  int atom;
+  int type;                   // 0 = KB, 1 = Hubbard
+  int nm;                     // number of functions
+  int nsupp;                  // support size
+  int64_t supp_off;           // into supp[]
+  int64_t val_off;            // into csc values: val[val_off + m*nsupp + q]
+  int j0;                     // first global projector index
+  int hub;                    // index among Hubbard atoms (type 1), else -1
+  int coup_off;               // into coupling matrices (nm*nm doubles)
+  // evaluation data
+  double center[3];
+  int nchan;
+  int chan_l[HCU_MAX_KB];
+  double chan_rc[HCU_MAX_KB];
+  double chan_norm[HCU_MAX_KB];
+  double chan_gamma[HCU_MAX_KB];
+  double width;               // KB Gaussian width
+  int power;                  // Hubbard radial power
+  double alpha;               // Hubbard exponent
+};
+
+struct StencilCoef {
+  int n[3];
+  int R;
+  double kin[3][kMaxR + 1];   // -1/2 * Laplacian weights per axis, [0] = centre
+  double center;              // sum_a kin[a][0]
+  double phase_re[3], phase_im[3];   // Bloch factor e^{i k_a L_a}
+};
+
+struct Ctx {
+  // problem
+  hcu_problem p;
+  std::vector<double> kpts, kw, pos;
+  std::vector<int> atom_species;
+  std::vector<hcu_species> species;
+  int nd = 0;
+  double dv = 0;
+  double h[3];
+  bool mixed = false;
+  bool any_complex = false;
+  std::vector<int> hub_atoms;        // atom index of each Hubbard atom
+  std::vector<int> hub_l;
+  std::vector<double> hub_U;
+  // projector structure (host)
+  std::vector<BlockDesc> blocks;
+  std::vector<int> supp;             // concatenated supports
+  int nproj = 0;
+  int64_t nval = 0;                  // csc values per k
+  std::vector<int> csr_ptr, csr_col;
+  std::vector<int64_t> csr_src;      // csc position of each csr entry
+  int coup_size = 0;
+  int nm_count[kMaxNm + 1] = {0};    // projector blocks per function count
+  int nm_offset[kMaxNm + 1] = {0};   // offset of each count's list in d_nm_lists
+  int* d_nm_lists = nullptr;
+  int* d_hub_blocks = nullptr;       // block index of each Hubbard atom
+  // device layout (byte offsets into the workspace)
+  size_t ws_bytes = 0;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  rocblas_handle blas = nullptr;
+  size_t elem = 8;                   // bytes of one block element (real)
+  // device pointers
+  double* d_V = nullptr;             // V_loc (double)
+  float* d_Vf = nullptr;             // V_loc (float, mixed)
+  int* d_supp = nullptr;
+  int* d_csr_ptr = nullptr;
+  int* d_csr_col = nullptr;
+  int64_t* d_csr_src = nullptr;
+  BlockDesc* d_blocks = nullptr;
+  std::vector<void*> d_cscv;         // per k: csc values (block element type)
+  std::vector<void*> d_csrv;         // per k: csr values
+  std::vector<double*> d_coup;       // per spin: coupling matrices
+  std::vector<void*> d_X;            // per (spin, k): orbitals nd x ns
+  std::vector<void*> d_v0;           // per (spin, k): Lanczos start vector
+  void* d_W[3] = {nullptr, nullptr, nullptr};   // work blocks nd x ns
+  void* d_P = nullptr;               // projections [ns][nproj] (block type)
+  void* d_Q = nullptr;               // coupled projections
+  void* d_PY = nullptr;              // projections of the filtered block (for D)
+  std::vector<void*> d_PX;           // per (spin,k) projections of X [ns][nproj]
+  double* d_part = nullptr;          // split-K partials of the Gram matrices
+  int2* d_tiles = nullptr;           // upper-triangular output tiles of the Gram kernels
+  size_t part_elems = 0;
+  double* d_S = nullptr;             // ns x ns (complex: 2x)
+  double* d_Hs = nullptr;
+  double* d_C = nullptr;             // eigenvectors (ns x ns)
+  void* d_Cb = nullptr;              // C in block precision
+  double* d_lam = nullptr;           // per (spin,k) eigenvalues [nspin*nk*ns]
+  double* d_occ = nullptr;           // per (spin,k) occupations
+  double* d_E = nullptr;             // rocsolver work (ns)
+  int* d_info = nullptr;
+  double* d_D = nullptr;             // D_out [nspin][nhub][25]
+  double* d_red = nullptr;           // scalar reductions scratch
+  double* d_scal = nullptr;          // scalars [0..63]: mu, e_band, dc, E_U, kT S, F, dot results;
+                                     // then kw per (spin,k), U per Hubbard atom, coupling pointers
+  double* d_rho = nullptr;           // density [nspin][nd]
+  void* d_vec = nullptr;             // Lanczos work vectors (4 x nd)
+  // state
+  std::vector<double> D_in;          // [nspin][nhub][25]
+  std::vector<double> bounds;        // per (spin,k): a, b, aL
+  std::vector<double> lam;           // host copy of eigenvalues
+  std::vector<double> occ;
+  std::vector<double> D_out;
+  hcu_energies en{};
+  bool have_results = false;
+  std::string err;
+  // tuning
+  int tile_x = 0, tile_yt = 0, ry = 4, tile_z = 0;
+};
+
+inline int sk_index(const Ctx& c, int spin, int ik) { return spin * c.p.nk + ik; }
+inline bool k_complex(const Ctx& c, int ik) {
+  return c.kpts[3 * ik] != 0.0 || c.kpts[3 * ik + 1] != 0.0 || c.kpts[3 * ik + 2] != 0.0;
+}
+
+// ---------------------------------------------------------------- launchers
+// setup.hip
+hcu_status build_structure(Ctx& c);          // host: supports, blocks, csr
+hcu_status device_tables(Ctx& c);            // device: V_loc, csc/csr values, Loewdin
+void fill_stencil_coef(const Ctx& c, int ik, StencilCoef& sc);
+
+// stencil.hip: out = alpha*(H_loc y + NL - c y) - beta*yprev   (Q holds coupled projections)
+template <typename T>
+void launch_stencil(const Ctx& c, int ik, const T* Yin, int64_t ld, const T* Yprev, int64_t ld_prev, T* Yout,
+                    int64_t ld_out, int ncol, const T* Q, const T* csrv, double alpha, double cshift, double beta,
+                    hipStream_t st);
+
+// proj.hip: P = Phi^H Y dV (per block) and Q = C_b P
+template <typename T>
+void launch_project(const Ctx& c, const T* Y, int ncol, int64_t ld, const T* cscv, const double* coup,
+                    T* P, T* Q, hipStream_t st);
+
+// gemm.hip
+size_t gram_partial_elems(int n, int64_t nd);
+size_t gram_partial_elems_c(int n, int64_t nd);
+std::vector<int2> gram_tiles(int n, bool cplx_);
+template <typename T>
+void launch_gram2(const Ctx& c, const T* Y, const T* HY, int ncol, int64_t ld, double* S, double* Hs,
+                  hipStream_t st);
+template <typename T>
+void launch_rotate(const Ctx& c, const T* Y, int64_t ld, const T* Cb, T* X, int ncol, hipStream_t st);
+template <typename T>
+void launch_rotate_proj(const Ctx& c, const T* PY, const T* Cb, T* PX, int ncol, hipStream_t st);
+
+// scf_kernels.hip
+template <typename T>
+void launch_dot(const Ctx& c, const T* x, const T* y, int64_t n, double* out2, hipStream_t st);
+template <typename T>
+void launch_axpby(const Ctx& c, T* y, const T* x, double a_re, double a_im, double b, int64_t n, hipStream_t st);
+template <typename T>
+void launch_scale_copy(T* dst, const T* src, double s, int64_t n, hipStream_t st);
+template <typename T>
+void launch_convert_c(const double* C, T* Cb, int n, int cplx, hipStream_t st);
+void launch_fermi(const Ctx& c, hipStream_t st);
+template <typename T>
+void launch_occupation_matrix(const Ctx& c, int spin, int ik, const T* PX, hipStream_t st);
+void launch_energies(const Ctx& c, const double* d_coup_all, hipStream_t st);
+template <typename T>
+void launch_density(const Ctx& c, const T* X, int64_t ld, const double* occ, double w, double* rho,
+                    hipStream_t st);
+
+}  // namespace hcu
+
+#define HCU_HIP(call)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess) {                                                  \
+      c.err = std::string("HIP error: ") + hipGetErrorString(e_) + " at " +  \
+              __FILE__ + ":" + std::to_string(__LINE__);                     \
+      return HCU_DEVICE;                                                     \
+    }                                                                        \
+  } while (0)

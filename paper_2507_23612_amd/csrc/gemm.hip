@@ -1,0 +1,401 @@
+// Rayleigh-Ritz contractions on the matrix cores (MFMA):
+//   S = Y^T Y dV and Hs = Y^T (HY) dV in one pass (split over the grid
+//   dimension, deterministic two-stage reduction in FP64), and the subspace
+//   rotation X = Y C.  FP64 blocks use v_mfma_f64_16x16x4, FP32 blocks
+//   v_mfma_f32_16x16x4 with FP32 accumulation.
+//
+// Fragment layout of the 16x16x4 MFMA (one wave): lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; it receives D[i][l % 16] in
+// accumulator element r with i = 4 (l / 16) + r for the FP32 form and
+// i = l / 16 + 4 r for the FP64 form (checked on the device).
+#include "common.h"
+
+#include <algorithm>
+
+namespace hcu {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Acc;
+template <> struct Acc<double> {
+  using V = d4;
+  __device__ static inline V mfma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <> struct Acc<float> {
+  using V = f4;
+  __device__ static inline V mfma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+constexpr int GT = 64;     // output tile (states x states) per workgroup
+constexpr int GK = 32;     // grid points per LDS stage
+constexpr int GP = GK + 1; // padded LDS row
+
+// part layout: [chunk][tile][2][GT][GT] doubles
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram2(const T* __restrict__ Y, const T* __restrict__ HY, int64_t ld,
+                                               int n, int64_t nd, int64_t kchunk, const int2* __restrict__ tiles,
+                                               int ntiles, double* __restrict__ part) {
+  using V = typename Acc<T>::V;
+  __shared__ T sA[GT][GP], sB[GT][GP], sH[GT][GP];
+  const int2 tl = tiles[blockIdx.x];
+  const int i0 = tl.x * GT, j0 = tl.y * GT;
+  const int64_t kb = (int64_t)blockIdx.y * kchunk;
+  const int64_t ke = min(nd, kb + kchunk);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  V accS[2][2], accH[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int r = 0; r < 4; ++r) { accS[a][b][r] = 0; accH[a][b][r] = 0; }
+  for (int64_t k = kb; k < ke; k += GK) {
+    for (int e = threadIdx.x; e < GT * GK; e += 256) {
+      const int col = e / GK, kk = e % GK;
+      const int64_t g = k + kk;
+      const bool okk = g < ke;
+      sA[col][kk] = (okk && i0 + col < n) ? Y[(int64_t)(i0 + col) * ld + g] : T(0);
+      sB[col][kk] = (okk && j0 + col < n) ? Y[(int64_t)(j0 + col) * ld + g] : T(0);
+      sH[col][kk] = (okk && j0 + col < n) ? HY[(int64_t)(j0 + col) * ld + g] : T(0);
+    }
+    __syncthreads();
+    for (int kk = 0; kk < GK; kk += 4) {
+      T af[2], bf[2], hf[2];
+      for (int a = 0; a < 2; ++a) af[a] = sA[32 * wi + 16 * a + (lane & 15)][kk + (lane >> 4)];
+      for (int b = 0; b < 2; ++b) {
+        bf[b] = sB[32 * wj + 16 * b + (lane & 15)][kk + (lane >> 4)];
+        hf[b] = sH[32 * wj + 16 * b + (lane & 15)][kk + (lane >> 4)];
+      }
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+          accS[a][b] = Acc<T>::mfma(af[a], bf[b], accS[a][b]);
+          accH[a][b] = Acc<T>::mfma(af[a], hf[b], accH[a][b]);
+        }
+    }
+    __syncthreads();
+  }
+  double* outS = part + ((int64_t)blockIdx.y * ntiles + blockIdx.x) * 2 * GT * GT;
+  double* outH = outS + GT * GT;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int r = 0; r < 4; ++r) {
+        const int i = 32 * wi + 16 * a + Acc<T>::row(lane, r);
+        const int j = 32 * wj + 16 * b + (lane & 15);
+        outS[i * GT + j] = (double)accS[a][b][r];
+        outH[i * GT + j] = (double)accH[a][b][r];
+      }
+}
+
+// Sum the chunk partials in a fixed order, scale by dV, mirror into full
+// symmetric n x n column-major matrices (diagonal tiles symmetrised).
+__global__ void k_gram_reduce(const double* __restrict__ part, int nchunk, int ntiles,
+                              const int2* __restrict__ tiles, int n, double dv, double* __restrict__ S,
+                              double* __restrict__ Hs) {
+  const int t = blockIdx.x;
+  const int2 tl = tiles[t];
+  const int i0 = tl.x * GT, j0 = tl.y * GT;
+  const bool diag = tl.x == tl.y;
+  for (int e = threadIdx.x; e < GT * GT; e += blockDim.x) {
+    const int i = e / GT, j = e % GT;
+    if (i0 + i >= n || j0 + j >= n) continue;
+    if (diag && j < i) continue;
+    for (int w = 0; w < 2; ++w) {
+      double s1 = 0, s2 = 0;
+      for (int ch = 0; ch < nchunk; ++ch) {
+        const double* base = part + (((int64_t)ch * ntiles + t) * 2 + w) * GT * GT;
+        s1 += base[i * GT + j];
+        if (diag) s2 += base[j * GT + i];
+      }
+      double v = diag ? 0.5 * (s1 + s2) * dv : s1 * dv;
+      double* M = w == 0 ? S : Hs;
+      M[(int64_t)(i0 + i) + (int64_t)(j0 + j) * n] = v;
+      M[(int64_t)(j0 + j) + (int64_t)(i0 + i) * n] = v;
+    }
+  }
+}
+
+static void gram_plan(int n, int64_t nd, int& ntiles_1d, int& ntiles, int64_t& kchunk, int& nchunk) {
+  ntiles_1d = (n + GT - 1) / GT;
+  ntiles = ntiles_1d * (ntiles_1d + 1) / 2;
+  int want = std::max(1, 2048 / ntiles);
+  kchunk = (nd + want - 1) / want;
+  kchunk = ((kchunk + GK - 1) / GK) * GK;
+  if (kchunk < 1024) kchunk = 1024;
+  nchunk = (int)((nd + kchunk - 1) / kchunk);
+}
+
+size_t gram_partial_elems(int n, int64_t nd) {
+  int t1, nt, nc;
+  int64_t kc;
+  gram_plan(n, nd, t1, nt, kc, nc);
+  return (size_t)nc * nt * 2 * GT * GT;
+}
+
+// upper-triangular tile list (i <= j) of an n x n Gram matrix
+std::vector<int2> gram_tiles(int n, bool cplx_) {
+  const int t = cplx_ ? 32 : 64;
+  const int t1 = (n + t - 1) / t;
+  std::vector<int2> tl;
+  for (int i = 0; i < t1; ++i)
+    for (int j = i; j < t1; ++j) tl.push_back(make_int2(i, j));
+  return tl;
+}
+
+template <typename T>
+void launch_gram2(const Ctx& c, const T* Y, const T* HY, int ncol, int64_t ld, double* S, double* Hs,
+                  hipStream_t st) {
+  int t1, nt, nc;
+  int64_t kc;
+  gram_plan(ncol, c.nd, t1, nt, kc, nc);
+  const int2* d_tiles = c.d_tiles;
+  k_gram2<T><<<dim3(nt, nc), 256, 0, st>>>(Y, HY, ld, ncol, c.nd, kc, d_tiles, nt, c.d_part);
+  k_gram_reduce<<<nt, 256, 0, st>>>(c.d_part, nc, nt, d_tiles, ncol, c.dv, S, Hs);
+}
+
+// X = Y C, computed as X^T = C^T Y^T so that each lane's outputs run along the
+// grid (contiguous in X).  Workgroup tile: 64 grid points x 64 states.
+constexpr int RK = 32;
+template <typename T>
+__global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ Y, int64_t ld, const T* __restrict__ C,
+                                                T* __restrict__ X, int n, int64_t nd) {
+  using V = typename Acc<T>::V;
+  __shared__ T sY[RK][GT + 1], sC[RK][GT + 1];
+  const int j0 = blockIdx.x * GT;
+  const int64_t p0 = (int64_t)blockIdx.y * GT;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wp = wave >> 1, wj = wave & 1;
+  V acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int r = 0; r < 4; ++r) acc[a][b][r] = 0;
+  for (int i0 = 0; i0 < n; i0 += RK) {
+    for (int e = threadIdx.x; e < RK * GT; e += 256) {
+      const int ii = e / GT, pp = e % GT;
+      const int64_t g = p0 + pp;
+      sY[ii][pp] = (i0 + ii < n && g < nd) ? Y[(int64_t)(i0 + ii) * ld + g] : T(0);
+      const int jj = e / RK, i2 = e % RK;
+      sC[i2][jj] = (i0 + i2 < n && j0 + jj < n) ? C[(int64_t)(j0 + jj) * n + i0 + i2] : T(0);
+    }
+    __syncthreads();
+    for (int kk = 0; kk < RK; kk += 4) {
+      T af[2], bf[2];
+      for (int a = 0; a < 2; ++a) af[a] = sC[kk + (lane >> 4)][32 * wj + 16 * a + (lane & 15)];
+      for (int b = 0; b < 2; ++b) bf[b] = sY[kk + (lane >> 4)][32 * wp + 16 * b + (lane & 15)];
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = Acc<T>::mfma(af[a], bf[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int r = 0; r < 4; ++r) {
+        const int j = j0 + 32 * wj + 16 * a + Acc<T>::row(lane, r);
+        const int64_t p = p0 + 32 * wp + 16 * b + (lane & 15);
+        if (j < n && p < nd) X[(int64_t)j * ld + p] = acc[a][b][r];
+      }
+}
+
+template <typename T>
+void launch_rotate(const Ctx& c, const T* Y, int64_t ld, const T* Cb, T* X, int ncol, hipStream_t st) {
+  dim3 grid((ncol + GT - 1) / GT, (unsigned)((c.nd + GT - 1) / GT));
+  k_rotate<T><<<grid, 256, 0, st>>>(Y, ld, Cb, X, ncol, c.nd);
+}
+
+// PX[s][j] = sum_i C[i][s] PY[i][j]  (projections follow the rotation)
+template <typename T>
+__global__ void k_rotate_proj(const T* __restrict__ PY, const T* __restrict__ C, T* __restrict__ PX, int n,
+                              int nproj) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (j >= nproj) return;
+  T acc = T(0);
+  for (int i = 0; i < n; ++i) acc += C[(int64_t)s * n + i] * PY[(int64_t)i * nproj + j];
+  PX[(int64_t)s * nproj + j] = acc;
+}
+
+template <typename T>
+void launch_rotate_proj(const Ctx& c, const T* PY, const T* Cb, T* PX, int ncol, hipStream_t st) {
+  if (c.nproj == 0) return;
+  dim3 grid((c.nproj + 127) / 128, ncol);
+  k_rotate_proj<T><<<grid, 128, 0, st>>>(PY, Cb, PX, ncol, c.nproj);
+}
+
+template void launch_gram2<double>(const Ctx&, const double*, const double*, int, int64_t, double*, double*, hipStream_t);
+template void launch_gram2<float>(const Ctx&, const float*, const float*, int, int64_t, double*, double*, hipStream_t);
+template void launch_rotate<double>(const Ctx&, const double*, int64_t, const double*, double*, int, hipStream_t);
+template void launch_rotate<float>(const Ctx&, const float*, int64_t, const float*, float*, int, hipStream_t);
+template void launch_rotate_proj<double>(const Ctx&, const double*, const double*, double*, int, hipStream_t);
+template void launch_rotate_proj<float>(const Ctx&, const float*, const float*, float*, int, hipStream_t);
+
+// ---------------------------------------------------------------- complex blocks
+// Complex (Bloch) blocks use VALU tiles: S = Y^H Y dV, Hs = Y^H HY dV
+// (Hermitian), X = Y C.  Partials hold interleaved complex doubles.
+constexpr int CT = 32;     // output tile
+constexpr int CK = 32;     // grid points per stage
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram2_c(const T* __restrict__ Y, const T* __restrict__ HY, int64_t ld,
+                                                 int n, int64_t nd, int64_t kchunk, const int2* __restrict__ tiles,
+                                                 int ntiles, double* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) unsigned char raw[3 * CT * (CK + 1) * sizeof(T)];
+  T(*sA)[CK + 1] = reinterpret_cast<T(*)[CK + 1]>(raw);
+  T(*sB)[CK + 1] = sA + CT;
+  T(*sH)[CK + 1] = sB + CT;
+  const int2 tl = tiles[blockIdx.x];
+  const int i0 = tl.x * CT, j0 = tl.y * CT;
+  const int64_t kb = (int64_t)blockIdx.y * kchunk;
+  const int64_t ke = min(nd, kb + kchunk);
+  const int ti = threadIdx.x / 8, tj = (threadIdx.x % 8) * 4;
+  T aS[4], aH[4];
+  for (int q = 0; q < 4; ++q) { aS[q] = T(0); aH[q] = T(0); }
+  for (int64_t k = kb; k < ke; k += CK) {
+    for (int e = threadIdx.x; e < CT * CK; e += 256) {
+      const int col = e / CK, kk = e % CK;
+      const int64_t g = k + kk;
+      const bool okk = g < ke;
+      sA[col][kk] = (okk && i0 + col < n) ? Y[(int64_t)(i0 + col) * ld + g] : T(0);
+      sB[col][kk] = (okk && j0 + col < n) ? Y[(int64_t)(j0 + col) * ld + g] : T(0);
+      sH[col][kk] = (okk && j0 + col < n) ? HY[(int64_t)(j0 + col) * ld + g] : T(0);
+    }
+    __syncthreads();
+    for (int kk = 0; kk < CK; ++kk) {
+      const T a = conj_(sA[ti][kk]);
+      for (int q = 0; q < 4; ++q) {
+        aS[q] += a * sB[tj + q][kk];
+        aH[q] += a * sH[tj + q][kk];
+      }
+    }
+    __syncthreads();
+  }
+  double* outS = part + ((int64_t)blockIdx.y * ntiles + blockIdx.x) * 2 * CT * CT * 2;
+  double* outH = outS + CT * CT * 2;
+  for (int q = 0; q < 4; ++q) {
+    const int e = ti * CT + tj + q;
+    outS[2 * e] = (double)aS[q].re; outS[2 * e + 1] = (double)aS[q].im;
+    outH[2 * e] = (double)aH[q].re; outH[2 * e + 1] = (double)aH[q].im;
+  }
+}
+
+__global__ void k_gram_reduce_c(const double* __restrict__ part, int nchunk, int ntiles,
+                                const int2* __restrict__ tiles, int n, double dv, double* __restrict__ S,
+                                double* __restrict__ Hs) {
+  const int t = blockIdx.x;
+  const int2 tl = tiles[t];
+  const int i0 = tl.x * CT, j0 = tl.y * CT;
+  const bool diag = tl.x == tl.y;
+  for (int e = threadIdx.x; e < CT * CT; e += blockDim.x) {
+    const int i = e / CT, j = e % CT;
+    if (i0 + i >= n || j0 + j >= n) continue;
+    if (diag && j < i) continue;
+    for (int w = 0; w < 2; ++w) {
+      double r1 = 0, m1 = 0, r2 = 0, m2 = 0;
+      for (int ch = 0; ch < nchunk; ++ch) {
+        const double* base = part + (((int64_t)ch * ntiles + t) * 2 + w) * CT * CT * 2;
+        r1 += base[2 * (i * CT + j)];
+        m1 += base[2 * (i * CT + j) + 1];
+        if (diag) { r2 += base[2 * (j * CT + i)]; m2 += base[2 * (j * CT + i) + 1]; }
+      }
+      double re = diag ? 0.5 * (r1 + r2) : r1, im = diag ? 0.5 * (m1 - m2) : m1;
+      re *= dv; im *= dv;
+      double* M = w == 0 ? S : Hs;
+      const int64_t a = (int64_t)(i0 + i) + (int64_t)(j0 + j) * n, b = (int64_t)(j0 + j) + (int64_t)(i0 + i) * n;
+      M[2 * a] = re; M[2 * a + 1] = im;
+      M[2 * b] = re; M[2 * b + 1] = -im;
+    }
+  }
+}
+
+static void gram_plan_c(int n, int64_t nd, int& t1, int& nt, int64_t& kchunk, int& nchunk) {
+  t1 = (n + CT - 1) / CT;
+  nt = t1 * (t1 + 1) / 2;
+  int want = std::max(1, 2048 / nt);
+  kchunk = (nd + want - 1) / want;
+  kchunk = ((kchunk + CK - 1) / CK) * CK;
+  if (kchunk < 1024) kchunk = 1024;
+  nchunk = (int)((nd + kchunk - 1) / kchunk);
+}
+
+size_t gram_partial_elems_c(int n, int64_t nd) {
+  int t1, nt, nc;
+  int64_t kc;
+  gram_plan_c(n, nd, t1, nt, kc, nc);
+  return (size_t)nc * nt * 2 * CT * CT * 2;
+}
+
+template <typename T>
+void launch_gram2_c(const Ctx& c, const T* Y, const T* HY, int ncol, int64_t ld, double* S, double* Hs,
+                    hipStream_t st) {
+  int t1, nt, nc;
+  int64_t kc;
+  gram_plan_c(ncol, c.nd, t1, nt, kc, nc);
+  const int2* d_tiles = c.d_tiles;
+  k_gram2_c<T><<<dim3(nt, nc), 256, 0, st>>>(Y, HY, ld, ncol, c.nd, kc, d_tiles, nt, c.d_part);
+  k_gram_reduce_c<<<nt, 256, 0, st>>>(c.d_part, nc, nt, d_tiles, ncol, c.dv, S, Hs);
+}
+
+// X = Y C for complex blocks: workgroup = 64 grid points x 32 states.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rotate_c(const T* __restrict__ Y, int64_t ld, const T* __restrict__ C,
+                                                  T* __restrict__ X, int n, int64_t nd) {
+  __shared__ __attribute__((aligned(16))) unsigned char raw[(16 * 64 + 16 * CT) * sizeof(T)];
+  T(*sY)[64] = reinterpret_cast<T(*)[64]>(raw);
+  T(*sC)[CT] = reinterpret_cast<T(*)[CT]>(raw + 16 * 64 * sizeof(T));
+  const int j0 = blockIdx.x * CT;
+  const int64_t p0 = (int64_t)blockIdx.y * 64;
+  const int tp = threadIdx.x % 64, tj = (threadIdx.x / 64) * 8;
+  T acc[8];
+  for (int q = 0; q < 8; ++q) acc[q] = T(0);
+  for (int i0 = 0; i0 < n; i0 += 16) {
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      const int ii = e / 64, pp = e % 64;
+      sY[ii][pp] = (i0 + ii < n && p0 + pp < nd) ? Y[(int64_t)(i0 + ii) * ld + p0 + pp] : T(0);
+    }
+    for (int e = threadIdx.x; e < 16 * CT; e += 256) {
+      const int jj = e / 16, ii = e % 16;
+      sC[ii][jj] = (i0 + ii < n && j0 + jj < n) ? C[(int64_t)(j0 + jj) * n + i0 + ii] : T(0);
+    }
+    __syncthreads();
+    for (int ii = 0; ii < 16; ++ii) {
+      const T y = sY[ii][tp];
+      for (int q = 0; q < 8; ++q) acc[q] += y * sC[ii][tj + q];
+    }
+    __syncthreads();
+  }
+  for (int q = 0; q < 8; ++q) {
+    const int j = j0 + tj + q;
+    if (j < n && p0 + tp < nd) X[(int64_t)j * ld + p0 + tp] = acc[q];
+  }
+}
+
+template <typename T>
+void launch_rotate_c(const Ctx& c, const T* Y, int64_t ld, const T* Cb, T* X, int ncol, hipStream_t st) {
+  dim3 grid((ncol + CT - 1) / CT, (unsigned)((c.nd + 63) / 64));
+  k_rotate_c<T><<<grid, 256, 0, st>>>(Y, ld, Cb, X, ncol, c.nd);
+}
+
+template <>
+void launch_gram2<cplx<double>>(const Ctx& c, const cplx<double>* Y, const cplx<double>* HY, int ncol, int64_t ld,
+                                double* S, double* Hs, hipStream_t st) {
+  launch_gram2_c(c, Y, HY, ncol, ld, S, Hs, st);
+}
+template <>
+void launch_gram2<cplx<float>>(const Ctx& c, const cplx<float>* Y, const cplx<float>* HY, int ncol, int64_t ld,
+                               double* S, double* Hs, hipStream_t st) {
+  launch_gram2_c(c, Y, HY, ncol, ld, S, Hs, st);
+}
+template <>
+void launch_rotate<cplx<double>>(const Ctx& c, const cplx<double>* Y, int64_t ld, const cplx<double>* Cb,
+                                 cplx<double>* X, int ncol, hipStream_t st) {
+  launch_rotate_c(c, Y, ld, Cb, X, ncol, st);
+}
+template <>
+void launch_rotate<cplx<float>>(const Ctx& c, const cplx<float>* Y, int64_t ld, const cplx<float>* Cb,
+                                cplx<float>* X, int ncol, hipStream_t st) {
+  launch_rotate_c(c, Y, ld, Cb, X, ncol, st);
+}
+template void launch_rotate_proj<cplx<double>>(const Ctx&, const cplx<double>*, const cplx<double>*, cplx<double>*,
+                                               int, hipStream_t);
+template void launch_rotate_proj<cplx<float>>(const Ctx&, const cplx<float>*, const cplx<float>*, cplx<float>*, int,
+                                              hipStream_t);
+
+}  // namespace hcu

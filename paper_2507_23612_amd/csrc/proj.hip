@@ -1,0 +1,132 @@
+// Projections of a block of states onto the atom-centred functions, one atom
+// block at a time (Sec. II.B: all integrals of one atom are computed together,
+// atom after atom, as for nonlocal projectors):
+//
+//   P[s][j0+m] = dV * sum_{q in supp} conj(phi_m(x_q)) y_s(x_q)          (trapezoid rule)
+//   Q[s][j0+m] = sum_m' C_b[m][m'] P[s][j0+m']
+//
+// with C_b = diag(gamma) for the KB channels and C_b = U (1/2 - D) for the
+// Hubbard manifold (Eq. DerED).  A workgroup owns one block and S states: it
+// sweeps the block's sorted support (x-runs are contiguous), holds the NM x S
+// partial sums per thread and reduces them across the workgroup once.
+#include "common.h"
+
+#include <algorithm>
+
+namespace hcu {
+
+template <typename T>
+__device__ inline T shfl_xor_t(T v, int m) { return __shfl_xor(v, m, 64); }
+template <typename R>
+__device__ inline cplx<R> shfl_xor_t(cplx<R> v, int m) {
+  return cplx<R>(__shfl_xor(v.re, m, 64), __shfl_xor(v.im, m, 64));
+}
+
+template <typename T, int NM, int S>
+__global__ __launch_bounds__(256) void k_project(const T* __restrict__ Y, int64_t ld, int ncol,
+                                                 const BlockDesc* __restrict__ blocks,
+                                                 const int* __restrict__ blist, const int* __restrict__ supp,
+                                                 const T* __restrict__ cscv, const double* __restrict__ coup,
+                                                 T* __restrict__ P, T* __restrict__ Q, int nproj, double dv) {
+  const BlockDesc& b = blocks[blist[blockIdx.x]];
+  const int s0 = blockIdx.y * S;
+  const int ns_here = min(S, ncol - s0);
+  T acc[NM][S];
+  for (int m = 0; m < NM; ++m)
+    for (int s = 0; s < S; ++s) acc[m][s] = T(0);
+  const int nsupp = b.nsupp;
+  const int* __restrict__ sp = supp + b.supp_off;
+  const T* __restrict__ v = cscv + b.val_off;
+  const T* __restrict__ Ys = Y + (int64_t)s0 * ld;
+  for (int q = threadIdx.x; q < nsupp; q += blockDim.x) {
+    const int idx = sp[q];
+    T phi[NM];
+    for (int m = 0; m < NM; ++m) phi[m] = conj_(v[(int64_t)m * nsupp + q]);
+    if (ns_here == S) {
+      for (int s = 0; s < S; ++s) {
+        const T x = Ys[(int64_t)s * ld + idx];
+        for (int m = 0; m < NM; ++m) acc[m][s] += phi[m] * x;
+      }
+    } else {
+      for (int s = 0; s < S; ++s) {
+        if (s < ns_here) {
+          const T x = Ys[(int64_t)s * ld + idx];
+          for (int m = 0; m < NM; ++m) acc[m][s] += phi[m] * x;
+        }
+      }
+    }
+  }
+  // wave reduction, then across the (up to 4) waves of the workgroup
+  // raw LDS storage (T may have a constructor)
+  __shared__ __attribute__((aligned(16))) unsigned char red_raw[4 * NM * S * sizeof(T)];
+  __shared__ __attribute__((aligned(16))) unsigned char pbuf_raw[NM * S * sizeof(T)];
+  T(*red)[NM * S] = reinterpret_cast<T(*)[NM * S]>(red_raw);
+  T* pbuf = reinterpret_cast<T*>(pbuf_raw);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int m = 0; m < NM; ++m)
+    for (int s = 0; s < S; ++s) {
+      T x = acc[m][s];
+      for (int off = 32; off > 0; off >>= 1) x += shfl_xor_t(x, off);
+      if (lane == 0) red[wave][m * S + s] = x;
+    }
+  __syncthreads();
+  const int nw = (blockDim.x + 63) / 64;
+  for (int t = threadIdx.x; t < NM * S; t += blockDim.x) {
+    T x = red[0][t];
+    for (int w = 1; w < nw; ++w) x += red[w][t];
+    pbuf[t] = (typename real_of<T>::type)dv * x;
+  }
+  __syncthreads();
+  const double* cb = coup + b.coup_off;
+  for (int t = threadIdx.x; t < NM * S; t += blockDim.x) {
+    const int m = t / S, s = t % S;
+    if (s >= ns_here) continue;
+    T qv = T(0);
+    for (int mp = 0; mp < NM; ++mp) qv += (typename real_of<T>::type)cb[m * NM + mp] * pbuf[mp * S + s];
+    P[(int64_t)(s0 + s) * nproj + b.j0 + m] = pbuf[t];
+    Q[(int64_t)(s0 + s) * nproj + b.j0 + m] = qv;
+  }
+}
+
+template <typename T, int NM>
+static void launch_nm(const Ctx& c, const T* Y, int ncol, int64_t ld, const T* cscv, const double* coup, T* P,
+                      T* Q, const int* d_list, int nblk, hipStream_t st) {
+  constexpr int S = (sizeof(T) > 8 || NM > 5) ? 4 : 8;
+  dim3 grid(nblk, (ncol + S - 1) / S);
+  k_project<T, NM, S><<<grid, 256, 0, st>>>(Y, ld, ncol, c.d_blocks, d_list, c.d_supp, cscv, coup, P, Q, c.nproj,
+                                            c.dv);
+}
+
+// Blocks are grouped by their function count; the per-count block lists live
+// in the context (built once at bind time).
+template <typename T>
+void launch_project(const Ctx& c, const T* Y, int ncol, int64_t ld, const T* cscv, const double* coup, T* P,
+                    T* Q, hipStream_t st) {
+  for (int nm = 1; nm <= kMaxNm; ++nm) {
+    const int nblk = c.nm_count[nm];
+    if (nblk == 0) continue;
+    const int* d_list = c.d_nm_lists + c.nm_offset[nm];
+    switch (nm) {
+      case 1: launch_nm<T, 1>(c, Y, ncol, ld, cscv, coup, P, Q, d_list, nblk, st); break;
+      case 2: launch_nm<T, 2>(c, Y, ncol, ld, cscv, coup, P, Q, d_list, nblk, st); break;
+      case 3: launch_nm<T, 3>(c, Y, ncol, ld, cscv, coup, P, Q, d_list, nblk, st); break;
+      case 4: launch_nm<T, 4>(c, Y, ncol, ld, cscv, coup, P, Q, d_list, nblk, st); break;
+      case 5: launch_nm<T, 5>(c, Y, ncol, ld, cscv, coup, P, Q, d_list, nblk, st); break;
+      case 6: launch_nm<T, 6>(c, Y, ncol, ld, cscv, coup, P, Q, d_list, nblk, st); break;
+      case 7: launch_nm<T, 7>(c, Y, ncol, ld, cscv, coup, P, Q, d_list, nblk, st); break;
+      case 8: launch_nm<T, 8>(c, Y, ncol, ld, cscv, coup, P, Q, d_list, nblk, st); break;
+      default: launch_nm<T, 9>(c, Y, ncol, ld, cscv, coup, P, Q, d_list, nblk, st); break;
+    }
+  }
+}
+
+template void launch_project<double>(const Ctx&, const double*, int, int64_t, const double*, const double*,
+                                     double*, double*, hipStream_t);
+template void launch_project<float>(const Ctx&, const float*, int, int64_t, const float*, const double*, float*,
+                                    float*, hipStream_t);
+template void launch_project<cplx<double>>(const Ctx&, const cplx<double>*, int, int64_t, const cplx<double>*,
+                                           const double*, cplx<double>*, cplx<double>*, hipStream_t);
+template void launch_project<cplx<float>>(const Ctx&, const cplx<float>*, int, int64_t, const cplx<float>*,
+                                          const double*, cplx<float>*, cplx<float>*, hipStream_t);
+
+}  // namespace hcu

@@ -1,0 +1,335 @@
+"""Thin ctypes binding of libhcu.so (include/hubbard_chfsi.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  PyTorch supplies the device workspace and the stream.  The binding
+raises if the compiled library is missing - there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libhcu.so")
+
+HCU_OK, HCU_INVALID_ARG, HCU_OOM, HCU_NOT_SPD, HCU_NOT_CONVERGED, HCU_NAN, HCU_DEVICE, HCU_NOT_BOUND = range(8)
+STATUS_NAMES = ["HCU_OK", "HCU_INVALID_ARG", "HCU_OOM", "HCU_NOT_SPD", "HCU_NOT_CONVERGED", "HCU_NAN",
+                "HCU_DEVICE", "HCU_NOT_BOUND"]
+HCU_FP64, HCU_MIXED = 0, 1
+MAX_KB = 4
+
+
+class hcu_species(C.Structure):
+    _fields_ = [("vloc_depth", C.c_double), ("vloc_width", C.c_double), ("n_kb", C.c_int),
+                ("kb_l", C.c_int * MAX_KB), ("kb_gamma", C.c_double * MAX_KB), ("kb_width", C.c_double),
+                ("hub_l", C.c_int), ("hub_U", C.c_double), ("hub_power", C.c_int), ("hub_alpha", C.c_double),
+                ("threshold", C.c_double)]
+
+
+class hcu_problem(C.Structure):
+    _fields_ = [("L", C.c_double * 3), ("n", C.c_int * 3), ("n0", C.c_int), ("nspin", C.c_int), ("nk", C.c_int),
+                ("kpts", C.POINTER(C.c_double)), ("kw", C.POINTER(C.c_double)), ("natom", C.c_int),
+                ("atom_species", C.POINTER(C.c_int)), ("pos", C.POINTER(C.c_double)), ("nspecies", C.c_int),
+                ("species", C.POINTER(hcu_species)), ("ns", C.c_int), ("nelec", C.c_double), ("kT", C.c_double),
+                ("degree", C.c_int), ("precision", C.c_int), ("lowdin", C.c_int)]
+
+
+class hcu_scf_opts(C.Structure):
+    _fields_ = [("max_iter", C.c_int), ("first_passes", C.c_int), ("lanczos_steps", C.c_int),
+                ("pulay_history", C.c_int), ("pulay_beta", C.c_double), ("tol_d", C.c_double),
+                ("tol_f", C.c_double), ("fixed_iterations", C.c_int), ("verbose", C.c_int)]
+
+
+class hcu_scf_report(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("F", C.c_double), ("E_U", C.c_double),
+                ("e_band", C.c_double), ("residual", C.c_double), ("seconds", C.c_double),
+                ("filter_seconds", C.c_double), ("hx_columns", C.c_double)]
+
+
+class hcu_energies(C.Structure):
+    _fields_ = [("F", C.c_double), ("e_band", C.c_double), ("dc", C.c_double), ("E_U", C.c_double),
+                ("ts", C.c_double), ("mu", C.c_double)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libhcu.so (raises FileNotFoundError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} not built: run python -m paper_2507_23612_amd.build")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    sig = {
+        "hcu_create": (C.c_int, [C.POINTER(hcu_problem), C.POINTER(P)]),
+        "hcu_destroy": (None, [P]),
+        "hcu_last_error": (C.c_char_p, [P]),
+        "hcu_workspace_size": (C.c_int, [P, C.POINTER(C.c_size_t)]),
+        "hcu_bind": (C.c_int, [P, P, C.c_size_t, P]),
+        "hcu_set_hubbard_occupation": (C.c_int, [P, C.POINTER(C.c_double)]),
+        "hcu_num_hubbard_atoms": (C.c_int, [P]),
+        "hcu_set_start": (C.c_int, [P, C.c_int, C.c_int, P, P]),
+        "hcu_apply_h": (C.c_int, [P, C.c_int, C.c_int, P, P, C.c_int, C.c_int64]),
+        "hcu_cheb_filter": (C.c_int, [P, C.c_int, C.c_int, P, P, C.c_int, C.c_int64, C.c_int, C.c_double,
+                                      C.c_double, C.c_double]),
+        "hcu_chfsi_pass": (C.c_int, [P, C.c_int, C.c_int]),
+        "hcu_lanczos_bounds": (C.c_int, [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double),
+                                         C.POINTER(C.c_double)]),
+        "hcu_gram": (C.c_int, [P, P, P, C.c_int, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "hcu_rotate": (C.c_int, [P, P, C.POINTER(C.c_double), P, C.c_int, C.c_int64]),
+        "hcu_scf": (C.c_int, [P, C.POINTER(hcu_scf_opts), C.POINTER(hcu_scf_report)]),
+        "hcu_update_occupations": (C.c_int, [P]),
+        "hcu_get_eigenvalues": (C.c_int, [P, C.POINTER(C.c_double)]),
+        "hcu_get_occupations": (C.c_int, [P, C.POINTER(C.c_double)]),
+        "hcu_get_hubbard_occupation": (C.c_int, [P, C.POINTER(C.c_double)]),
+        "hcu_get_energies": (C.c_int, [P, C.POINTER(hcu_energies)]),
+        "hcu_get_orbitals": (C.c_int, [P, C.c_int, C.c_int, P, C.c_int]),
+        "hcu_get_density": (C.c_int, [P, C.POINTER(C.c_double)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class HcuError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else status}: {msg}")
+        self.status = status
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def species_struct(sp):
+    s = hcu_species()
+    s.vloc_depth = sp["vloc_depth"]
+    s.vloc_width = sp["vloc_width"]
+    s.n_kb = len(sp["kb_l"])
+    for i, (l, g) in enumerate(zip(sp["kb_l"], sp["kb_gamma"])):
+        s.kb_l[i] = l
+        s.kb_gamma[i] = g
+    s.kb_width = sp["kb_width"]
+    s.hub_l = sp["hub_l"]
+    s.hub_U = sp["hub_U"]
+    s.hub_power = sp["hub_power"]
+    s.hub_alpha = sp["hub_alpha"]
+    s.threshold = sp["threshold"]
+    return s
+
+
+class Problem:
+    """hcu_problem built from a workload dict (keeps the host arrays alive)."""
+
+    def __init__(self, cfg, precision=None):
+        self.cfg = cfg
+        self.kpts = np.ascontiguousarray(np.asarray(cfg["kpts"], np.float64).reshape(-1, 3))
+        self.kw = np.ascontiguousarray(np.asarray(cfg["kw"], np.float64))
+        self.pos = np.ascontiguousarray(np.asarray(cfg["pos"], np.float64).reshape(-1, 3))
+        self.spec = np.ascontiguousarray(np.asarray(cfg["atom_species"], np.int32))
+        self.species = (hcu_species * len(cfg["species"]))(*[species_struct(s) for s in cfg["species"]])
+        p = hcu_problem()
+        for a in range(3):
+            p.L[a] = float(cfg["L"][a])
+            p.n[a] = int(cfg["n"][a])
+        p.n0 = int(cfg["n0"])
+        p.nspin = int(cfg["nspin"])
+        p.nk = len(self.kw)
+        p.kpts = _dptr(self.kpts)
+        p.kw = _dptr(self.kw)
+        p.natom = len(self.spec)
+        p.atom_species = self.spec.ctypes.data_as(C.POINTER(C.c_int))
+        p.pos = _dptr(self.pos)
+        p.nspecies = len(cfg["species"])
+        p.species = C.cast(self.species, C.POINTER(hcu_species))
+        p.ns = int(cfg["ns"])
+        p.nelec = float(cfg["nelec"])
+        p.kT = float(cfg["kT"])
+        p.degree = int(cfg["degree"])
+        prec = precision or cfg.get("precision", "fp64")
+        p.precision = HCU_MIXED if prec == "mixed" else HCU_FP64
+        p.lowdin = 1 if cfg.get("lowdin", True) else 0
+        self.p = p
+
+
+class HcuContext:
+    """One library context bound to a torch-allocated device workspace."""
+
+    def __init__(self, cfg, precision=None, device="cuda:0"):
+        import torch
+        self.lib = load_library()
+        self.torch = torch
+        self.prob = Problem(cfg, precision)
+        self.cfg = cfg
+        self.h = C.c_void_p()
+        st = self.lib.hcu_create(C.byref(self.prob.p), C.byref(self.h))
+        if st != HCU_OK:
+            msg = self.lib.hcu_last_error(self.h).decode() if self.h else "create failed"
+            self.lib.hcu_destroy(self.h)
+            self.h = None
+            raise HcuError(st, msg)
+        nb = C.c_size_t()
+        self._check(self.lib.hcu_workspace_size(self.h, C.byref(nb)))
+        self.workspace_bytes = nb.value
+        self.device = torch.device(device)
+        self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device)
+        self._check(self.lib.hcu_bind(self.h, C.c_void_p(self.ws_ptr), C.c_size_t(self.workspace_bytes),
+                                      C.c_void_p(self.stream.cuda_stream)))
+        self.nspin = int(cfg["nspin"])
+        self.nk = len(self.prob.kw)
+        self.ns = int(cfg["ns"])
+        self.nd = int(np.prod(cfg["n"]))
+        self.nhub = self.lib.hcu_num_hubbard_atoms(self.h)
+        self.mixed = self.prob.p.precision == HCU_MIXED
+        self.complex = bool(np.any(self.prob.kpts != 0))
+        base_t = torch.float32 if self.mixed else torch.float64
+        self.dtype = {torch.float32: torch.complex64, torch.float64: torch.complex128}[base_t] \
+            if self.complex else base_t
+
+    # -------------------------------------------------------------- helpers
+    def _check(self, st):
+        if st != HCU_OK:
+            raise HcuError(st, self.lib.hcu_last_error(self.h).decode())
+
+    def close(self):
+        if self.h:
+            self.lib.hcu_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- C ABI calls
+    def set_hubbard_occupation(self, D):
+        D = np.ascontiguousarray(np.asarray(D, np.float64).reshape(-1))
+        self._check(self.lib.hcu_set_hubbard_occupation(self.h, _dptr(D)))
+
+    def set_start(self, spin, ik, X0, v0):
+        assert X0.is_cuda and v0.is_cuda and X0.dtype == self.dtype and v0.dtype == self.dtype
+        X0 = X0.contiguous()
+        v0 = v0.contiguous()
+        self._check(self.lib.hcu_set_start(self.h, spin, ik, C.c_void_p(X0.data_ptr()), C.c_void_p(v0.data_ptr())))
+        self.stream.synchronize()
+
+    def apply_h(self, X, Y, ncol=None, ld=None, spin=0, ik=0):
+        """Y = H X; X, Y torch tensors of shape (ncol, ld) (state-major rows)."""
+        ncol = ncol or X.shape[0]
+        ld = ld or X.shape[1]
+        self._check(self.lib.hcu_apply_h(self.h, spin, ik, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),
+                                         ncol, ld))
+
+    def cheb_filter(self, X, Y, m, a, b, aL, ncol=None, ld=None, spin=0, ik=0):
+        ncol = ncol or X.shape[0]
+        ld = ld or X.shape[1]
+        self._check(self.lib.hcu_cheb_filter(self.h, spin, ik, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),
+                                             ncol, ld, m, a, b, aL))
+
+    def gram(self, Y, HY, ncol=None, ld=None):
+        """(S, Hs) = (Y^H Y dV, Y^H HY dV) as numpy arrays."""
+        ncol = ncol or Y.shape[0]
+        ld = ld or Y.shape[1]
+        dt = np.complex128 if self.complex else np.float64
+        S = np.zeros((ncol, ncol), dt)
+        Hs = np.zeros((ncol, ncol), dt)
+        self._check(self.lib.hcu_gram(self.h, C.c_void_p(Y.data_ptr()), C.c_void_p(HY.data_ptr()), ncol, ld,
+                                      S.ctypes.data_as(C.POINTER(C.c_double)),
+                                      Hs.ctypes.data_as(C.POINTER(C.c_double))))
+        # column-major on the device side: transpose
+        return S.T.copy(), Hs.T.copy()
+
+    def rotate(self, Y, Cm, X, ncol=None, ld=None):
+        """X = Y C (C numpy ncol x ncol)."""
+        ncol = ncol or Y.shape[0]
+        ld = ld or Y.shape[1]
+        dt = np.complex128 if self.complex else np.float64
+        Cf = np.asfortranarray(np.asarray(Cm, dt))
+        self._check(self.lib.hcu_rotate(self.h, C.c_void_p(Y.data_ptr()), Cf.ctypes.data_as(C.POINTER(C.c_double)),
+                                        C.c_void_p(X.data_ptr()), ncol, ld))
+
+    def lanczos_bounds(self, spin=0, ik=0, steps=10):
+        tmin, up = C.c_double(), C.c_double()
+        self._check(self.lib.hcu_lanczos_bounds(self.h, spin, ik, steps, C.byref(tmin), C.byref(up)))
+        return tmin.value, up.value
+
+    def chfsi_pass(self, spin=0, ik=0):
+        self._check(self.lib.hcu_chfsi_pass(self.h, spin, ik))
+
+    def update_occupations(self):
+        self._check(self.lib.hcu_update_occupations(self.h))
+
+    def scf(self, max_iter=100, first_passes=4, lanczos_steps=10, pulay_history=7, pulay_beta=0.3, tol_d=1e-7,
+            tol_f=1e-7, fixed_iterations=0, verbose=False, raise_on_nonconv=True):
+        o = hcu_scf_opts(max_iter, first_passes, lanczos_steps, pulay_history, pulay_beta, tol_d, tol_f,
+                         fixed_iterations, 1 if verbose else 0)
+        r = hcu_scf_report()
+        st = self.lib.hcu_scf(self.h, C.byref(o), C.byref(r))
+        if st != HCU_OK and not (st == HCU_NOT_CONVERGED and not raise_on_nonconv):
+            self._check(st)
+        return {k: getattr(r, k) for k, _ in hcu_scf_report._fields_}
+
+    def get_eigenvalues(self):
+        out = np.zeros((self.nspin, self.nk, self.ns))
+        self._check(self.lib.hcu_get_eigenvalues(self.h, _dptr(out)))
+        return out
+
+    def get_occupations(self):
+        out = np.zeros((self.nspin, self.nk, self.ns))
+        self._check(self.lib.hcu_get_occupations(self.h, _dptr(out)))
+        return out
+
+    def get_hubbard_occupation(self):
+        out = np.zeros((self.nspin, max(self.nhub, 0), 5, 5))
+        self._check(self.lib.hcu_get_hubbard_occupation(self.h, _dptr(out)))
+        return out
+
+    def get_energies(self):
+        e = hcu_energies()
+        self._check(self.lib.hcu_get_energies(self.h, C.byref(e)))
+        return {k: getattr(e, k) for k, _ in hcu_energies._fields_}
+
+    def get_orbitals(self, spin=0, ik=0):
+        X = self.torch.empty((self.ns, self.nd), dtype=self.dtype, device=self.device)
+        self._check(self.lib.hcu_get_orbitals(self.h, spin, ik, C.c_void_p(X.data_ptr()), 1))
+        return X
+
+    def get_density(self):
+        out = np.zeros((self.nspin, self.nd))
+        self._check(self.lib.hcu_get_density(self.h, _dptr(out)))
+        return out
+
+
+def start_inputs(ctx, cfg, spin=0, ik=0):
+    """Seeded start block and Lanczos vector of (spin, ik) as device tensors
+    in the context precision."""
+    import torch
+    import workloads
+    cplx = ctx.complex
+    X0 = workloads.random_block(ctx.nd, ctx.ns, workloads.start_seed(cfg, spin, ik), cplx)
+    v0 = workloads.random_vector(ctx.nd, workloads.lanczos_seed(cfg, spin, ik), cplx)
+    X0 = torch.from_numpy(X0).to(ctx.device).to(ctx.dtype)
+    v0 = torch.from_numpy(v0).to(ctx.device).to(ctx.dtype)
+    return X0, v0
+
+
+def initial_occupation(ctx, cfg):
+    """Diagonal initial D (isolated-atom average occupation), [nspin][nhub][5][5]."""
+    import workloads
+    D = np.zeros((ctx.nspin, ctx.nhub, 5, 5))
+    for s in range(ctx.nspin):
+        for h, g in enumerate(workloads.initial_occupation_diag(cfg, s)):
+            D[s, h] = g * np.eye(5)
+    return D

@@ -1,0 +1,63 @@
+"""The C-ABI library loads and exports every symbol the public header
+declares (no device call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hubbard_chfsi.h")
+LIB = os.path.join(ROOT, "paper_2507_23612_amd", "lib", "libhcu.so")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hcu_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_entry_points():
+    names = declared_symbols()
+    for must in ("hcu_create", "hcu_bind", "hcu_apply_h", "hcu_cheb_filter", "hcu_chfsi_pass", "hcu_scf"):
+        assert must in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_symbols() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_create_validates_on_host():
+    """Invalid problems are rejected by hcu_create before any device work."""
+    import numpy as np
+    import workloads
+    from paper_2507_23612_amd import hcu
+    lib = hcu.load_library()
+    cfg = workloads.make_config("tiny")
+    cases = []
+    bad = dict(cfg); bad["n0"] = 7      # FD order above 12 is not handled
+    cases.append(bad)
+    bad = dict(cfg); bad["kT"] = 0.0
+    cases.append(bad)
+    bad = dict(cfg); bad["ns"] = 4      # 4 states cannot hold 16 electrons
+    cases.append(bad)
+    for b in cases:
+        prob = hcu.Problem(b)
+        h = ctypes.c_void_p()
+        st = lib.hcu_create(ctypes.byref(prob.p), ctypes.byref(h))
+        assert st == hcu.HCU_INVALID_ARG
+        assert lib.hcu_last_error(h)
+        lib.hcu_destroy(h)
+    prob = hcu.Problem(cfg)
+    h = ctypes.c_void_p()
+    assert lib.hcu_create(ctypes.byref(prob.p), ctypes.byref(h)) == hcu.HCU_OK
+    n = ctypes.c_size_t()
+    assert lib.hcu_workspace_size(h, ctypes.byref(n)) == hcu.HCU_OK and n.value > 0
+    # compute calls before binding report HCU_NOT_BOUND
+    assert lib.hcu_chfsi_pass(h, 0, 0) == hcu.HCU_NOT_BOUND
+    assert lib.hcu_apply_h(h, 0, 0, None, None, 1, 10) == hcu.HCU_NOT_BOUND
+    lib.hcu_destroy(h)
