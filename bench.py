@@ -1,0 +1,162 @@
+"""Benchmark of the ChFSI hot path on one MI355X.
+
+A step is one SCF iteration of real-space DFT+U over one block of orbitals:
+degree-m Chebyshev filter (m applications of H = stencil + V_loc + KB +
+Hubbard, fused with the three-term step), Rayleigh-Ritz (H Y, S and Hs
+contractions, FP64 generalized eigensolve, rotation), Fermi level and
+occupations, occupation matrices D, E_U and free energy, Pulay mixing.
+Inputs are resident in HBM before the timed region; table setup is one-time
+and not timed.
+
+value = nd * ns * (m + 1) / seconds per step / 1e9  [Gpts.states/s]
+(m filter applications plus the H Y of Rayleigh-Ritz).
+
+Also reported: the stencil kernel's achieved HBM bandwidth against the
+MI355X peak (algorithmic bytes / event-timed average launch), the SCF wall
+time to convergence, and the CPU oracle's throughput on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "ChFSI H·X Gpts·states/s (FP64 vs mixed); SCF wall-time to 1e-5 Ha/atom"
+
+WORKLOADS = {
+    "c2": "48-atom TiO2-like cell (16 Ti + 32 O), 17.4x17.4x22.4 bohr, grid 72x72x96, 256 states, "
+          "Chebyshev degree 16, 12th-order FD, Gamma, spin-unpolarised",
+    "c3": "108-atom TiO2-like cell (36 Ti + 72 O), 26.1x26.1x22.4 bohr, grid 108x108x96, 640 states, "
+          "Chebyshev degree 16, 12th-order FD, Gamma, spin-unpolarised",
+    "c1": "6-atom TiO2-like cell, 8.7x8.7x5.6 bohr, grid 36x36x24, 32 states, Chebyshev degree 20",
+}
+
+
+def stencil_bytes(cfg, ctx_nproj_nnz, elem):
+    """Algorithmic HBM bytes of one fused Chebyshev-step launch: read Y_i and
+    Y_{i-1}, write Y_{i+1} (3 words per point-state), plus V once and the
+    per-point projector table (value + column) once."""
+    nd = int(np.prod(cfg["n"]))
+    ns = int(cfg["ns"])
+    nnz = ctx_nproj_nnz
+    return 3 * elem * nd * ns + elem * nd + nnz * (elem + 4) + 4 * (nd + 1)
+
+
+def cpu_baseline(cfg, nstates=8, degree=16):
+    """The oracle's Chebyshev filter on a bounded sample of the workload:
+    `nstates` states of the same grid and operator, degree-`degree` filter."""
+    import psutil
+    import workloads
+    from oracle import chfsi
+    from oracle.hamiltonian import Hamiltonian
+    h = Hamiltonian(cfg, D=[0.2 * np.eye(5)] * sum(1 for s in cfg["atom_species"] if s == 0))
+    X = workloads.random_block(h.nd, nstates, 1)
+    proc = psutil.Process()
+    c0 = proc.cpu_times()
+    t0 = time.perf_counter()
+    chfsi.cheb_filter(h.apply, X, degree, 20.0, 190.0, -0.1)
+    dt = time.perf_counter() - t0
+    c1 = proc.cpu_times()
+    cores = max(1, int(round(((c1.user - c0.user) + (c1.system - c0.system)) / dt)))
+    return {"value": h.nd * nstates * degree / dt / 1e9, "unit": "Gpts·states/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{nstates} of {cfg['ns']} states, one degree-{degree} Chebyshev filter "
+                      f"({degree} H applications) on the full {cfg['n'][0]}x{cfg['n'][1]}x{cfg['n'][2]} grid, "
+                      f"{dt:.1f} s on host cores"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--precision", default=None, help="fp64 | mixed (default: the config's)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-scf", action="store_true", help="skip the SCF wall-time run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
+              "(see the sharding design notes); --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    from paper_2507_23612_amd import hcu
+
+    cfg = workloads.make_config(args.config)
+    prec = args.precision or cfg["precision"]
+    nd = int(np.prod(cfg["n"]))
+    ns = int(cfg["ns"])
+    m = int(cfg["degree"])
+
+    ctx = hcu.HcuContext(cfg, prec)
+    ctx.set_hubbard_occupation(hcu.initial_occupation(ctx, cfg))
+    X0, v0 = hcu.start_inputs(ctx, cfg)
+    ctx.set_start(0, 0, X0, v0)
+    del X0, v0
+    torch.cuda.synchronize()
+    ctx.scf_begin(first_passes=1)
+    for _ in range(args.warmup):
+        ctx.scf_step()
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.scf_step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = ctx.get_kernel_times()
+    ctx.set_profiling(False)
+    ms_step = dt / args.steps * 1e3
+    value = nd * ns * (m + 1) / (dt / args.steps) / 1e9
+
+    elem = 4 if prec == "mixed" else 8
+    nnz = ctx.get_sizes()["table_nnz"]
+    bytes_launch = stencil_bytes(cfg, nnz, elem)
+    st_ms = kt["stencil_ms"] / max(kt["stencil_launches"], 1)
+    achieved = bytes_launch / (st_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_stencil (fused stencil + V + projector scatter + Chebyshev step)",
+                "avg_launch_ms": round(st_ms, 4), "algorithmic_bytes_per_launch": int(bytes_launch)}
+    breakdown = {k: round(v / args.steps, 3) for k, v in kt.items() if k.endswith("_ms")}
+
+    out = {"metric": METRIC, "value": round(value, 3), "unit": "Gpts·states/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32" if prec == "mixed" else "f64", "data": "synthetic",
+           "config": {"workload": f"{args.config}: {WORKLOADS.get(args.config, args.config)}",
+                      "precision": prec, "nd": nd, "ns": ns, "degree": m},
+           "roofline": roofline, "kernel_ms_per_step": breakdown}
+
+    if not args.no_scf:
+        ctx2 = hcu.HcuContext(cfg, prec)
+        ctx2.set_hubbard_occupation(hcu.initial_occupation(ctx2, cfg))
+        X0, v0 = hcu.start_inputs(ctx2, cfg)
+        ctx2.set_start(0, 0, X0, v0)
+        del X0, v0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = ctx2.scf(max_iter=100, raise_on_nonconv=False)
+        torch.cuda.synchronize()
+        out["scf"] = {"wall_s": round(time.perf_counter() - t0, 3), "iterations": rep["iterations"],
+                      "converged": bool(rep["converged"]), "F_Ha": rep["F"], "E_U_Ha": rep["E_U"],
+                      "criterion": "|D_out-D_in|_F < 1e-7 and |dF|/atom < 1e-7 Ha"}
+        ctx2.close()
+    ctx.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

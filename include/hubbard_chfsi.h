@@ -145,6 +145,16 @@ typedef struct hcu_energies {
   double mu;                    /* Fermi level                               */
 } hcu_energies;
 
+/* Accumulated device time per kernel family (HIP events on the bound
+ * stream, recorded only while profiling is on). */
+typedef struct hcu_kernel_times {
+  double stencil_ms;  long long stencil_launches;  /* stencil + Chebyshev step + scatter */
+  double project_ms;  long long project_launches;  /* projections onto atom functions    */
+  double gram_ms;     long long gram_launches;     /* S, Hs contractions + reduction     */
+  double eig_ms;      long long eig_launches;      /* generalized eigensolve (rocSOLVER) */
+  double rotate_ms;   long long rotate_launches;   /* X = Y C                            */
+} hcu_kernel_times;
+
 typedef struct hcu_ctx hcu_ctx;
 
 /* Create a context from the problem statement: validates it, builds the
@@ -175,6 +185,17 @@ hcu_status hcu_set_hubbard_occupation(hcu_ctx* ctx, const double* D);
 
 /* Number of atoms carrying a Hubbard manifold (in atom order). */
 int hcu_num_hubbard_atoms(const hcu_ctx* ctx);
+
+/* Sizes of the discretised problem (valid after hcu_create). */
+typedef struct hcu_sizes {
+  int64_t nd;               /* grid points                                   */
+  int     nproj;            /* atom-centred functions (KB + Hubbard)         */
+  int     nblocks;          /* projector blocks (per atom: KB, Hubbard)      */
+  int64_t support_points;   /* sum of block support sizes                    */
+  int64_t table_nnz;        /* (point, function) pairs of the per-point table */
+  size_t  workspace_bytes;
+} hcu_sizes;
+hcu_status hcu_get_sizes(const hcu_ctx* ctx, hcu_sizes* out);
 
 /* Copy a start block X0 (device, nd x ns, ld = nd, the context precision)
  * and a Lanczos start vector v0 (device, nd, same precision) for spin
@@ -225,9 +246,31 @@ hcu_status hcu_rotate(hcu_ctx* ctx, const void* Y, const double* C, void* X, int
  * HCU_NOT_SPD, HCU_NAN. */
 hcu_status hcu_scf(hcu_ctx* ctx, const hcu_scf_opts* opts, hcu_scf_report* rep);
 
+/* Step-wise SCF for callers that drive the loop themselves.  hcu_scf_begin
+ * stores the options, computes the Lanczos bounds of every (spin, k) and
+ * resets the mixing history; each hcu_scf_step runs one SCF iteration (first
+ * one: first_passes filter + Rayleigh-Ritz passes per (spin, k)), updates
+ * occupations, D_out and energies, tests convergence and, unless converged,
+ * Pulay-mixes D and installs the new D_in.  hcu_scf = begin + steps. */
+typedef struct hcu_scf_step_info {
+  int    iteration;
+  int    converged;
+  double F;
+  double E_U;
+  double residual;             /* |D_out - D_in|_F of this iteration        */
+  double dF;                   /* |F - F_prev| / natom (inf on the first)   */
+} hcu_scf_step_info;
+hcu_status hcu_scf_begin(hcu_ctx* ctx, const hcu_scf_opts* opts);
+hcu_status hcu_scf_step(hcu_ctx* ctx, hcu_scf_step_info* info);
+
 /* Occupations, energies and D_out of the current orbitals (used by hcu_scf;
  * callable after hcu_chfsi_pass on every (spin, k)). */
 hcu_status hcu_update_occupations(hcu_ctx* ctx);
+
+/* Turn per-kernel event timing on (1) or off (0); resets the accumulators. */
+hcu_status hcu_set_profiling(hcu_ctx* ctx, int on);
+/* Accumulated kernel times since profiling was turned on (synchronises). */
+hcu_status hcu_get_kernel_times(hcu_ctx* ctx, hcu_kernel_times* t);
 
 /* Results (host outputs, caller-owned buffers). */
 hcu_status hcu_get_eigenvalues(const hcu_ctx* ctx, double* eig);    /* [nspin][nk][ns] */

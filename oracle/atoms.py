@@ -111,6 +111,23 @@ def _images(rc, L):
     return [int(np.ceil(rc / L[a])) + 1 for a in range(3)]
 
 
+def _box_indices(c, rc, L, n):
+    """Grid nodes (no wrap) inside the axis-aligned box [c - rc, c + rc]:
+    returns linear indices and displacements x - c, or None if empty."""
+    h = L / n
+    rng = []
+    for a in range(3):
+        lo = max(int(np.ceil((c[a] - rc) / h[a])), 0)
+        hi = min(int(np.floor((c[a] + rc) / h[a])), n[a] - 1)
+        if lo > hi:
+            return None
+        rng.append(np.arange(lo, hi + 1))
+    kk, jj, ii = np.meshgrid(rng[2], rng[1], rng[0], indexing="ij")
+    d = np.stack([ii.ravel() * h[0] - c[0], jj.ravel() * h[1] - c[1], kk.ravel() * h[2] - c[2]], axis=1)
+    lin = ii.ravel() + n[0] * (jj.ravel() + n[1] * kk.ravel())
+    return lin, d
+
+
 def bloch_function_at(points, center, L, k, radial, l, rc):
     """Bloch-mapped atom-centred functions at arbitrary points.
 
@@ -122,11 +139,17 @@ def bloch_function_at(points, center, L, k, radial, l, rc):
     cplx = np.any(k != 0)
     out = np.zeros((2 * l + 1, points.shape[0]), dtype=complex if cplx else float)
     nim = _images(rc, L)
+    lo, hi = points.min(axis=0), points.max(axis=0)
     for t3 in range(-nim[2], nim[2] + 1):
         for t2 in range(-nim[1], nim[1] + 1):
             for t1 in range(-nim[0], nim[0] + 1):
                 T = np.array([t1, t2, t3]) * L
-                d = points - center - T
+                c = center + T
+                # skip images whose sphere misses the points' bounding box
+                gap = np.maximum(np.maximum(lo - c, c - hi), 0.0)
+                if np.sqrt(np.sum(gap * gap)) > rc:
+                    continue
+                d = points - c
                 r = np.sqrt(np.sum(d * d, axis=1))
                 m = r <= rc
                 if not np.any(m):
@@ -143,28 +166,19 @@ def support_indices(center, L, n, rc):
     `center` (the atom's compact support)."""
     L = np.asarray(L, float)
     n = np.asarray(n)
-    h = L / n
-    idx = set()
+    parts = []
     nim = _images(rc, L)
     for t3 in range(-nim[2], nim[2] + 1):
         for t2 in range(-nim[1], nim[1] + 1):
             for t1 in range(-nim[0], nim[0] + 1):
-                c = center + np.array([t1, t2, t3]) * L
-                rng = []
-                for a in range(3):
-                    lo = max(int(np.ceil((c[a] - rc) / h[a])), 0)
-                    hi = min(int(np.floor((c[a] + rc) / h[a])), n[a] - 1)
-                    rng.append(np.arange(lo, hi + 1))
-                if any(len(x) == 0 for x in rng):
+                box = _box_indices(center + np.array([t1, t2, t3]) * L, rc, L, n)
+                if box is None:
                     continue
-                kk, jj, ii = np.meshgrid(rng[2], rng[1], rng[0], indexing="ij")
-                d = np.stack([ii.ravel() * h[0] - c[0], jj.ravel() * h[1] - c[1],
-                              kk.ravel() * h[2] - c[2]], axis=1)
-                r = np.sqrt(np.sum(d * d, axis=1))
-                sel = r <= rc
-                lin = ii.ravel()[sel] + n[0] * (jj.ravel()[sel] + n[1] * kk.ravel()[sel])
-                idx.update(lin.tolist())
-    return np.array(sorted(idx), dtype=np.int64)
+                lin, d = box
+                parts.append(lin[np.sqrt(np.sum(d * d, axis=1)) <= rc])
+    if not parts:
+        return np.zeros(0, np.int64)
+    return np.unique(np.concatenate(parts)).astype(np.int64)
 
 
 def atom_functions(cfg, k=(0.0, 0.0, 0.0)):
@@ -226,12 +240,11 @@ def lowdin(vals, dv):
 
 
 def local_potential(cfg, tail=1e-17):
-    """V(x) on the grid: -D sum_I sum_T exp(-|x-R_I-T|^2/(2 s^2)), over every
-    image whose Gaussian can exceed `tail` inside the cell."""
+    """V(x) on the grid: -D sum_I sum_T exp(-|x-R_I-T|^2/(2 s^2)), summing
+    every image term that exceeds `tail` (|x - R_I - T| <= s sqrt(2 ln(D/tail)))."""
     L = np.asarray(cfg["L"], float)
     n = np.asarray(cfg["n"])
-    coords = fd.grid_coords(L, n)
-    V = np.zeros(coords.shape[0])
+    V = np.zeros(int(np.prod(n)))
     for ia, s in enumerate(cfg["atom_species"]):
         sp = cfg["species"][s]
         D, sg = sp["vloc_depth"], sp["vloc_width"]
@@ -241,8 +254,13 @@ def local_potential(cfg, tail=1e-17):
         for t3 in range(-nim[2], nim[2] + 1):
             for t2 in range(-nim[1], nim[1] + 1):
                 for t1 in range(-nim[0], nim[0] + 1):
-                    d = coords - R - np.array([t1, t2, t3]) * L
-                    V -= D * np.exp(-np.sum(d * d, axis=1) / (2 * sg * sg))
+                    box = _box_indices(R + np.array([t1, t2, t3]) * L, rcut, L, n)
+                    if box is None:
+                        continue
+                    lin, d = box
+                    r2 = np.sum(d * d, axis=1)
+                    m = r2 <= rcut * rcut
+                    np.subtract.at(V, lin[m], D * np.exp(-r2[m] / (2 * sg * sg)))
     return V
 
 

@@ -163,9 +163,11 @@ template <typename T>
 void apply_h_t(Ctx& c, int spin, int ik, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncol) {
   const T* Q = nullptr;
   if (c.nproj > 0) {
+    ProfScope ps(c, PK_PROJECT);
     launch_project<T>(c, X, ncol, ldx, (const T*)c.d_cscv[ik], c.d_coup[spin], (T*)c.d_P, (T*)c.d_Q, c.stream);
     Q = (const T*)c.d_Q;
   }
+  ProfScope ps(c, PK_STENCIL);
   launch_stencil<T>(c, ik, X, ldx, nullptr, 0, Y, ldy, ncol, Q, (const T*)c.d_csrv[ik], 1.0, 0.0, 0.0, c.stream);
 }
 
@@ -180,12 +182,16 @@ int filter_t(Ctx& c, int spin, int ik, const T* X, int64_t ldx, int ncol, int m,
   const T* csrv = (const T*)c.d_csrv[ik];
   auto project = [&](const T* Y, int64_t ld) {
     if (c.nproj > 0) {
+      ProfScope ps(c, PK_PROJECT);
       launch_project<T>(c, Y, ncol, ld, (const T*)c.d_cscv[ik], c.d_coup[spin], (T*)c.d_P, (T*)c.d_Q, c.stream);
       Q = (const T*)c.d_Q;
     }
   };
   project(X, ldx);
-  launch_stencil<T>(c, ik, X, ldx, nullptr, 0, (T*)c.d_W[0], nd, ncol, Q, csrv, sigma / e, cc, 0.0, c.stream);
+  {
+    ProfScope ps(c, PK_STENCIL);
+    launch_stencil<T>(c, ik, X, ldx, nullptr, 0, (T*)c.d_W[0], nd, ncol, Q, csrv, sigma / e, cc, 0.0, c.stream);
+  }
   const T* prev = X;
   int64_t ldp = ldx;
   int cur = 0;
@@ -193,8 +199,11 @@ int filter_t(Ctx& c, int spin, int ik, const T* X, int64_t ldx, int ncol, int m,
     const double s2 = 1.0 / (tau - sigma);
     const int out = (cur + 1) % 3;
     project((const T*)c.d_W[cur], nd);
-    launch_stencil<T>(c, ik, (const T*)c.d_W[cur], nd, prev, ldp, (T*)c.d_W[out], nd, ncol, Q, csrv,
-                      2.0 * s2 / e, cc, sigma * s2, c.stream);
+    {
+      ProfScope ps(c, PK_STENCIL);
+      launch_stencil<T>(c, ik, (const T*)c.d_W[cur], nd, prev, ldp, (T*)c.d_W[out], nd, ncol, Q, csrv,
+                        2.0 * s2 / e, cc, sigma * s2, c.stream);
+    }
     prev = (const T*)c.d_W[cur];
     ldp = nd;
     cur = out;
@@ -222,20 +231,29 @@ hcu_status pass_t(Ctx& c, int spin, int ik, double* filter_ms) {
   HCU_HIP(hipEventRecord(e1, c.stream));
   if (c.nproj > 0)
     HCU_HIP(hipMemcpyAsync(c.d_PY, c.d_P, esize(c) * (size_t)ns * c.nproj, hipMemcpyDeviceToDevice, c.stream));
-  launch_gram2<T>(c, Y, HY, ns, nd, c.d_S, c.d_Hs, c.stream);
+  {
+    ProfScope ps(c, PK_GRAM);
+    launch_gram2<T>(c, Y, HY, ns, nd, c.d_S, c.d_Hs, c.stream);
+  }
   HCU_HIP(hipGetLastError());
   rocblas_status rs;
   const bool cp = sizeof(T) > sizeof(typename real_of<T>::type);
-  if (cp)
-    rs = rocsolver_zhegvd(c.blas, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, ns,
-                          (rocblas_double_complex*)c.d_Hs, ns, (rocblas_double_complex*)c.d_S, ns,
-                          c.d_lam + (size_t)sk * ns, c.d_E, c.d_info);
-  else
-    rs = rocsolver_dsygvd(c.blas, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, ns, c.d_Hs, ns,
-                          c.d_S, ns, c.d_lam + (size_t)sk * ns, c.d_E, c.d_info);
+  {
+    ProfScope ps(c, PK_EIG);
+    if (cp)
+      rs = rocsolver_zhegvd(c.blas, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, ns,
+                            (rocblas_double_complex*)c.d_Hs, ns, (rocblas_double_complex*)c.d_S, ns,
+                            c.d_lam + (size_t)sk * ns, c.d_E, c.d_info);
+    else
+      rs = rocsolver_dsygvd(c.blas, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, ns, c.d_Hs, ns,
+                            c.d_S, ns, c.d_lam + (size_t)sk * ns, c.d_E, c.d_info);
+  }
   if (rs != rocblas_status_success) return fail(c, HCU_DEVICE, "rocsolver generalized eigensolve failed");
   launch_convert_c<T>(c.d_Hs, (T*)c.d_Cb, ns, cp ? 1 : 0, c.stream);
-  launch_rotate<T>(c, Y, nd, (const T*)c.d_Cb, X, ns, c.stream);
+  {
+    ProfScope ps(c, PK_ROTATE);
+    launch_rotate<T>(c, Y, nd, (const T*)c.d_Cb, X, ns, c.stream);
+  }
   if (c.nproj > 0) launch_rotate_proj<T>(c, (const T*)c.d_PY, (const T*)c.d_Cb, (T*)c.d_PX[sk], ns, c.stream);
   HCU_HIP(hipGetLastError());
   int info = 0;
@@ -246,6 +264,7 @@ hcu_status pass_t(Ctx& c, int spin, int ik, double* filter_ms) {
   float ms = 0;
   hipEventElapsedTime(&ms, e0, e1);
   if (filter_ms) *filter_ms += ms;
+  prof_resolve(c);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (info != 0) {
@@ -374,7 +393,8 @@ hcu_status density_t(Ctx& c, double* rho) {
 struct Pulay {
   int h;
   double beta;
-  std::vector<std::vector<double>> xs, fs;
+  std::vector<std::vector<double>>& xs;
+  std::vector<std::vector<double>>& fs;
   std::vector<double> step(const std::vector<double>& x, const std::vector<double>& f) {
     xs.push_back(x);
     fs.push_back(f);
@@ -505,6 +525,21 @@ hcu_status get_orbitals_v(Ctx& c, int sk, void* dst, int on_device) {
 
 }  // namespace
 
+namespace hcu {
+void prof_resolve(Ctx& c) {
+  for (auto& pe : c.ev_pending) {
+    float ms = 0;
+    if (pe.first >= 0 && hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
+      c.prof_ms[pe.first] += ms;
+      c.prof_count[pe.first] += 1;
+    }
+    c.ev_pool.push_back(pe.second.first);
+    c.ev_pool.push_back(pe.second.second);
+  }
+  c.ev_pending.clear();
+}
+}  // namespace hcu
+
 // ====================================================================== C ABI
 extern "C" {
 
@@ -572,8 +607,29 @@ hcu_status hcu_create(const hcu_problem* p, hcu_ctx** out) {
   return HCU_OK;
 }
 
+hcu_status hcu_set_profiling(hcu_ctx* ctx, int on) {
+  if (!ctx) return HCU_INVALID_ARG;
+  if (ctx->bound) { hipStreamSynchronize(ctx->stream); prof_resolve(*ctx); }
+  ctx->prof = on != 0;
+  for (int i = 0; i < 8; ++i) { ctx->prof_ms[i] = 0; ctx->prof_count[i] = 0; }
+  return HCU_OK;
+}
+
+hcu_status hcu_get_kernel_times(hcu_ctx* ctx, hcu_kernel_times* t) {
+  if (!ctx || !t) return HCU_INVALID_ARG;
+  if (ctx->bound) { hipStreamSynchronize(ctx->stream); prof_resolve(*ctx); }
+  t->stencil_ms = ctx->prof_ms[PK_STENCIL]; t->stencil_launches = ctx->prof_count[PK_STENCIL];
+  t->project_ms = ctx->prof_ms[PK_PROJECT]; t->project_launches = ctx->prof_count[PK_PROJECT];
+  t->gram_ms = ctx->prof_ms[PK_GRAM]; t->gram_launches = ctx->prof_count[PK_GRAM];
+  t->eig_ms = ctx->prof_ms[PK_EIG]; t->eig_launches = ctx->prof_count[PK_EIG];
+  t->rotate_ms = ctx->prof_ms[PK_ROTATE]; t->rotate_launches = ctx->prof_count[PK_ROTATE];
+  return HCU_OK;
+}
+
 void hcu_destroy(hcu_ctx* ctx) {
   if (!ctx) return;
+  for (auto& pe : ctx->ev_pending) { hipEventDestroy(pe.second.first); hipEventDestroy(pe.second.second); }
+  for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
   if (ctx->blas) rocblas_destroy_handle(ctx->blas);
   delete ctx;
 }
@@ -587,6 +643,17 @@ hcu_status hcu_workspace_size(const hcu_ctx* ctx, size_t* bytes) {
 }
 
 int hcu_num_hubbard_atoms(const hcu_ctx* ctx) { return ctx ? (int)ctx->hub_atoms.size() : -1; }
+
+hcu_status hcu_get_sizes(const hcu_ctx* ctx, hcu_sizes* out) {
+  if (!ctx || !out) return HCU_INVALID_ARG;
+  out->nd = ctx->nd;
+  out->nproj = ctx->nproj;
+  out->nblocks = (int)ctx->blocks.size();
+  out->support_points = (int64_t)ctx->supp.size();
+  out->table_nnz = ctx->csr_ptr.empty() ? 0 : ctx->csr_ptr[ctx->nd];
+  out->workspace_bytes = ctx->ws_bytes;
+  return HCU_OK;
+}
 
 hcu_status hcu_bind(hcu_ctx* ctx, void* dev_ptr, size_t bytes, void* stream) {
   if (!ctx) return HCU_INVALID_ARG;
@@ -721,55 +788,66 @@ hcu_status hcu_update_occupations(hcu_ctx* ctx) {
   return DISPATCH(c, occupations_t, c);
 }
 
-hcu_status hcu_scf(hcu_ctx* ctx, const hcu_scf_opts* o, hcu_scf_report* rep) {
+hcu_status hcu_scf_begin(hcu_ctx* ctx, const hcu_scf_opts* o) {
   hcu_status s = check_ctx(ctx);
   if (s != HCU_OK) return s;
   Ctx& c = *ctx;
-  if (!o || !rep) return fail(c, HCU_INVALID_ARG, "null options/report");
+  if (!o) return fail(c, HCU_INVALID_ARG, "null options");
   if (o->max_iter < 1 || o->first_passes < 1 || o->lanczos_steps < 1 || o->pulay_history < 1)
     return fail(c, HCU_INVALID_ARG, "bad SCF options");
-  std::memset(rep, 0, sizeof(*rep));
-  const auto t0 = std::chrono::steady_clock::now();
+  c.scf_opts = *o;
+  c.scf_iter = 0;
+  c.scf_have_old = false;
+  c.mix_x.clear();
+  c.mix_f.clear();
+  c.scf_filter_ms = 0;
+  c.scf_hx_cols = 0;
   for (int sp = 0; sp < c.p.nspin; ++sp)
     for (int k = 0; k < c.p.nk; ++k) {
       s = DISPATCH(c, lanczos_t, c, sp, k, o->lanczos_steps, (double*)nullptr, (double*)nullptr);
       if (s != HCU_OK) return s;
     }
-  Pulay mix{o->pulay_history, o->pulay_beta, {}, {}};
+  c.scf_ready = true;
+  return HCU_OK;
+}
+
+hcu_status hcu_scf_step(hcu_ctx* ctx, hcu_scf_step_info* info) {
+  hcu_status s = check_ctx(ctx);
+  if (s != HCU_OK) return s;
+  Ctx& c = *ctx;
+  if (!c.scf_ready) return fail(c, HCU_INVALID_ARG, "call hcu_scf_begin first");
+  const hcu_scf_opts& o = c.scf_opts;
+  const int passes = c.scf_iter == 0 ? o.first_passes : 1;
+  for (int sp = 0; sp < c.p.nspin; ++sp)
+    for (int k = 0; k < c.p.nk; ++k)
+      for (int ps = 0; ps < passes; ++ps) {
+        s = DISPATCH(c, pass_t, c, sp, k, &c.scf_filter_ms);
+        if (s != HCU_OK) return s;
+        c.scf_hx_cols += (double)c.p.ns * (c.p.degree + 1);
+      }
+  s = DISPATCH(c, occupations_t, c);
+  if (s != HCU_OK) return s;
+  double res = 0;
+  for (size_t i = 0; i < c.D_in.size(); ++i) res += (c.D_out[i] - c.D_in[i]) * (c.D_out[i] - c.D_in[i]);
+  res = std::sqrt(res);
   const int natom = std::max(c.p.natom, 1);
-  double F_old = 0;
-  bool have_old = false;
-  double filt_ms = 0;
-  hcu_status final_status = HCU_NOT_CONVERGED;
-  int it = 0;
-  for (it = 0; it < o->max_iter; ++it) {
-    const int passes = it == 0 ? o->first_passes : 1;
-    for (int sp = 0; sp < c.p.nspin; ++sp)
-      for (int k = 0; k < c.p.nk; ++k)
-        for (int ps = 0; ps < passes; ++ps) {
-          s = DISPATCH(c, pass_t, c, sp, k, &filt_ms);
-          if (s != HCU_OK) return s;
-          rep->hx_columns += (double)c.p.ns * (c.p.degree + 1);
-        }
-    s = DISPATCH(c, occupations_t, c);
-    if (s != HCU_OK) return s;
-    double res = 0;
-    for (size_t i = 0; i < c.D_in.size(); ++i) res += (c.D_out[i] - c.D_in[i]) * (c.D_out[i] - c.D_in[i]);
-    res = std::sqrt(res);
-    const double dF = have_old ? std::fabs(c.en.F - F_old) / natom : INFINITY;
-    if (o->verbose)
-      std::fprintf(stderr, "[hcu scf] it=%d F=%.12f E_U=%.6e res=%.3e dF=%.3e\n", it, c.en.F, c.en.E_U, res, dF);
-    F_old = c.en.F;
-    have_old = true;
-    rep->residual = res;
-    if (o->fixed_iterations > 0) {
-      if (it + 1 >= o->fixed_iterations) { final_status = HCU_OK; ++it; break; }
-    } else if (res < o->tol_d && dF < o->tol_f) {
-      final_status = HCU_OK;
-      rep->converged = 1;
-      ++it;
-      break;
-    }
+  const double dF = c.scf_have_old ? std::fabs(c.en.F - c.scf_F_old) / natom : INFINITY;
+  if (o.verbose)
+    std::fprintf(stderr, "[hcu scf] it=%d F=%.12f E_U=%.6e res=%.3e dF=%.3e\n", c.scf_iter, c.en.F, c.en.E_U, res, dF);
+  c.scf_F_old = c.en.F;
+  c.scf_have_old = true;
+  const bool conv = res < o.tol_d && dF < o.tol_f;
+  if (info) {
+    info->iteration = c.scf_iter;
+    info->converged = conv ? 1 : 0;
+    info->F = c.en.F;
+    info->E_U = c.en.E_U;
+    info->residual = res;
+    info->dF = dF;
+  }
+  ++c.scf_iter;
+  if (!conv) {
+    Pulay mix{o.pulay_history, o.pulay_beta, c.mix_x, c.mix_f};
     std::vector<double> x = d_to_vec(c, c.D_in), xo = d_to_vec(c, c.D_out), f(x.size());
     for (size_t i = 0; i < x.size(); ++i) f[i] = xo[i] - x[i];
     std::vector<double> xn = mix.step(x, f);
@@ -777,12 +855,41 @@ hcu_status hcu_scf(hcu_ctx* ctx, const hcu_scf_opts* o, hcu_scf_report* rep) {
     s = upload_coupling(c);
     if (s != HCU_OK) return s;
   }
+  return HCU_OK;
+}
+
+hcu_status hcu_scf(hcu_ctx* ctx, const hcu_scf_opts* o, hcu_scf_report* rep) {
+  hcu_status s = check_ctx(ctx);
+  if (s != HCU_OK) return s;
+  Ctx& c = *ctx;
+  if (!o || !rep) return fail(c, HCU_INVALID_ARG, "null options/report");
+  std::memset(rep, 0, sizeof(*rep));
+  const auto t0 = std::chrono::steady_clock::now();
+  s = hcu_scf_begin(ctx, o);
+  if (s != HCU_OK) return s;
+  hcu_status final_status = HCU_NOT_CONVERGED;
+  int it = 0;
+  hcu_scf_step_info si{};
+  for (it = 0; it < o->max_iter; ++it) {
+    s = hcu_scf_step(ctx, &si);
+    if (s != HCU_OK) return s;
+    rep->residual = si.residual;
+    if (o->fixed_iterations > 0) {
+      if (it + 1 >= o->fixed_iterations) { final_status = HCU_OK; ++it; break; }
+    } else if (si.converged) {
+      final_status = HCU_OK;
+      rep->converged = 1;
+      ++it;
+      break;
+    }
+  }
   rep->iterations = it;
   rep->F = c.en.F;
   rep->E_U = c.en.E_U;
   rep->e_band = c.en.e_band;
   rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  rep->filter_seconds = filt_ms * 1e-3;
+  rep->filter_seconds = c.scf_filter_ms * 1e-3;
+  rep->hx_columns = c.scf_hx_cols;
   if (final_status != HCU_OK) c.err = "SCF did not converge within max_iter";
   return final_status;
 }

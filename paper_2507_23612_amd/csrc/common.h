@@ -155,7 +155,48 @@ struct Ctx {
   std::string err;
   // tuning
   int tile_x = 0, tile_yt = 0, ry = 4, tile_z = 0;
+  // SCF state (hcu_scf_begin / hcu_scf_step)
+  hcu_scf_opts scf_opts{};
+  int scf_iter = 0;
+  bool scf_ready = false;
+  double scf_F_old = 0;
+  bool scf_have_old = false;
+  std::vector<std::vector<double>> mix_x, mix_f;
+  double scf_filter_ms = 0;
+  double scf_hx_cols = 0;
+  // kernel timing (HIP events on the bound stream, resolved at sync points)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  double prof_ms[8] = {0};
+  long prof_count[8] = {0};
 };
+
+enum ProfKind { PK_STENCIL = 0, PK_PROJECT = 1, PK_GRAM = 2, PK_EIG = 3, PK_ROTATE = 4, PK_SMALL = 5 };
+
+// Scoped timing of the launches queued inside it (no-op unless profiling).
+struct ProfScope {
+  Ctx& c;
+  int kind;
+  hipEvent_t e1 = nullptr, e2 = nullptr;
+  ProfScope(Ctx& c_, int k) : c(c_), kind(k) {
+    if (!c.prof) return;
+    e1 = take(); e2 = take();
+    hipEventRecord(e1, c.stream);
+  }
+  ~ProfScope() {
+    if (!c.prof) return;
+    hipEventRecord(e2, c.stream);
+    c.ev_pending.push_back({kind, {e1, e2}});
+  }
+  hipEvent_t take() {
+    hipEvent_t e;
+    if (!c.ev_pool.empty()) { e = c.ev_pool.back(); c.ev_pool.pop_back(); }
+    else hipEventCreate(&e);
+    return e;
+  }
+};
+void prof_resolve(Ctx& c);   // after a stream sync: accumulate and recycle events
 
 inline int sk_index(const Ctx& c, int spin, int ik) { return spin * c.p.nk + ik; }
 inline bool k_complex(const Ctx& c, int ik) {

@@ -48,9 +48,27 @@ class hcu_scf_report(C.Structure):
                 ("filter_seconds", C.c_double), ("hx_columns", C.c_double)]
 
 
+class hcu_scf_step_info(C.Structure):
+    _fields_ = [("iteration", C.c_int), ("converged", C.c_int), ("F", C.c_double), ("E_U", C.c_double),
+                ("residual", C.c_double), ("dF", C.c_double)]
+
+
+class hcu_sizes(C.Structure):
+    _fields_ = [("nd", C.c_int64), ("nproj", C.c_int), ("nblocks", C.c_int), ("support_points", C.c_int64),
+                ("table_nnz", C.c_int64), ("workspace_bytes", C.c_size_t)]
+
+
 class hcu_energies(C.Structure):
     _fields_ = [("F", C.c_double), ("e_band", C.c_double), ("dc", C.c_double), ("E_U", C.c_double),
                 ("ts", C.c_double), ("mu", C.c_double)]
+
+
+class hcu_kernel_times(C.Structure):
+    _fields_ = [("stencil_ms", C.c_double), ("stencil_launches", C.c_longlong),
+                ("project_ms", C.c_double), ("project_launches", C.c_longlong),
+                ("gram_ms", C.c_double), ("gram_launches", C.c_longlong),
+                ("eig_ms", C.c_double), ("eig_launches", C.c_longlong),
+                ("rotate_ms", C.c_double), ("rotate_launches", C.c_longlong)]
 
 
 _lib = None
@@ -73,6 +91,7 @@ def load_library(path=LIB_PATH):
         "hcu_bind": (C.c_int, [P, P, C.c_size_t, P]),
         "hcu_set_hubbard_occupation": (C.c_int, [P, C.POINTER(C.c_double)]),
         "hcu_num_hubbard_atoms": (C.c_int, [P]),
+        "hcu_get_sizes": (C.c_int, [P, C.POINTER(hcu_sizes)]),
         "hcu_set_start": (C.c_int, [P, C.c_int, C.c_int, P, P]),
         "hcu_apply_h": (C.c_int, [P, C.c_int, C.c_int, P, P, C.c_int, C.c_int64]),
         "hcu_cheb_filter": (C.c_int, [P, C.c_int, C.c_int, P, P, C.c_int, C.c_int64, C.c_int, C.c_double,
@@ -84,6 +103,10 @@ def load_library(path=LIB_PATH):
         "hcu_rotate": (C.c_int, [P, P, C.POINTER(C.c_double), P, C.c_int, C.c_int64]),
         "hcu_scf": (C.c_int, [P, C.POINTER(hcu_scf_opts), C.POINTER(hcu_scf_report)]),
         "hcu_update_occupations": (C.c_int, [P]),
+        "hcu_scf_begin": (C.c_int, [P, C.POINTER(hcu_scf_opts)]),
+        "hcu_scf_step": (C.c_int, [P, C.POINTER(hcu_scf_step_info)]),
+        "hcu_set_profiling": (C.c_int, [P, C.c_int]),
+        "hcu_get_kernel_times": (C.c_int, [P, C.POINTER(hcu_kernel_times)]),
         "hcu_get_eigenvalues": (C.c_int, [P, C.POINTER(C.c_double)]),
         "hcu_get_occupations": (C.c_int, [P, C.POINTER(C.c_double)]),
         "hcu_get_hubbard_occupation": (C.c_int, [P, C.POINTER(C.c_double)]),
@@ -280,6 +303,30 @@ class HcuContext:
         if st != HCU_OK and not (st == HCU_NOT_CONVERGED and not raise_on_nonconv):
             self._check(st)
         return {k: getattr(r, k) for k, _ in hcu_scf_report._fields_}
+
+    def get_sizes(self):
+        z = hcu_sizes()
+        self._check(self.lib.hcu_get_sizes(self.h, C.byref(z)))
+        return {k: getattr(z, k) for k, _ in hcu_sizes._fields_}
+
+    def set_profiling(self, on=True):
+        self._check(self.lib.hcu_set_profiling(self.h, 1 if on else 0))
+
+    def get_kernel_times(self):
+        t = hcu_kernel_times()
+        self._check(self.lib.hcu_get_kernel_times(self.h, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in hcu_kernel_times._fields_}
+
+    def scf_begin(self, max_iter=100, first_passes=4, lanczos_steps=10, pulay_history=7, pulay_beta=0.3,
+                  tol_d=1e-7, tol_f=1e-7, verbose=False):
+        self._scf_opts = hcu_scf_opts(max_iter, first_passes, lanczos_steps, pulay_history, pulay_beta, tol_d,
+                                      tol_f, 0, 1 if verbose else 0)
+        self._check(self.lib.hcu_scf_begin(self.h, C.byref(self._scf_opts)))
+
+    def scf_step(self):
+        i = hcu_scf_step_info()
+        self._check(self.lib.hcu_scf_step(self.h, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in hcu_scf_step_info._fields_}
 
     def get_eigenvalues(self):
         out = np.zeros((self.nspin, self.nk, self.ns))
