@@ -148,11 +148,12 @@ typedef struct hcu_energies {
 /* Accumulated device time per kernel family (HIP events on the bound
  * stream, recorded only while profiling is on). */
 typedef struct hcu_kernel_times {
-  double stencil_ms;  long long stencil_launches;  /* stencil + Chebyshev step + scatter */
+  double stencil_ms;  long long stencil_launches;  /* stencil + V + Chebyshev step       */
   double project_ms;  long long project_launches;  /* projections onto atom functions    */
   double gram_ms;     long long gram_launches;     /* S, Hs contractions + reduction     */
   double eig_ms;      long long eig_launches;      /* generalized eigensolve (rocSOLVER) */
   double rotate_ms;   long long rotate_launches;   /* X = Y C                            */
+  double scatter_ms;  long long scatter_launches;  /* projector scatter (KB + Hubbard)   */
 } hcu_kernel_times;
 
 typedef struct hcu_ctx hcu_ctx;

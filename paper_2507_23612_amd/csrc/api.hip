@@ -158,17 +158,81 @@ void small_sym_eigvals(std::vector<double> A, int n, std::vector<double>& ev) {
   std::sort(ev.begin(), ev.end());
 }
 
+// Hs C = S C diag(lam), C^H S C = I (FP64 on the device): Cholesky S = U^H U,
+// A = U^-H Hs U^-1, A = Q diag(lam) Q^H, C = U^-1 Q.  Overwrites d_S with U
+// and d_Hs with C.  Sets d_info (nonzero: S not positive definite or the
+// tridiagonal eigensolver did not converge).
+hcu_status generalized_eig(Ctx& c, int n, bool cp, double* lam) {
+  rocblas_status r;
+  if (cp) {
+    auto* S = (rocblas_double_complex*)c.d_S;
+    auto* A = (rocblas_double_complex*)c.d_Hs;
+    const rocblas_double_complex one{1.0, 0.0};
+    r = rocsolver_zpotrf(c.blas, rocblas_fill_upper, n, S, n, c.d_info);
+    if (r == rocblas_status_success)
+      r = rocblas_ztrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_conjugate_transpose,
+                        rocblas_diagonal_non_unit, n, n, &one, S, n, A, n);
+    if (r == rocblas_status_success)
+      r = rocblas_ztrsm(c.blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                        rocblas_diagonal_non_unit, n, n, &one, S, n, A, n);
+    if (r == rocblas_status_success)
+      r = rocsolver_zheevd(c.blas, rocblas_evect_original, rocblas_fill_upper, n, A, n, lam, c.d_E, c.d_info + 1);
+    if (r == rocblas_status_success)
+      r = rocblas_ztrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                        rocblas_diagonal_non_unit, n, n, &one, S, n, A, n);
+  } else {
+    const double one = 1.0;
+    r = rocsolver_dpotrf(c.blas, rocblas_fill_upper, n, c.d_S, n, c.d_info);
+    if (r == rocblas_status_success)
+      r = rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
+                        rocblas_diagonal_non_unit, n, n, &one, c.d_S, n, c.d_Hs, n);
+    if (r == rocblas_status_success)
+      r = rocblas_dtrsm(c.blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                        rocblas_diagonal_non_unit, n, n, &one, c.d_S, n, c.d_Hs, n);
+    if (r == rocblas_status_success)
+      r = rocsolver_dsyevd(c.blas, rocblas_evect_original, rocblas_fill_upper, n, c.d_Hs, n, lam, c.d_E,
+                           c.d_info + 1);
+    if (r == rocblas_status_success)
+      r = rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                        rocblas_diagonal_non_unit, n, n, &one, c.d_S, n, c.d_Hs, n);
+  }
+  if (r != rocblas_status_success) return fail(c, HCU_DEVICE, "rocSOLVER/rocBLAS call failed in the eigensolve");
+  return HCU_OK;
+}
+
 // ------------------------------------------------------------------ typed steps
 template <typename T>
 void apply_h_t(Ctx& c, int spin, int ik, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncol) {
-  const T* Q = nullptr;
   if (c.nproj > 0) {
     ProfScope ps(c, PK_PROJECT);
     launch_project<T>(c, X, ncol, ldx, (const T*)c.d_cscv[ik], c.d_coup[spin], (T*)c.d_P, (T*)c.d_Q, c.stream);
-    Q = (const T*)c.d_Q;
   }
-  ProfScope ps(c, PK_STENCIL);
-  launch_stencil<T>(c, ik, X, ldx, nullptr, 0, Y, ldy, ncol, Q, (const T*)c.d_csrv[ik], 1.0, 0.0, 0.0, c.stream);
+  {
+    ProfScope ps(c, PK_STENCIL);
+    launch_stencil<T>(c, ik, X, ldx, nullptr, 0, Y, ldy, ncol, 1.0, 0.0, 0.0, c.stream);
+  }
+  if (c.nproj > 0) {
+    ProfScope ps(c, PK_SCATTER);
+    launch_nl_scatter<T>(c, ik, Y, ldy, ncol, (const T*)c.d_Q, 1.0, c.stream);
+  }
+}
+
+// One Chebyshev step: out = alpha (H y - c y) - beta yprev
+template <typename T>
+void cheb_step_t(Ctx& c, int spin, int ik, const T* y, int64_t ldy, const T* yprev, int64_t ldp, T* out,
+                 int64_t ldo, int ncol, double alpha, double cc, double beta) {
+  if (c.nproj > 0) {
+    ProfScope ps(c, PK_PROJECT);
+    launch_project<T>(c, y, ncol, ldy, (const T*)c.d_cscv[ik], c.d_coup[spin], (T*)c.d_P, (T*)c.d_Q, c.stream);
+  }
+  {
+    ProfScope ps(c, PK_STENCIL);
+    launch_stencil<T>(c, ik, y, ldy, yprev, ldp, out, ldo, ncol, alpha, cc, beta, c.stream);
+  }
+  if (c.nproj > 0) {
+    ProfScope ps(c, PK_SCATTER);
+    launch_nl_scatter<T>(c, ik, out, ldo, ncol, (const T*)c.d_Q, alpha, c.stream);
+  }
 }
 
 // returns the index of the work block that holds the filtered block
@@ -178,32 +242,15 @@ int filter_t(Ctx& c, int spin, int ik, const T* X, int64_t ldx, int ncol, int m,
   double sigma = e / (aL - cc);
   const double tau = 2.0 / sigma;
   const int64_t nd = c.nd;
-  const T* Q = nullptr;
-  const T* csrv = (const T*)c.d_csrv[ik];
-  auto project = [&](const T* Y, int64_t ld) {
-    if (c.nproj > 0) {
-      ProfScope ps(c, PK_PROJECT);
-      launch_project<T>(c, Y, ncol, ld, (const T*)c.d_cscv[ik], c.d_coup[spin], (T*)c.d_P, (T*)c.d_Q, c.stream);
-      Q = (const T*)c.d_Q;
-    }
-  };
-  project(X, ldx);
-  {
-    ProfScope ps(c, PK_STENCIL);
-    launch_stencil<T>(c, ik, X, ldx, nullptr, 0, (T*)c.d_W[0], nd, ncol, Q, csrv, sigma / e, cc, 0.0, c.stream);
-  }
+  cheb_step_t<T>(c, spin, ik, X, ldx, nullptr, 0, (T*)c.d_W[0], nd, ncol, sigma / e, cc, 0.0);
   const T* prev = X;
   int64_t ldp = ldx;
   int cur = 0;
   for (int i = 2; i <= m; ++i) {
     const double s2 = 1.0 / (tau - sigma);
     const int out = (cur + 1) % 3;
-    project((const T*)c.d_W[cur], nd);
-    {
-      ProfScope ps(c, PK_STENCIL);
-      launch_stencil<T>(c, ik, (const T*)c.d_W[cur], nd, prev, ldp, (T*)c.d_W[out], nd, ncol, Q, csrv,
-                        2.0 * s2 / e, cc, sigma * s2, c.stream);
-    }
+    cheb_step_t<T>(c, spin, ik, (const T*)c.d_W[cur], nd, prev, ldp, (T*)c.d_W[out], nd, ncol, 2.0 * s2 / e, cc,
+                   sigma * s2);
     prev = (const T*)c.d_W[cur];
     ldp = nd;
     cur = out;
@@ -236,19 +283,12 @@ hcu_status pass_t(Ctx& c, int spin, int ik, double* filter_ms) {
     launch_gram2<T>(c, Y, HY, ns, nd, c.d_S, c.d_Hs, c.stream);
   }
   HCU_HIP(hipGetLastError());
-  rocblas_status rs;
   const bool cp = sizeof(T) > sizeof(typename real_of<T>::type);
   {
     ProfScope ps(c, PK_EIG);
-    if (cp)
-      rs = rocsolver_zhegvd(c.blas, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, ns,
-                            (rocblas_double_complex*)c.d_Hs, ns, (rocblas_double_complex*)c.d_S, ns,
-                            c.d_lam + (size_t)sk * ns, c.d_E, c.d_info);
-    else
-      rs = rocsolver_dsygvd(c.blas, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, ns, c.d_Hs, ns,
-                            c.d_S, ns, c.d_lam + (size_t)sk * ns, c.d_E, c.d_info);
+    hcu_status es = generalized_eig(c, ns, cp, c.d_lam + (size_t)sk * ns);
+    if (es != HCU_OK) return es;
   }
-  if (rs != rocblas_status_success) return fail(c, HCU_DEVICE, "rocsolver generalized eigensolve failed");
   launch_convert_c<T>(c.d_Hs, (T*)c.d_Cb, ns, cp ? 1 : 0, c.stream);
   {
     ProfScope ps(c, PK_ROTATE);
@@ -256,8 +296,8 @@ hcu_status pass_t(Ctx& c, int spin, int ik, double* filter_ms) {
   }
   if (c.nproj > 0) launch_rotate_proj<T>(c, (const T*)c.d_PY, (const T*)c.d_Cb, (T*)c.d_PX[sk], ns, c.stream);
   HCU_HIP(hipGetLastError());
-  int info = 0;
-  HCU_HIP(hipMemcpyAsync(&info, c.d_info, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+  int info2[2] = {0, 0};
+  HCU_HIP(hipMemcpyAsync(info2, c.d_info, 2 * sizeof(int), hipMemcpyDeviceToHost, c.stream));
   std::vector<double> lam(ns);
   HCU_HIP(hipMemcpyAsync(lam.data(), c.d_lam + (size_t)sk * ns, sizeof(double) * ns, hipMemcpyDeviceToHost, c.stream));
   HCU_HIP(hipStreamSynchronize(c.stream));
@@ -267,10 +307,11 @@ hcu_status pass_t(Ctx& c, int spin, int ik, double* filter_ms) {
   prof_resolve(c);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  if (info != 0) {
-    return fail(c, HCU_NOT_SPD, "generalized eigensolve failed (info=" + std::to_string(info) +
-                                    "): Gram matrix not positive definite or no convergence");
-  }
+  if (info2[0] != 0)
+    return fail(c, HCU_NOT_SPD, "Gram matrix of the filtered block not positive definite (potrf info=" +
+                                    std::to_string(info2[0]) + ")");
+  if (info2[1] != 0)
+    return fail(c, HCU_DEVICE, "subspace eigensolver did not converge (info=" + std::to_string(info2[1]) + ")");
   for (int i = 0; i < ns; ++i)
     if (!std::isfinite(lam[i])) return fail(c, HCU_NAN, "non-finite Ritz value");
   c.bounds[3 * sk] = lam[ns - 1];
@@ -623,6 +664,7 @@ hcu_status hcu_get_kernel_times(hcu_ctx* ctx, hcu_kernel_times* t) {
   t->gram_ms = ctx->prof_ms[PK_GRAM]; t->gram_launches = ctx->prof_count[PK_GRAM];
   t->eig_ms = ctx->prof_ms[PK_EIG]; t->eig_launches = ctx->prof_count[PK_EIG];
   t->rotate_ms = ctx->prof_ms[PK_ROTATE]; t->rotate_launches = ctx->prof_count[PK_ROTATE];
+  t->scatter_ms = ctx->prof_ms[PK_SCATTER]; t->scatter_launches = ctx->prof_count[PK_SCATTER];
   return HCU_OK;
 }
 

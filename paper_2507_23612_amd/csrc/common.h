@@ -124,7 +124,7 @@ struct Ctx {
   std::vector<void*> d_v0;           // per (spin, k): Lanczos start vector
   void* d_W[3] = {nullptr, nullptr, nullptr};   // work blocks nd x ns
   void* d_P = nullptr;               // projections [ns][nproj] (block type)
-  void* d_Q = nullptr;               // coupled projections
+  void* d_Q = nullptr;               // coupled projections, transposed: [nproj][ns]
   void* d_PY = nullptr;              // projections of the filtered block (for D)
   std::vector<void*> d_PX;           // per (spin,k) projections of X [ns][nproj]
   double* d_part = nullptr;          // split-K partials of the Gram matrices
@@ -172,7 +172,7 @@ struct Ctx {
   long prof_count[8] = {0};
 };
 
-enum ProfKind { PK_STENCIL = 0, PK_PROJECT = 1, PK_GRAM = 2, PK_EIG = 3, PK_ROTATE = 4, PK_SMALL = 5 };
+enum ProfKind { PK_STENCIL = 0, PK_PROJECT = 1, PK_GRAM = 2, PK_EIG = 3, PK_ROTATE = 4, PK_SCATTER = 5 };
 
 // Scoped timing of the launches queued inside it (no-op unless profiling).
 struct ProfScope {
@@ -209,11 +209,13 @@ hcu_status build_structure(Ctx& c);          // host: supports, blocks, csr
 hcu_status device_tables(Ctx& c);            // device: V_loc, csc/csr values, Loewdin
 void fill_stencil_coef(const Ctx& c, int ik, StencilCoef& sc);
 
-// stencil.hip: out = alpha*(H_loc y + NL - c y) - beta*yprev   (Q holds coupled projections)
+// stencil.hip: out = alpha*(H_loc y - c y) - beta*yprev
 template <typename T>
 void launch_stencil(const Ctx& c, int ik, const T* Yin, int64_t ld, const T* Yprev, int64_t ld_prev, T* Yout,
-                    int64_t ld_out, int ncol, const T* Q, const T* csrv, double alpha, double cshift, double beta,
-                    hipStream_t st);
+                    int64_t ld_out, int ncol, double alpha, double cshift, double beta, hipStream_t st);
+// nonlocal.hip: Y += alpha * sum_j phi_j Qt[j][s]  (per-point table, state-blocked)
+template <typename T>
+void launch_nl_scatter(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T* Qt, double alpha, hipStream_t st);
 
 // proj.hip: P = Phi^H Y dV (per block) and Q = C_b P
 template <typename T>

@@ -89,36 +89,37 @@ __global__ __launch_bounds__(256) void k_gram2(const T* __restrict__ Y, const T*
 
 // Sum the chunk partials in a fixed order, scale by dV, mirror into full
 // symmetric n x n column-major matrices (diagonal tiles symmetrised).
+// Grid: (tile, element block of 256, matrix).
 __global__ void k_gram_reduce(const double* __restrict__ part, int nchunk, int ntiles,
                               const int2* __restrict__ tiles, int n, double dv, double* __restrict__ S,
                               double* __restrict__ Hs) {
   const int t = blockIdx.x;
+  const int w = blockIdx.z;
   const int2 tl = tiles[t];
   const int i0 = tl.x * GT, j0 = tl.y * GT;
   const bool diag = tl.x == tl.y;
-  for (int e = threadIdx.x; e < GT * GT; e += blockDim.x) {
-    const int i = e / GT, j = e % GT;
-    if (i0 + i >= n || j0 + j >= n) continue;
-    if (diag && j < i) continue;
-    for (int w = 0; w < 2; ++w) {
-      double s1 = 0, s2 = 0;
-      for (int ch = 0; ch < nchunk; ++ch) {
-        const double* base = part + (((int64_t)ch * ntiles + t) * 2 + w) * GT * GT;
-        s1 += base[i * GT + j];
-        if (diag) s2 += base[j * GT + i];
-      }
-      double v = diag ? 0.5 * (s1 + s2) * dv : s1 * dv;
-      double* M = w == 0 ? S : Hs;
-      M[(int64_t)(i0 + i) + (int64_t)(j0 + j) * n] = v;
-      M[(int64_t)(j0 + j) + (int64_t)(i0 + i) * n] = v;
-    }
+  const int e = blockIdx.y * blockDim.x + threadIdx.x;
+  if (e >= GT * GT) return;
+  const int i = e / GT, j = e % GT;
+  if (i0 + i >= n || j0 + j >= n) return;
+  if (diag && j < i) return;
+  double s1 = 0, s2 = 0;
+  const int64_t stride = (int64_t)ntiles * 2 * GT * GT;
+  const double* base = part + ((int64_t)t * 2 + w) * GT * GT;
+  for (int ch = 0; ch < nchunk; ++ch) {
+    s1 += base[ch * stride + i * GT + j];
+    if (diag) s2 += base[ch * stride + j * GT + i];
   }
+  const double v = diag ? 0.5 * (s1 + s2) * dv : s1 * dv;
+  double* M = w == 0 ? S : Hs;
+  M[(int64_t)(i0 + i) + (int64_t)(j0 + j) * n] = v;
+  M[(int64_t)(j0 + j) + (int64_t)(i0 + i) * n] = v;
 }
 
 static void gram_plan(int n, int64_t nd, int& ntiles_1d, int& ntiles, int64_t& kchunk, int& nchunk) {
   ntiles_1d = (n + GT - 1) / GT;
   ntiles = ntiles_1d * (ntiles_1d + 1) / 2;
-  int want = std::max(1, 2048 / ntiles);
+  int want = std::max(1, 1024 / ntiles);
   kchunk = (nd + want - 1) / want;
   kchunk = ((kchunk + GK - 1) / GK) * GK;
   if (kchunk < 1024) kchunk = 1024;
@@ -150,7 +151,7 @@ void launch_gram2(const Ctx& c, const T* Y, const T* HY, int ncol, int64_t ld, d
   gram_plan(ncol, c.nd, t1, nt, kc, nc);
   const int2* d_tiles = c.d_tiles;
   k_gram2<T><<<dim3(nt, nc), 256, 0, st>>>(Y, HY, ld, ncol, c.nd, kc, d_tiles, nt, c.d_part);
-  k_gram_reduce<<<nt, 256, 0, st>>>(c.d_part, nc, nt, d_tiles, ncol, c.dv, S, Hs);
+  k_gram_reduce<<<dim3(nt, GT * GT / 256, 2), 256, 0, st>>>(c.d_part, nc, nt, d_tiles, ncol, c.dv, S, Hs);
 }
 
 // X = Y C, computed as X^T = C^T Y^T so that each lane's outputs run along the

@@ -3,7 +3,7 @@
 // atom after atom, as for nonlocal projectors):
 //
 //   P[s][j0+m] = dV * sum_{q in supp} conj(phi_m(x_q)) y_s(x_q)          (trapezoid rule)
-//   Q[s][j0+m] = sum_m' C_b[m][m'] P[s][j0+m']
+//   Q[j0+m][s] = sum_m' C_b[m][m'] P[s][j0+m']     (Q stored transposed for the scatter)
 //
 // with C_b = diag(gamma) for the KB channels and C_b = U (1/2 - D) for the
 // Hubbard manifold (Eq. DerED).  A workgroup owns one block and S states: it
@@ -27,7 +27,8 @@ __global__ __launch_bounds__(256) void k_project(const T* __restrict__ Y, int64_
                                                  const BlockDesc* __restrict__ blocks,
                                                  const int* __restrict__ blist, const int* __restrict__ supp,
                                                  const T* __restrict__ cscv, const double* __restrict__ coup,
-                                                 T* __restrict__ P, T* __restrict__ Q, int nproj, double dv) {
+                                                 T* __restrict__ P, T* __restrict__ Q, int nproj, int ldq,
+                                                 double dv) {
   const BlockDesc& b = blocks[blist[blockIdx.x]];
   const int s0 = blockIdx.y * S;
   const int ns_here = min(S, ncol - s0);
@@ -84,7 +85,7 @@ __global__ __launch_bounds__(256) void k_project(const T* __restrict__ Y, int64_
     T qv = T(0);
     for (int mp = 0; mp < NM; ++mp) qv += (typename real_of<T>::type)cb[m * NM + mp] * pbuf[mp * S + s];
     P[(int64_t)(s0 + s) * nproj + b.j0 + m] = pbuf[t];
-    Q[(int64_t)(s0 + s) * nproj + b.j0 + m] = qv;
+    Q[(int64_t)(b.j0 + m) * ldq + s0 + s] = qv;
   }
 }
 
@@ -94,7 +95,7 @@ static void launch_nm(const Ctx& c, const T* Y, int ncol, int64_t ld, const T* c
   constexpr int S = (sizeof(T) > 8 || NM > 5) ? 4 : 8;
   dim3 grid(nblk, (ncol + S - 1) / S);
   k_project<T, NM, S><<<grid, 256, 0, st>>>(Y, ld, ncol, c.d_blocks, d_list, c.d_supp, cscv, coup, P, Q, c.nproj,
-                                            c.dv);
+                                            c.p.ns, c.dv);
 }
 
 // Blocks are grouped by their function count; the per-count block lists live

@@ -1,12 +1,12 @@
 // Local part of H and the Chebyshev three-term step in one pass over the grid:
 //
-//   out = alpha * ( -1/2 Delta_h y + V y + sum_j phi_j(x) Q_j - c y ) - beta * yprev
+//   out = alpha * ( -1/2 Delta_h y + V y - c y ) - beta * yprev
 //
 // -1/2 Delta_h is the centred 2*n0-order stencil along each axis with
 // periodic wrap and the Bloch factor e^{+-i k_a L_a} on wrapped values
 // (Sec. II.B: off-grid indices are mapped back periodically with the Bloch
-// factor).  The last sum is the projector scatter (KB + Hubbard) with Q the
-// coupled projections of y, read from a per-point list of (function, value).
+// factor).  The projector term alpha * sum_j phi_j Q_j is added afterwards by
+// the state-blocked scatter kernel (nonlocal.hip).
 //
 // Layout: y is one column of an nd x ncol column-major block, x fastest.  A
 // workgroup owns a TX x TY tile of an x-y plane for one state and streams a
@@ -31,8 +31,7 @@ struct KArgs {
   RT ph_re[3], ph_im[3];        // Bloch factor per axis
   int n1, n2, n3;
   int tiles_x, tz;
-  int nproj;
-  int has_prev, has_nl;
+  int has_prev;
   int64_t ld, ld_prev, ld_out;
 };
 
@@ -68,8 +67,6 @@ __device__ inline int wrap(int g, int n, int& w) {
 template <typename T, typename RT, int R, int RY>
 __global__ __launch_bounds__(256) void k_stencil(const T* __restrict__ Yin, const T* __restrict__ Yprev,
                                                  T* __restrict__ Yout, const RT* __restrict__ V,
-                                                 const int* __restrict__ csr_ptr, const int* __restrict__ csr_col,
-                                                 const T* __restrict__ csr_val, const T* __restrict__ Q,
                                                  const KArgs<RT> a) {
   extern __shared__ unsigned char smem_raw[];
   T* sp = reinterpret_cast<T*>(smem_raw);
@@ -146,13 +143,6 @@ __global__ __launch_bounds__(256) void k_stencil(const T* __restrict__ Yin, cons
         const int64_t pidx = gx + (int64_t)n1 * gy[r] + zoff;
         const T cen = q[r][R];
         acc += (a.center + V[pidx] - a.cshift) * cen;
-        if (a.has_nl) {
-          const int e0 = csr_ptr[pidx], e1 = csr_ptr[pidx + 1];
-          const T* Qs = Q + s * a.nproj;
-          T nl = T(0);
-          for (int e = e0; e < e1; ++e) nl += csr_val[e] * Qs[csr_col[e]];
-          acc += nl;
-        }
         T out = a.alpha * acc;
         if (a.has_prev) out += (-a.beta) * Yprev[s * a.ld_prev + pidx];
         Yout[s * a.ld_out + pidx] = out;
@@ -185,15 +175,14 @@ static void pick_tiles(const Ctx& c, int RY, int& TX, int& TYt, int& tz, int nco
 }
 
 template <typename T, typename RT, int R>
-static void launch_r(const Ctx& c, const KArgs<RT>& a, dim3 grid, dim3 block, size_t lds, const T* Yin,
-                     const T* Yprev, T* Yout, const RT* V, const T* csrv, const T* Q, hipStream_t st) {
-  k_stencil<T, RT, R, ry_of<T>()><<<grid, block, lds, st>>>(Yin, Yprev, Yout, V, c.d_csr_ptr, c.d_csr_col, csrv, Q, a);
+static void launch_r(const KArgs<RT>& a, dim3 grid, dim3 block, size_t lds, const T* Yin, const T* Yprev, T* Yout,
+                     const RT* V, hipStream_t st) {
+  k_stencil<T, RT, R, ry_of<T>()><<<grid, block, lds, st>>>(Yin, Yprev, Yout, V, a);
 }
 
 template <typename T>
 void launch_stencil(const Ctx& c, int ik, const T* Yin, int64_t ld, const T* Yprev, int64_t ld_prev, T* Yout,
-                    int64_t ld_out, int ncol, const T* Q, const T* csrv, double alpha, double cshift, double beta,
-                    hipStream_t st) {
+                    int64_t ld_out, int ncol, double alpha, double cshift, double beta, hipStream_t st) {
   using RT = typename real_of<T>::type;
   StencilCoef sc;
   fill_stencil_coef(c, ik, sc);
@@ -207,9 +196,7 @@ void launch_stencil(const Ctx& c, int ik, const T* Yin, int64_t ld, const T* Ypr
   a.alpha = (RT)alpha; a.cshift = (RT)cshift; a.beta = (RT)beta;
   for (int d = 0; d < 3; ++d) { a.ph_re[d] = (RT)sc.phase_re[d]; a.ph_im[d] = (RT)sc.phase_im[d]; }
   a.n1 = c.p.n[0]; a.n2 = c.p.n[1]; a.n3 = c.p.n[2];
-  a.nproj = c.nproj;
   a.has_prev = (Yprev != nullptr && beta != 0.0) ? 1 : 0;
-  a.has_nl = (c.nproj > 0 && Q != nullptr) ? 1 : 0;
   a.ld = ld;
   a.ld_prev = ld_prev;
   a.ld_out = ld_out;
@@ -225,18 +212,18 @@ void launch_stencil(const Ctx& c, int ik, const T* Yin, int64_t ld, const T* Ypr
   const RT* V;
   if constexpr (sizeof(RT) == 4) V = c.d_Vf; else V = c.d_V;
   switch (R) {
-    case 1: launch_r<T, RT, 1>(c, a, grid, block, lds, Yin, Yprev, Yout, V, csrv, Q, st); break;
-    case 2: launch_r<T, RT, 2>(c, a, grid, block, lds, Yin, Yprev, Yout, V, csrv, Q, st); break;
-    case 3: launch_r<T, RT, 3>(c, a, grid, block, lds, Yin, Yprev, Yout, V, csrv, Q, st); break;
-    case 4: launch_r<T, RT, 4>(c, a, grid, block, lds, Yin, Yprev, Yout, V, csrv, Q, st); break;
-    case 5: launch_r<T, RT, 5>(c, a, grid, block, lds, Yin, Yprev, Yout, V, csrv, Q, st); break;
-    default: launch_r<T, RT, 6>(c, a, grid, block, lds, Yin, Yprev, Yout, V, csrv, Q, st); break;
+    case 1: launch_r<T, RT, 1>(a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    case 2: launch_r<T, RT, 2>(a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    case 3: launch_r<T, RT, 3>(a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    case 4: launch_r<T, RT, 4>(a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    case 5: launch_r<T, RT, 5>(a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    default: launch_r<T, RT, 6>(a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
   }
 }
 
 #define INST_STENCIL(T)                                                                                 \
   template void launch_stencil<T>(const Ctx&, int, const T*, int64_t, const T*, int64_t, T*, int64_t, int, \
-                                  const T*, const T*, double, double, double, hipStream_t);
+                                  double, double, double, hipStream_t);
 INST_STENCIL(double)
 INST_STENCIL(float)
 INST_STENCIL(cplx<double>)

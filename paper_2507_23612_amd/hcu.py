@@ -68,7 +68,8 @@ class hcu_kernel_times(C.Structure):
                 ("project_ms", C.c_double), ("project_launches", C.c_longlong),
                 ("gram_ms", C.c_double), ("gram_launches", C.c_longlong),
                 ("eig_ms", C.c_double), ("eig_launches", C.c_longlong),
-                ("rotate_ms", C.c_double), ("rotate_launches", C.c_longlong)]
+                ("rotate_ms", C.c_double), ("rotate_launches", C.c_longlong),
+                ("scatter_ms", C.c_double), ("scatter_launches", C.c_longlong)]
 
 
 _lib = None
