@@ -104,6 +104,7 @@ def main():
     ctx.set_start(0, 0, X0, v0)
     del X0, v0
     torch.cuda.synchronize()
+    tuning = ctx.autotune()
     ctx.scf_begin(first_passes=1)
     for _ in range(args.warmup):
         ctx.scf_step()
@@ -136,10 +137,11 @@ def main():
            "dtype": "f32" if prec == "mixed" else "f64", "data": "synthetic",
            "config": {"workload": f"{args.config}: {WORKLOADS.get(args.config, args.config)}",
                       "precision": prec, "nd": nd, "ns": ns, "degree": m},
-           "roofline": roofline, "kernel_ms_per_step": breakdown}
+           "roofline": roofline, "kernel_ms_per_step": breakdown, "stencil_tuning": tuning}
 
     if not args.no_scf:
         ctx2 = hcu.HcuContext(cfg, prec)
+        ctx2.set_tuning(tuning["tile_x"], tuning["tile_yt"], tuning["ry"], tuning["tile_z"])
         ctx2.set_hubbard_occupation(hcu.initial_occupation(ctx2, cfg))
         X0, v0 = hcu.start_inputs(ctx2, cfg)
         ctx2.set_start(0, 0, X0, v0)

@@ -268,6 +268,21 @@ hcu_status hcu_scf_step(hcu_ctx* ctx, hcu_scf_step_info* info);
  * callable after hcu_chfsi_pass on every (spin, k)). */
 hcu_status hcu_update_occupations(hcu_ctx* ctx);
 
+/* Stencil tile shape: tile_x threads along x (== n1: the x halo is taken
+ * from the tile itself), tile_yt thread rows of ry points, tile_z planes
+ * streamed per workgroup; stencil_ms = measured time of one full-block
+ * launch (autotune output). */
+typedef struct hcu_tuning {
+  int tile_x, tile_yt, ry, tile_z;
+  double stencil_ms;
+} hcu_tuning;
+/* Time every admissible tile shape on the full orbital block of (spin 0,
+ * k 0) (contents are not changed) and keep the fastest; tile_x = 0 in
+ * hcu_set_tuning restores the built-in choice.  Errors: HCU_INVALID_ARG for
+ * a shape the grid does not admit. */
+hcu_status hcu_autotune(hcu_ctx* ctx, hcu_tuning* best);
+hcu_status hcu_set_tuning(hcu_ctx* ctx, const hcu_tuning* t);
+
 /* Turn per-kernel event timing on (1) or off (0); resets the accumulators. */
 hcu_status hcu_set_profiling(hcu_ctx* ctx, int on);
 /* Accumulated kernel times since profiling was turned on (synchronises). */

@@ -556,6 +556,56 @@ hcu_status rotate_v(Ctx& c, const void* Y, const double* C, void* X, int ncol, i
   return HCU_OK;
 }
 
+// Time every admissible stencil tile shape on the full block of (spin 0,
+// k 0) and keep the fastest (hcu_autotune).
+template <typename T>
+hcu_status autotune_t(Ctx& c, hcu_tuning* best) {
+  const int n1 = c.p.n[0], n3 = c.p.n[2];
+  const int ns = c.p.ns;
+  const T* X = (const T*)c.d_X[0];
+  const T* Yp = (const T*)c.d_W[1];
+  T* Y = (T*)c.d_W[0];
+  std::vector<hcu_tuning> cands;
+  const int txs[3] = {n1 <= 128 ? n1 : 64, 64, 32};
+  for (int RY : {4, 2})
+    for (int ti = 0; ti < 3; ++ti) {
+      const int TX = txs[ti];
+      if (TX > n1 || (ti > 0 && TX == txs[0])) continue;
+      for (int TYt : {1, 2, 3, 4, 6, 8, 12, 16}) {
+        if (TX * TYt > 512 || TX * TYt < 64) continue;
+        for (int zd : {1, 2, 4}) {
+          const int tz = (n3 + zd - 1) / zd;
+          if (zd > 1 && tz < 8) continue;
+          if (!stencil_shape_ok(c, TX, TYt, RY, tz)) continue;
+          cands.push_back(hcu_tuning{TX, TYt, RY, tz, 0.0});
+        }
+      }
+    }
+  if (cands.empty()) return fail(c, HCU_INVALID_ARG, "no admissible stencil shape");
+  hipEvent_t e0, e1;
+  HCU_HIP(hipEventCreate(&e0));
+  HCU_HIP(hipEventCreate(&e1));
+  double best_ms = 1e300;
+  hcu_tuning bt = cands[0];
+  for (hcu_tuning& t : cands) {
+    c.tile_x = t.tile_x; c.tile_yt = t.tile_yt; c.ry = t.ry; c.tile_z = t.tile_z;
+    launch_stencil<T>(c, 0, X, c.nd, Yp, c.nd, Y, c.nd, ns, 0.5, 1.0, 0.25, c.stream);
+    HCU_HIP(hipEventRecord(e0, c.stream));
+    for (int r = 0; r < 3; ++r) launch_stencil<T>(c, 0, X, c.nd, Yp, c.nd, Y, c.nd, ns, 0.5, 1.0, 0.25, c.stream);
+    HCU_HIP(hipEventRecord(e1, c.stream));
+    HCU_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    t.stencil_ms = ms / 3.0;
+    if (t.stencil_ms < best_ms) { best_ms = t.stencil_ms; bt = t; }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  c.tile_x = bt.tile_x; c.tile_yt = bt.tile_yt; c.ry = bt.ry; c.tile_z = bt.tile_z;
+  if (best) *best = bt;
+  return HCU_OK;
+}
+
 template <typename T>
 hcu_status get_orbitals_v(Ctx& c, int sk, void* dst, int on_device) {
   HCU_HIP(hipMemcpyAsync(dst, c.d_X[sk], sizeof(T) * (size_t)c.nd * c.p.ns,
@@ -934,6 +984,23 @@ hcu_status hcu_scf(hcu_ctx* ctx, const hcu_scf_opts* o, hcu_scf_report* rep) {
   rep->hx_columns = c.scf_hx_cols;
   if (final_status != HCU_OK) c.err = "SCF did not converge within max_iter";
   return final_status;
+}
+
+hcu_status hcu_autotune(hcu_ctx* ctx, hcu_tuning* best) {
+  hcu_status s = check_ctx(ctx);
+  if (s != HCU_OK) return s;
+  Ctx& c = *ctx;
+  return DISPATCH(c, autotune_t, c, best);
+}
+
+hcu_status hcu_set_tuning(hcu_ctx* ctx, const hcu_tuning* t) {
+  if (!ctx || !t) return HCU_INVALID_ARG;
+  Ctx& c = *ctx;
+  if (t->tile_x == 0) { c.tile_x = 0; return HCU_OK; }   // back to the built-in choice
+  if (!stencil_shape_ok(c, t->tile_x, t->tile_yt, t->ry, t->tile_z))
+    return fail(c, HCU_INVALID_ARG, "stencil tile shape not admissible for this grid");
+  c.tile_x = t->tile_x; c.tile_yt = t->tile_yt; c.ry = t->ry; c.tile_z = t->tile_z;
+  return HCU_OK;
 }
 
 hcu_status hcu_get_eigenvalues(const hcu_ctx* ctx, double* eig) {

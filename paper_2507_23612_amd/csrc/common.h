@@ -213,6 +213,7 @@ void fill_stencil_coef(const Ctx& c, int ik, StencilCoef& sc);
 template <typename T>
 void launch_stencil(const Ctx& c, int ik, const T* Yin, int64_t ld, const T* Yprev, int64_t ld_prev, T* Yout,
                     int64_t ld_out, int ncol, double alpha, double cshift, double beta, hipStream_t st);
+bool stencil_shape_ok(const Ctx& c, int TX, int TYt, int RY, int tz);
 // nonlocal.hip: Y += alpha * sum_j phi_j Qt[j][s]  (per-point table, state-blocked)
 template <typename T>
 void launch_nl_scatter(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T* Qt, double alpha, hipStream_t st);

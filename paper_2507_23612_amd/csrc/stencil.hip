@@ -20,8 +20,6 @@
 
 namespace hcu {
 
-// points per thread along y: fewer for double complex to bound registers
-template <typename T> constexpr int ry_of() { return sizeof(T) > 8 ? 2 : 4; }
 
 template <typename RT>
 struct KArgs {
@@ -64,14 +62,17 @@ __device__ inline int wrap(int g, int n, int& w) {
   return g - w * n;
 }
 
+constexpr int kHaloSlots = 8;     // halo values a thread stages per plane (host checks the bound)
+
 template <typename T, typename RT, int R, int RY>
-__global__ __launch_bounds__(256) void k_stencil(const T* __restrict__ Yin, const T* __restrict__ Yprev,
+__global__ __launch_bounds__(512) void k_stencil(const T* __restrict__ Yin, const T* __restrict__ Yprev,
                                                  T* __restrict__ Yout, const RT* __restrict__ V,
                                                  const KArgs<RT> a) {
   extern __shared__ unsigned char smem_raw[];
-  T* sp = reinterpret_cast<T*>(smem_raw);
   const int TX = blockDim.x, TYt = blockDim.y, TY = TYt * RY;
-  const int SW = TX + 2 * R;
+  const int SW = TX + 2 * R, SH = TY + 2 * R;
+  T* const buf0 = reinterpret_cast<T*>(smem_raw);
+  T* const buf1 = buf0 + SW * SH;
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = ty * TX + tx, nthr = TX * TYt;
   const int bx = blockIdx.x % a.tiles_x, by = blockIdx.x / a.tiles_x;
@@ -82,102 +83,171 @@ __global__ __launch_bounds__(256) void k_stencil(const T* __restrict__ Yin, cons
   const T* __restrict__ Ys = Yin + s * a.ld;
   const int n1 = a.n1, n2 = a.n2, n3 = a.n3;
   const int64_t plane = (int64_t)n1 * n2;
+  // x halo from the LDS row itself when the tile spans the whole x range
+  const bool xfull = (TX == n1) && (n1 >= R);
 
   int wxo, wyo[RY];
-  const int gx = wrap(x0 + tx, n1, wxo);      // wxo == 1 only for ragged tiles
+  const int gx = wrap(x0 + tx, n1, wxo);
   int gy[RY];
   for (int r = 0; r < RY; ++r) gy[r] = wrap(y0 + ty * RY + r, n2, wyo[r]);
 
+  // halo slots owned by this thread: y halo (2R rows x TX) then, unless
+  // xfull, x halo (TY rows x 2R)
+  const int nyh = 2 * R * TX, nh = nyh + (xfull ? 0 : TY * 2 * R);
+  int h_xy[kHaloSlots], h_lds[kHaloSlots], h_w[kHaloSlots];
+  for (int k = 0; k < kHaloSlots; ++k) {
+    const int e = tid + k * nthr;
+    h_lds[k] = -1; h_xy[k] = 0; h_w[k] = 0;
+    if (e >= nh) continue;
+    int row, col, hx, hy, wx, wy;
+    if (e < nyh) {
+      const int rh = e / TX;
+      col = e % TX + R;
+      row = rh < R ? rh : TY + rh;
+      hx = wrap(x0 + col - R, n1, wx);
+      hy = wrap(y0 + row - R, n2, wy);
+    } else {
+      const int e2 = e - nyh;
+      const int cc = e2 % (2 * R);
+      row = e2 / (2 * R) + R;
+      col = cc < R ? cc : TX + cc;
+      hx = wrap(x0 + col - R, n1, wx);
+      hy = wrap(y0 + row - R, n2, wy);
+    }
+    h_lds[k] = row * SW + col;
+    h_xy[k] = hx + n1 * hy;
+    h_w[k] = (wx + 4) * 16 + (wy + 4);
+  }
+
   T q[RY][2 * R + 1];
-  // prime the z queue with planes zbeg-R .. zbeg+R-1
-  for (int dz = -R; dz < R; ++dz) {
+  for (int dz = -R; dz <= R; ++dz) {
     int wz;
-    int gz = wrap(zbeg + dz, n3, wz);
+    const int gz = wrap(zbeg + dz, n3, wz);
     for (int r = 0; r < RY; ++r)
       q[r][dz + R] = Ld<T>::get(Ys, gx + (int64_t)n1 * gy[r] + plane * gz, wxo, wyo[r], wz, a);
   }
-
-  for (int z = zbeg; z < zend; ++z) {
-    {
-      int wz;
-      int gz = wrap(z + R, n3, wz);
-      for (int r = 0; r < RY; ++r)
-        q[r][2 * R] = Ld<T>::get(Ys, gx + (int64_t)n1 * gy[r] + plane * gz, wxo, wyo[r], wz, a);
-    }
-    __syncthreads();
-    for (int r = 0; r < RY; ++r) sp[(ty * RY + r + R) * SW + tx + R] = q[r][R];
-    const int64_t zoff = plane * z;
-    // x halo: TY rows x 2R columns
-    for (int e = tid; e < TY * 2 * R; e += nthr) {
-      int row = e / (2 * R), cc = e % (2 * R);
-      int col = cc < R ? cc : TX + cc;
-      int wx, wy;
-      int hx = wrap(x0 + col - R, n1, wx);
-      int hy = wrap(y0 + row, n2, wy);
-      sp[(row + R) * SW + col] = Ld<T>::get(Ys, hx + (int64_t)n1 * hy + zoff, wx, wy, 0, a);
-    }
-    // y halo: 2R rows x TX columns
-    for (int e = tid; e < 2 * R * TX; e += nthr) {
-      int rh = e / TX, col = e % TX;
-      int row = rh < R ? rh : TY + rh;
-      int wx, wy;
-      int hx = wrap(x0 + col, n1, wx);
-      int hy = wrap(y0 + row - R, n2, wy);
-      sp[row * SW + col + R] = Ld<T>::get(Ys, hx + (int64_t)n1 * hy + zoff, wx, wy, 0, a);
-    }
-    __syncthreads();
-
-    T strip[RY + 2 * R];
-    for (int t = 0; t < RY + 2 * R; ++t) strip[t] = sp[(ty * RY + t) * SW + tx + R];
+  // stage plane zbeg
+  auto stage = [&](T* buf, const T* hreg) {
     for (int r = 0; r < RY; ++r) {
       const int row = ty * RY + r + R;
-      const T* L = sp + row * SW + tx + R;
+      const T v = q[r][R];
+      buf[row * SW + tx + R] = v;
+      if (xfull) {
+        if (tx < R) buf[row * SW + tx + n1 + R] = Ld<T>::get(&v, 0, 1, 0, 0, a);
+        if (tx >= n1 - R) buf[row * SW + tx - n1 + R] = Ld<T>::get(&v, 0, -1, 0, 0, a);
+      }
+    }
+    for (int k = 0; k < kHaloSlots; ++k)
+      if (h_lds[k] >= 0) buf[h_lds[k]] = hreg[k];
+  };
+  T hreg[kHaloSlots];
+  {
+    int wz;
+    const int gz = wrap(zbeg, n3, wz);
+    for (int k = 0; k < kHaloSlots; ++k)
+      if (h_lds[k] >= 0)
+        hreg[k] = Ld<T>::get(Ys, h_xy[k] + plane * gz, h_w[k] / 16 - 4, h_w[k] % 16 - 4, wz, a);
+  }
+  stage(buf0, hreg);
+  __syncthreads();
+
+  int cur = 0;
+  for (int z = zbeg; z < zend; ++z) {
+    const bool more = z + 1 < zend;
+    // prefetch: next plane's halo and queue head, this plane's V and Yprev
+    T qn[RY];
+    if (more) {
+      int wz;
+      const int gz = wrap(z + 1 + R, n3, wz);
+      for (int r = 0; r < RY; ++r)
+        qn[r] = Ld<T>::get(Ys, gx + (int64_t)n1 * gy[r] + plane * gz, wxo, wyo[r], wz, a);
+      for (int k = 0; k < kHaloSlots; ++k)
+        if (h_lds[k] >= 0)
+          hreg[k] = Ld<T>::get(Ys, h_xy[k] + plane * (z + 1), h_w[k] / 16 - 4, h_w[k] % 16 - 4, 0, a);
+    }
+    const int64_t zoff = plane * z;
+    RT vv[RY];
+    T yp[RY];
+    for (int r = 0; r < RY; ++r) {
+      const int64_t pidx = gx + (int64_t)n1 * gy[r] + zoff;
+      vv[r] = V[pidx];
+      yp[r] = a.has_prev ? Yprev[s * a.ld_prev + pidx] : T(0);
+    }
+    const T* B = cur ? buf1 : buf0;
+    for (int r = 0; r < RY; ++r) {
+      const int row = ty * RY + r + R;
+      const T* L = B + row * SW + tx + R;
       T acc = T(0);
       for (int p = 1; p <= R; ++p) {
         acc += a.kx[p] * (L[p] + L[-p]);
-        acc += a.ky[p] * (strip[r + R + p] + strip[r + R - p]);
+        acc += a.ky[p] * (L[p * SW] + L[-p * SW]);
         acc += a.kz[p] * (q[r][R + p] + q[r][R - p]);
       }
       const bool active = (x0 + tx < n1) && (y0 + ty * RY + r < n2);
       if (active) {
         const int64_t pidx = gx + (int64_t)n1 * gy[r] + zoff;
-        const T cen = q[r][R];
-        acc += (a.center + V[pidx] - a.cshift) * cen;
+        acc += (a.center + vv[r] - a.cshift) * q[r][R];
         T out = a.alpha * acc;
-        if (a.has_prev) out += (-a.beta) * Yprev[s * a.ld_prev + pidx];
+        if (a.has_prev) out += (-a.beta) * yp[r];
         Yout[s * a.ld_out + pidx] = out;
       }
     }
-    for (int r = 0; r < RY; ++r)
+    for (int r = 0; r < RY; ++r) {
       for (int t = 0; t < 2 * R; ++t) q[r][t] = q[r][t + 1];
+      if (more) q[r][2 * R] = qn[r];
+    }
+    if (more) stage(cur ? buf0 : buf1, hreg);
+    __syncthreads();
+    cur ^= 1;
   }
 }
 
-// Tile shape for a grid (TX threads along x, TYt thread rows, RY points each).
-static void pick_tiles(const Ctx& c, int RY, int& TX, int& TYt, int& tz, int ncol) {
+// Tile shape for a grid: TX threads along x, TYt thread rows, RY points per
+// thread along y, tz planes per workgroup.  Tuned values (hcu_autotune) win.
+struct StencilShape { int TX, TYt, RY, tz; };
+
+static bool shape_ok(const Ctx& c, const StencilShape& sh, int R) {
+  const int n1 = c.p.n[0], n2 = c.p.n[1];
+  if (sh.TX < 1 || sh.TX > n1 || sh.TYt < 1 || sh.TX * sh.TYt > 512) return false;
+  if (sh.RY != 2 && sh.RY != 4) return false;
+  const int TY = sh.TYt * sh.RY;
+  if (TY > n2) return false;
+  const int nthr = sh.TX * sh.TYt;
+  const int nh = 2 * R * sh.TX + ((sh.TX == n1 && n1 >= R) ? 0 : TY * 2 * R);
+  if ((nh + nthr - 1) / nthr > kHaloSlots) return false;
+  return sh.tz >= 1;
+}
+
+bool stencil_shape_ok(const Ctx& c, int TX, int TYt, int RY, int tz) {
+  return shape_ok(c, StencilShape{TX, TYt, RY, tz}, c.p.n0);
+}
+
+static StencilShape pick_tiles(const Ctx& c, int ncol, int elem) {
   const int n1 = c.p.n[0], n2 = c.p.n[1], n3 = c.p.n[2];
-  if (c.tile_x > 0) {
-    TX = c.tile_x; TYt = c.tile_yt; tz = c.tile_z;
-  } else {
-    TX = n1 <= 128 ? n1 : 64;
-    TYt = std::max(1, 256 / TX);
-    tz = 0;
-  }
-  TX = std::min(TX, n1);
-  while (TYt > 1 && TYt * RY > n2) --TYt;
-  if (TYt * RY > n2) TYt = 1;
-  if (tz <= 0) {
-    int tiles = ((n1 + TX - 1) / TX) * ((n2 + TYt * RY - 1) / (TYt * RY));
-    int zs = 1;
-    while ((int64_t)tiles * zs * ncol < 2048 && n3 / (zs * 2) >= 16) zs *= 2;
-    tz = (n3 + zs - 1) / zs;
-  }
+  const int R = c.p.n0;
+  StencilShape sh{c.tile_x, c.tile_yt, c.ry, c.tile_z};
+  if (sh.TX > 0 && shape_ok(c, sh, R)) return sh;
+  sh.RY = elem > 8 ? 2 : 4;
+  sh.TX = n1 <= 128 ? n1 : 64;
+  sh.TYt = std::max(1, 256 / sh.TX);
+  while (sh.TYt > 1 && sh.TYt * sh.RY > n2) --sh.TYt;
+  if (sh.TYt * sh.RY > n2) sh.RY = 2;
+  if (sh.TYt * sh.RY > n2) sh.RY = 2, sh.TYt = 1;
+  int tiles = ((n1 + sh.TX - 1) / sh.TX) * ((n2 + sh.TYt * sh.RY - 1) / (sh.TYt * sh.RY));
+  int zs = 1;
+  while ((int64_t)tiles * zs * ncol < 2048 && n3 / (zs * 2) >= 16) zs *= 2;
+  sh.tz = (n3 + zs - 1) / zs;
+  while (!shape_ok(c, sh, R) && sh.TYt > 1) --sh.TYt;
+  return sh;
 }
 
 template <typename T, typename RT, int R>
-static void launch_r(const KArgs<RT>& a, dim3 grid, dim3 block, size_t lds, const T* Yin, const T* Yprev, T* Yout,
-                     const RT* V, hipStream_t st) {
-  k_stencil<T, RT, R, ry_of<T>()><<<grid, block, lds, st>>>(Yin, Yprev, Yout, V, a);
+static void launch_r(int RY, const KArgs<RT>& a, dim3 grid, dim3 block, size_t lds, const T* Yin, const T* Yprev,
+                     T* Yout, const RT* V, hipStream_t st) {
+  if (RY == 4)
+    k_stencil<T, RT, R, 4><<<grid, block, lds, st>>>(Yin, Yprev, Yout, V, a);
+  else
+    k_stencil<T, RT, R, 2><<<grid, block, lds, st>>>(Yin, Yprev, Yout, V, a);
 }
 
 template <typename T>
@@ -200,24 +270,24 @@ void launch_stencil(const Ctx& c, int ik, const T* Yin, int64_t ld, const T* Ypr
   a.ld = ld;
   a.ld_prev = ld_prev;
   a.ld_out = ld_out;
-  int TX, TYt, tz;
-  pick_tiles(c, ry_of<T>(), TX, TYt, tz, ncol);
-  const int TY = TYt * ry_of<T>();
+  const StencilShape sh = pick_tiles(c, ncol, (int)sizeof(T));
+  const int TX = sh.TX, TYt = sh.TYt, tz = sh.tz;
+  const int TY = TYt * sh.RY;
   a.tiles_x = (a.n1 + TX - 1) / TX;
   a.tz = tz;
   dim3 grid(a.tiles_x * ((a.n2 + TY - 1) / TY), (a.n3 + tz - 1) / tz, ncol);
   dim3 block(TX, TYt);
   const int R = sc.R;
-  size_t lds = (size_t)(TY + 2 * R) * (TX + 2 * R) * sizeof(T);
+  size_t lds = 2 * (size_t)(TY + 2 * R) * (TX + 2 * R) * sizeof(T);
   const RT* V;
   if constexpr (sizeof(RT) == 4) V = c.d_Vf; else V = c.d_V;
   switch (R) {
-    case 1: launch_r<T, RT, 1>(a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
-    case 2: launch_r<T, RT, 2>(a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
-    case 3: launch_r<T, RT, 3>(a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
-    case 4: launch_r<T, RT, 4>(a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
-    case 5: launch_r<T, RT, 5>(a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
-    default: launch_r<T, RT, 6>(a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    case 1: launch_r<T, RT, 1>(sh.RY, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    case 2: launch_r<T, RT, 2>(sh.RY, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    case 3: launch_r<T, RT, 3>(sh.RY, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    case 4: launch_r<T, RT, 4>(sh.RY, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    case 5: launch_r<T, RT, 5>(sh.RY, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    default: launch_r<T, RT, 6>(sh.RY, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
   }
 }
 

@@ -72,6 +72,11 @@ class hcu_kernel_times(C.Structure):
                 ("scatter_ms", C.c_double), ("scatter_launches", C.c_longlong)]
 
 
+class hcu_tuning(C.Structure):
+    _fields_ = [("tile_x", C.c_int), ("tile_yt", C.c_int), ("ry", C.c_int), ("tile_z", C.c_int),
+                ("stencil_ms", C.c_double)]
+
+
 _lib = None
 
 
@@ -107,6 +112,8 @@ def load_library(path=LIB_PATH):
         "hcu_scf_begin": (C.c_int, [P, C.POINTER(hcu_scf_opts)]),
         "hcu_scf_step": (C.c_int, [P, C.POINTER(hcu_scf_step_info)]),
         "hcu_set_profiling": (C.c_int, [P, C.c_int]),
+        "hcu_autotune": (C.c_int, [P, C.POINTER(hcu_tuning)]),
+        "hcu_set_tuning": (C.c_int, [P, C.POINTER(hcu_tuning)]),
         "hcu_get_kernel_times": (C.c_int, [P, C.POINTER(hcu_kernel_times)]),
         "hcu_get_eigenvalues": (C.c_int, [P, C.POINTER(C.c_double)]),
         "hcu_get_occupations": (C.c_int, [P, C.POINTER(C.c_double)]),
@@ -309,6 +316,15 @@ class HcuContext:
         z = hcu_sizes()
         self._check(self.lib.hcu_get_sizes(self.h, C.byref(z)))
         return {k: getattr(z, k) for k, _ in hcu_sizes._fields_}
+
+    def autotune(self):
+        t = hcu_tuning()
+        self._check(self.lib.hcu_autotune(self.h, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in hcu_tuning._fields_}
+
+    def set_tuning(self, tile_x, tile_yt=1, ry=4, tile_z=1):
+        t = hcu_tuning(tile_x, tile_yt, ry, tile_z, 0.0)
+        self._check(self.lib.hcu_set_tuning(self.h, C.byref(t)))
 
     def set_profiling(self, on=True):
         self._check(self.lib.hcu_set_profiling(self.h, 1 if on else 0))

@@ -66,6 +66,46 @@ def test_apply_h_matches_oracle(name):
     assert err < 1e-12
 
 
+@pytest.mark.parametrize("shape", [(20, 2, 4, 14), (20, 4, 2, 5), (8, 8, 2, 3), (16, 4, 4, 7), (20, 2, 2, 1)])
+def test_apply_h_tile_shapes_ragged(shape):
+    """Every stencil tiling mode (x halo from the tile row or from memory,
+    ragged x/y tiles, 2 or 4 rows per thread, z chunks) against the oracle."""
+    torch = _torch()
+    cfg = _ragged()
+    ctx = _ctx(cfg)
+    ctx.set_tuning(*shape)
+    D = _rand_D(1, ctx.nhub, 8)
+    ctx.set_hubbard_occupation(D)
+    X = workloads.random_block(ctx.nd, ctx.ns, 15)
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.empty_like(Xd)
+    ctx.apply_h(Xd, Yd)
+    torch.cuda.synchronize()
+    want = _oracle_H(cfg, D[0]).apply(X)
+    err = np.max(np.abs(Yd.cpu().numpy() - want)) / np.max(np.abs(want))
+    assert err < 1e-12
+
+
+def test_apply_h_after_autotune_c1():
+    torch = _torch()
+    cfg = workloads.make_config("c1")
+    ctx = _ctx(cfg)
+    from paper_2507_23612_amd import hcu
+    X0, v0 = hcu.start_inputs(ctx, cfg)
+    ctx.set_start(0, 0, X0, v0)
+    best = ctx.autotune()
+    print(f"[gpu] autotune c1 -> {best}", flush=True)
+    D = _rand_D(1, ctx.nhub, 9)
+    ctx.set_hubbard_occupation(D)
+    X = workloads.random_block(ctx.nd, ctx.ns, 16)
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.empty_like(Xd)
+    ctx.apply_h(Xd, Yd)
+    torch.cuda.synchronize()
+    want = _oracle_H(cfg, D[0]).apply(X)
+    assert np.max(np.abs(Yd.cpu().numpy() - want)) / np.max(np.abs(want)) < 1e-12
+
+
 def test_apply_h_ld_and_partial_columns():
     torch = _torch()
     cfg = workloads.make_config("tiny")
