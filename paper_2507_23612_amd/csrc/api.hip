@@ -47,11 +47,17 @@ size_t layout(Ctx& c, char* base) {
   b.take(c.d_blocks, sizeof(BlockDesc) * c.blocks.size());
   b.take(c.d_nm_lists, sizeof(int) * c.blocks.size());
   b.take(c.d_hub_blocks, sizeof(int) * nh);
+  b.take(c.d_boff, sizeof(int64_t) * c.boff.size());
+  b.take(c.d_bnj, sizeof(int) * c.bnj.size());
+  b.take(c.d_bj, sizeof(int) * c.bj.size());
+  b.take(c.d_bsrc, sizeof(int64_t) * c.bsrc.size());
   c.d_cscv.assign(c.p.nk, nullptr);
   c.d_csrv.assign(c.p.nk, nullptr);
+  c.d_bval.assign(c.p.nk, nullptr);
   for (int k = 0; k < c.p.nk; ++k) {
     b.take(c.d_cscv[k], es * c.nval);
     b.take(c.d_csrv[k], es * nnz);
+    b.take(c.d_bval[k], es * c.bsrc.size());
   }
   c.d_coup.assign(c.p.nspin, nullptr);
   for (int s = 0; s < c.p.nspin; ++s) b.take(c.d_coup[s], sizeof(double) * c.coup_size);
@@ -67,6 +73,7 @@ size_t layout(Ctx& c, char* base) {
   b.take(c.d_P, es * (size_t)ns * c.nproj);
   b.take(c.d_Q, es * (size_t)ns * c.nproj);
   b.take(c.d_PY, es * (size_t)ns * c.nproj);
+  b.take(c.d_ppart, es * (size_t)ns * c.nproj * project_max_chunks(c));
   c.part_elems = c.any_complex ? gram_partial_elems_c(ns, c.nd) : gram_partial_elems(ns, c.nd);
   b.take(c.d_part, sizeof(double) * c.part_elems);
   b.take(c.d_tiles, sizeof(int2) * gram_tiles(ns, c.any_complex).size());
@@ -201,41 +208,44 @@ hcu_status generalized_eig(Ctx& c, int n, bool cp, double* lam) {
 }
 
 // ------------------------------------------------------------------ typed steps
+// Projection of y onto every atom-centred function: P = Phi^H y dV,
+// Q = C P (Q transposed).
+template <typename T>
+void project_t(Ctx& c, int spin, int ik, const T* y, int64_t ldy, int ncol) {
+  ProfScope ps(c, PK_PROJECT);
+  launch_project<T>(c, y, ncol, ldy, (const T*)c.d_cscv[ik], c.d_coup[spin], (T*)c.d_P, (T*)c.d_Q, c.stream);
+}
+
+// Y (already holding the local part) += alpha Phi Q.
+template <typename T>
+void scatter_t(Ctx& c, int ik, T* Y, int64_t ldy, int ncol, double alpha) {
+  ProfScope ps(c, PK_SCATTER);
+  launch_nl_scatter<T>(c, ik, Y, ldy, ncol, (const T*)c.d_Q, alpha, c.stream);
+}
+
 template <typename T>
 void apply_h_t(Ctx& c, int spin, int ik, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncol) {
-  if (c.nproj > 0) {
-    ProfScope ps(c, PK_PROJECT);
-    launch_project<T>(c, X, ncol, ldx, (const T*)c.d_cscv[ik], c.d_coup[spin], (T*)c.d_P, (T*)c.d_Q, c.stream);
-  }
+  if (c.nproj > 0) project_t<T>(c, spin, ik, X, ldx, ncol);
   {
     ProfScope ps(c, PK_STENCIL);
     launch_stencil<T>(c, ik, X, ldx, nullptr, 0, Y, ldy, ncol, 1.0, 0.0, 0.0, c.stream);
   }
-  if (c.nproj > 0) {
-    ProfScope ps(c, PK_SCATTER);
-    launch_nl_scatter<T>(c, ik, Y, ldy, ncol, (const T*)c.d_Q, 1.0, c.stream);
-  }
+  if (c.nproj > 0) scatter_t<T>(c, ik, Y, ldy, ncol, 1.0);
 }
 
-// One Chebyshev step: out = alpha (H y - c y) - beta yprev
+// One Chebyshev step: out = alpha (H y - c y) - beta yprev.
 template <typename T>
 void cheb_step_t(Ctx& c, int spin, int ik, const T* y, int64_t ldy, const T* yprev, int64_t ldp, T* out,
                  int64_t ldo, int ncol, double alpha, double cc, double beta) {
-  if (c.nproj > 0) {
-    ProfScope ps(c, PK_PROJECT);
-    launch_project<T>(c, y, ncol, ldy, (const T*)c.d_cscv[ik], c.d_coup[spin], (T*)c.d_P, (T*)c.d_Q, c.stream);
-  }
+  if (c.nproj > 0) project_t<T>(c, spin, ik, y, ldy, ncol);
   {
     ProfScope ps(c, PK_STENCIL);
     launch_stencil<T>(c, ik, y, ldy, yprev, ldp, out, ldo, ncol, alpha, cc, beta, c.stream);
   }
-  if (c.nproj > 0) {
-    ProfScope ps(c, PK_SCATTER);
-    launch_nl_scatter<T>(c, ik, out, ldo, ncol, (const T*)c.d_Q, alpha, c.stream);
-  }
+  if (c.nproj > 0) scatter_t<T>(c, ik, out, ldo, ncol, alpha);
 }
 
-// returns the index of the work block that holds the filtered block
+// Returns the index of the work block that holds the filtered block.
 template <typename T>
 int filter_t(Ctx& c, int spin, int ik, const T* X, int64_t ldx, int ncol, int m, double a, double b, double aL) {
   const double e = (b - a) / 2, cc = (b + a) / 2;

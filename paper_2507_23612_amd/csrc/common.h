@@ -98,6 +98,18 @@ struct Ctx {
   std::vector<int> csr_ptr, csr_col;
   std::vector<int64_t> csr_src;      // csc position of each csr entry
   int coup_size = 0;
+  // Bricks of 64 consecutive grid points.  Brick b has bnj[b] functions,
+  // listed in bj[boff[b] .. boff[b+1]) (padded to a multiple of 4 with -1),
+  // and a dense value tile [slot][64 points].
+  std::vector<int64_t> boff;         // nbrick + 1, in slots
+  std::vector<int> bnj;
+  std::vector<int> bj;
+  std::vector<int64_t> bsrc;         // csc position per (slot, point) or -1
+  int64_t* d_boff = nullptr;
+  int* d_bnj = nullptr;
+  int* d_bj = nullptr;
+  int64_t* d_bsrc = nullptr;
+  std::vector<void*> d_bval;         // per k: [slot][point]
   int nm_count[kMaxNm + 1] = {0};    // projector blocks per function count
   int nm_offset[kMaxNm + 1] = {0};   // offset of each count's list in d_nm_lists
   int* d_nm_lists = nullptr;
@@ -126,6 +138,7 @@ struct Ctx {
   void* d_P = nullptr;               // projections [ns][nproj] (block type)
   void* d_Q = nullptr;               // coupled projections, transposed: [nproj][ns]
   void* d_PY = nullptr;              // projections of the filtered block (for D)
+  void* d_ppart = nullptr;           // projection partial sums [chunk][nproj][ns]
   std::vector<void*> d_PX;           // per (spin,k) projections of X [ns][nproj]
   double* d_part = nullptr;          // split-K partials of the Gram matrices
   int2* d_tiles = nullptr;           // upper-triangular output tiles of the Gram kernels
@@ -214,14 +227,17 @@ template <typename T>
 void launch_stencil(const Ctx& c, int ik, const T* Yin, int64_t ld, const T* Yprev, int64_t ld_prev, T* Yout,
                     int64_t ld_out, int ncol, double alpha, double cshift, double beta, hipStream_t st);
 bool stencil_shape_ok(const Ctx& c, int TX, int TYt, int RY, int tz);
-// nonlocal.hip: Y += alpha * sum_j phi_j Qt[j][s]  (per-point table, state-blocked)
+// nonlocal.hip: Y += alpha * sum_j phi_j Qt[j][s]  (64-point bricks on the
+// matrix cores for real blocks, per-point table for complex blocks)
 template <typename T>
 void launch_nl_scatter(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T* Qt, double alpha, hipStream_t st);
+constexpr int kBrick = 64;
 
-// proj.hip: P = Phi^H Y dV (per block) and Q = C_b P
+// proj.hip: P = Phi^H Y dV (per block, chunked support) and Q = C_b P (transposed)
 template <typename T>
 void launch_project(const Ctx& c, const T* Y, int ncol, int64_t ld, const T* cscv, const double* coup,
                     T* P, T* Q, hipStream_t st);
+int project_max_chunks(const Ctx& c);
 
 // gemm.hip
 size_t gram_partial_elems(int n, int64_t nd);

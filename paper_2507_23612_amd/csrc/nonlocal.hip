@@ -4,9 +4,16 @@
 //
 // (Sec. II.A potential section: V_U psi = sum phi_m' U/2 (delta - 2D) <phi_m|psi>;
 // Sec. II.B: implemented like the nonlocal projectors).  Each point owns its
-// output (no atomics, deterministic): a thread reads the point's list of
-// (function, value) pairs once and applies it to S states, so the per-point
-// table is read once per S states; Q rows are contiguous in s.
+// output (no atomics, deterministic).
+//
+// Real blocks: the grid is cut into bricks of 64 consecutive points; each
+// brick stores the dense tile Phi_b over the functions touching it (padded
+// to a multiple of 4).  A workgroup updates one brick for 64 states as a
+// small GEMM on the matrix cores,
+//   Y_b^T (64 states x 64 pts) += alpha Q^T (64 x nj) Phi_b (nj x 64),
+// so every table value is read once per 64 states.
+// Complex blocks: a thread reads the point's list of (function, value) pairs
+// once and applies it to S states.
 #include "common.h"
 
 namespace hcu {
@@ -41,15 +48,82 @@ __global__ __launch_bounds__(256) void k_nl_scatter(T* __restrict__ Y, int64_t l
     if (s < nh) Yp[(int64_t)s * ld] += alpha * acc[s];
 }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+template <typename T> struct Mf;
+template <> struct Mf<double> {
+  using V = d4;
+  __device__ static inline V mfma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <> struct Mf<float> {
+  using V = f4;
+  __device__ static inline V mfma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+// Workgroup: 4 waves x 16 states = 64 states, one brick of 64 points.
+// Wave w owns states s0 + 16 w .. + 16 and computes
+// D'(16 s x 16 p) += A'(16 s x 4 j) B'(4 j x 16 p) for the brick's 4 point
+// tiles, with A' = alpha Q^T (lane: s = l%16, j = l/16) and
+// B' = Phi (j = l/16, p = l%16); D' starts from Y and is written back.
+template <typename T>
+__global__ __launch_bounds__(256) void k_nl_brick(T* __restrict__ Y, int64_t ld, int ncol,
+                                                  const int64_t* __restrict__ boff, const int* __restrict__ bnj,
+                                                  const int* __restrict__ bj, const T* __restrict__ bval,
+                                                  const T* __restrict__ Qt, int ldq, T alpha, int64_t nd) {
+  using V = typename Mf<T>::V;
+  const int b = blockIdx.y;
+  const int64_t jo = boff[b];
+  const int nj4 = (bnj[b] + 3) & ~3;
+  if (nj4 == 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int s0 = blockIdx.x * 64 + wave * 16;
+  const int sa = s0 + (lane & 15);
+  const bool sa_ok = sa < ncol;
+  const int64_t p0 = (int64_t)b * kBrick;
+  const T* __restrict__ vb = bval + jo * kBrick;
+  V acc[4];
+  for (int pt = 0; pt < 4; ++pt)
+    for (int q = 0; q < 4; ++q) {
+      const int s = s0 + Mf<T>::row(lane, q);
+      const int64_t p = p0 + pt * 16 + (lane & 15);
+      acc[pt][q] = (s < ncol && p < nd) ? Y[(int64_t)s * ld + p] : T(0);
+    }
+  for (int jj = 0; jj < nj4; jj += 4) {
+    const int jl = jj + (lane >> 4);
+    const int jg = bj[jo + jl];
+    const T a = (sa_ok && jg >= 0) ? alpha * Qt[(int64_t)jg * ldq + sa] : T(0);
+    for (int pt = 0; pt < 4; ++pt) {
+      const T bb = vb[(int64_t)jl * kBrick + pt * 16 + (lane & 15)];
+      acc[pt] = Mf<T>::mfma(a, bb, acc[pt]);
+    }
+  }
+  for (int pt = 0; pt < 4; ++pt)
+    for (int q = 0; q < 4; ++q) {
+      const int s = s0 + Mf<T>::row(lane, q);
+      const int64_t p = p0 + pt * 16 + (lane & 15);
+      if (s < ncol && p < nd) Y[(int64_t)s * ld + p] = acc[pt][q];
+    }
+}
+
 template <typename T>
 void launch_nl_scatter(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T* Qt, double alpha,
                        hipStream_t st) {
   if (c.nproj == 0) return;
-  constexpr int S = sizeof(T) > 8 ? 8 : 16;
+  if constexpr (sizeof(T) == sizeof(typename real_of<T>::type)) {
+    const int nbrick = (int)c.boff.size() - 1;
+    dim3 grid((ncol + 63) / 64, nbrick);
+    k_nl_brick<T><<<grid, 256, 0, st>>>(Y, ld, ncol, c.d_boff, c.d_bnj, c.d_bj, (const T*)c.d_bval[ik], Qt, c.p.ns,
+                                       (T)alpha, c.nd);
+    return;
+  }
+  constexpr int S = 8;
   dim3 grid((ncol + S - 1) / S, (unsigned)((c.nd + 255) / 256));
   k_nl_scatter<T, S><<<grid, 256, 0, st>>>(Y, ld, ncol, c.d_csr_ptr, c.d_csr_col, (const T*)c.d_csrv[ik], Qt,
                                             c.p.ns, (typename real_of<T>::type)alpha, c.nd);
 }
+
 
 template void launch_nl_scatter<double>(const Ctx&, int, double*, int64_t, int, const double*, double, hipStream_t);
 template void launch_nl_scatter<float>(const Ctx&, int, float*, int64_t, int, const float*, double, hipStream_t);

@@ -6,9 +6,11 @@
 //   Q[j0+m][s] = sum_m' C_b[m][m'] P[s][j0+m']     (Q stored transposed for the scatter)
 //
 // with C_b = diag(gamma) for the KB channels and C_b = U (1/2 - D) for the
-// Hubbard manifold (Eq. DerED).  A workgroup owns one block and S states: it
-// sweeps the block's sorted support (x-runs are contiguous), holds the NM x S
-// partial sums per thread and reduces them across the workgroup once.
+// Hubbard manifold (Eq. DerED).  A workgroup owns one block, S states and one
+// 4096-point chunk of the block's sorted support (x-runs are contiguous): it
+// holds the NM x S partial sums per thread, reduces them across the
+// workgroup and writes them per chunk; a second kernel sums the chunks in a
+// fixed order (deterministic) and applies the coupling.
 #include "common.h"
 
 #include <algorithm>
@@ -22,15 +24,22 @@ __device__ inline cplx<R> shfl_xor_t(cplx<R> v, int m) {
   return cplx<R>(__shfl_xor(v.re, m, 64), __shfl_xor(v.im, m, 64));
 }
 
+constexpr int kChunk = 4096;   // support points per workgroup
+
+// Stage 1: partial sums over one chunk of one block's support for S states,
+// written (unscaled) to part[chunk][j][s].
 template <typename T, int NM, int S>
 __global__ __launch_bounds__(256) void k_project(const T* __restrict__ Y, int64_t ld, int ncol,
                                                  const BlockDesc* __restrict__ blocks,
                                                  const int* __restrict__ blist, const int* __restrict__ supp,
-                                                 const T* __restrict__ cscv, const double* __restrict__ coup,
-                                                 T* __restrict__ P, T* __restrict__ Q, int nproj, int ldq,
-                                                 double dv) {
+                                                 const T* __restrict__ cscv, T* __restrict__ part, int nproj,
+                                                 int ldp) {
   const BlockDesc& b = blocks[blist[blockIdx.x]];
   const int s0 = blockIdx.y * S;
+  const int chunk = blockIdx.z;
+  const int q0 = chunk * kChunk;
+  if (q0 >= b.nsupp) return;
+  const int q1 = min(b.nsupp, q0 + kChunk);
   const int ns_here = min(S, ncol - s0);
   T acc[NM][S];
   for (int m = 0; m < NM; ++m)
@@ -39,7 +48,7 @@ __global__ __launch_bounds__(256) void k_project(const T* __restrict__ Y, int64_
   const int* __restrict__ sp = supp + b.supp_off;
   const T* __restrict__ v = cscv + b.val_off;
   const T* __restrict__ Ys = Y + (int64_t)s0 * ld;
-  for (int q = threadIdx.x; q < nsupp; q += blockDim.x) {
+  for (int q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
     const int idx = sp[q];
     T phi[NM];
     for (int m = 0; m < NM; ++m) phi[m] = conj_(v[(int64_t)m * nsupp + q]);
@@ -60,9 +69,7 @@ __global__ __launch_bounds__(256) void k_project(const T* __restrict__ Y, int64_
   // wave reduction, then across the (up to 4) waves of the workgroup
   // raw LDS storage (T may have a constructor)
   __shared__ __attribute__((aligned(16))) unsigned char red_raw[4 * NM * S * sizeof(T)];
-  __shared__ __attribute__((aligned(16))) unsigned char pbuf_raw[NM * S * sizeof(T)];
   T(*red)[NM * S] = reinterpret_cast<T(*)[NM * S]>(red_raw);
-  T* pbuf = reinterpret_cast<T*>(pbuf_raw);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int m = 0; m < NM; ++m)
     for (int s = 0; s < S; ++s) {
@@ -72,30 +79,54 @@ __global__ __launch_bounds__(256) void k_project(const T* __restrict__ Y, int64_
     }
   __syncthreads();
   const int nw = (blockDim.x + 63) / 64;
-  for (int t = threadIdx.x; t < NM * S; t += blockDim.x) {
-    T x = red[0][t];
-    for (int w = 1; w < nw; ++w) x += red[w][t];
-    pbuf[t] = (typename real_of<T>::type)dv * x;
-  }
-  __syncthreads();
-  const double* cb = coup + b.coup_off;
+  T* __restrict__ out = part + (int64_t)chunk * nproj * ldp;
   for (int t = threadIdx.x; t < NM * S; t += blockDim.x) {
     const int m = t / S, s = t % S;
     if (s >= ns_here) continue;
+    T x = red[0][t];
+    for (int w = 1; w < nw; ++w) x += red[w][t];
+    out[(int64_t)(b.j0 + m) * ldp + s0 + s] = x;
+  }
+}
+
+// Stage 2: P[s][j] = dV * sum over the block's chunks (fixed order);
+// Q[j][s] = sum_m' C_b[m][m'] P[s][j0+m'].  One thread per (block, state).
+template <typename T>
+__global__ void k_project_finish(const T* __restrict__ part, const BlockDesc* __restrict__ blocks, int ncol,
+                                 const double* __restrict__ coup, T* __restrict__ P, T* __restrict__ Q, int nproj,
+                                 int ldp, double dv) {
+  const BlockDesc& b = blocks[blockIdx.y];
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ncol) return;
+  const int nch = (b.nsupp + kChunk - 1) / kChunk;
+  using R = typename real_of<T>::type;
+  T pv[kMaxNm];
+  for (int m = 0; m < b.nm; ++m) {
+    T x = T(0);
+    for (int ch = 0; ch < nch; ++ch) x += part[(int64_t)ch * nproj * ldp + (int64_t)(b.j0 + m) * ldp + s];
+    pv[m] = (R)dv * x;
+    P[(int64_t)s * nproj + b.j0 + m] = pv[m];
+  }
+  const double* cb = coup + b.coup_off;
+  for (int m = 0; m < b.nm; ++m) {
     T qv = T(0);
-    for (int mp = 0; mp < NM; ++mp) qv += (typename real_of<T>::type)cb[m * NM + mp] * pbuf[mp * S + s];
-    P[(int64_t)(s0 + s) * nproj + b.j0 + m] = pbuf[t];
-    Q[(int64_t)(b.j0 + m) * ldq + s0 + s] = qv;
+    for (int mp = 0; mp < b.nm; ++mp) qv += (R)cb[m * b.nm + mp] * pv[mp];
+    Q[(int64_t)(b.j0 + m) * ldp + s] = qv;
   }
 }
 
 template <typename T, int NM>
-static void launch_nm(const Ctx& c, const T* Y, int ncol, int64_t ld, const T* cscv, const double* coup, T* P,
-                      T* Q, const int* d_list, int nblk, hipStream_t st) {
+static void launch_nm(const Ctx& c, const T* Y, int ncol, int64_t ld, const T* cscv, T* part, const int* d_list,
+                      int nblk, int maxch, hipStream_t st) {
   constexpr int S = (sizeof(T) > 8 || NM > 5) ? 4 : 8;
-  dim3 grid(nblk, (ncol + S - 1) / S);
-  k_project<T, NM, S><<<grid, 256, 0, st>>>(Y, ld, ncol, c.d_blocks, d_list, c.d_supp, cscv, coup, P, Q, c.nproj,
-                                            c.p.ns, c.dv);
+  dim3 grid(nblk, (ncol + S - 1) / S, maxch);
+  k_project<T, NM, S><<<grid, 256, 0, st>>>(Y, ld, ncol, c.d_blocks, d_list, c.d_supp, cscv, part, c.nproj, c.p.ns);
+}
+
+int project_max_chunks(const Ctx& c) {
+  int mx = 1;
+  for (const BlockDesc& b : c.blocks) mx = std::max(mx, (b.nsupp + kChunk - 1) / kChunk);
+  return mx;
 }
 
 // Blocks are grouped by their function count; the per-count block lists live
@@ -103,21 +134,30 @@ static void launch_nm(const Ctx& c, const T* Y, int ncol, int64_t ld, const T* c
 template <typename T>
 void launch_project(const Ctx& c, const T* Y, int ncol, int64_t ld, const T* cscv, const double* coup, T* P,
                     T* Q, hipStream_t st) {
+  T* part = reinterpret_cast<T*>(c.d_ppart);
   for (int nm = 1; nm <= kMaxNm; ++nm) {
     const int nblk = c.nm_count[nm];
     if (nblk == 0) continue;
+    int maxch = 1;
+    for (const BlockDesc& b : c.blocks)
+      if (b.nm == nm) maxch = std::max(maxch, (b.nsupp + kChunk - 1) / kChunk);
     const int* d_list = c.d_nm_lists + c.nm_offset[nm];
     switch (nm) {
-      case 1: launch_nm<T, 1>(c, Y, ncol, ld, cscv, coup, P, Q, d_list, nblk, st); break;
-      case 2: launch_nm<T, 2>(c, Y, ncol, ld, cscv, coup, P, Q, d_list, nblk, st); break;
-      case 3: launch_nm<T, 3>(c, Y, ncol, ld, cscv, coup, P, Q, d_list, nblk, st); break;
-      case 4: launch_nm<T, 4>(c, Y, ncol, ld, cscv, coup, P, Q, d_list, nblk, st); break;
-      case 5: launch_nm<T, 5>(c, Y, ncol, ld, cscv, coup, P, Q, d_list, nblk, st); break;
-      case 6: launch_nm<T, 6>(c, Y, ncol, ld, cscv, coup, P, Q, d_list, nblk, st); break;
-      case 7: launch_nm<T, 7>(c, Y, ncol, ld, cscv, coup, P, Q, d_list, nblk, st); break;
-      case 8: launch_nm<T, 8>(c, Y, ncol, ld, cscv, coup, P, Q, d_list, nblk, st); break;
-      default: launch_nm<T, 9>(c, Y, ncol, ld, cscv, coup, P, Q, d_list, nblk, st); break;
+      case 1: launch_nm<T, 1>(c, Y, ncol, ld, cscv, part, d_list, nblk, maxch, st); break;
+      case 2: launch_nm<T, 2>(c, Y, ncol, ld, cscv, part, d_list, nblk, maxch, st); break;
+      case 3: launch_nm<T, 3>(c, Y, ncol, ld, cscv, part, d_list, nblk, maxch, st); break;
+      case 4: launch_nm<T, 4>(c, Y, ncol, ld, cscv, part, d_list, nblk, maxch, st); break;
+      case 5: launch_nm<T, 5>(c, Y, ncol, ld, cscv, part, d_list, nblk, maxch, st); break;
+      case 6: launch_nm<T, 6>(c, Y, ncol, ld, cscv, part, d_list, nblk, maxch, st); break;
+      case 7: launch_nm<T, 7>(c, Y, ncol, ld, cscv, part, d_list, nblk, maxch, st); break;
+      case 8: launch_nm<T, 8>(c, Y, ncol, ld, cscv, part, d_list, nblk, maxch, st); break;
+      default: launch_nm<T, 9>(c, Y, ncol, ld, cscv, part, d_list, nblk, maxch, st); break;
     }
+  }
+  const int nb = (int)c.blocks.size();
+  if (nb > 0) {
+    dim3 grid((ncol + 63) / 64, nb);
+    k_project_finish<T><<<grid, 64, 0, st>>>(part, c.d_blocks, ncol, coup, P, Q, c.nproj, c.p.ns, c.dv);
   }
 }
 

@@ -188,6 +188,7 @@ hcu_status build_structure(Ctx& c) {
         c.csr_col[e] = b.j0 + m;
         c.csr_src[e] = b.val_off + (int64_t)m * b.nsupp + q;
       }
+  // (the per-point rows are sorted below)
   // within a row, order by column (blocks were visited in order, m inner to
   // the block, but all m of one block precede the next block: already sorted
   // except that rows interleave m-major fills of one block; sort to be safe)
@@ -198,6 +199,36 @@ hcu_status build_structure(Ctx& c) {
     for (int t = a; t < e; ++t) row.push_back({c.csr_col[t], c.csr_src[t]});
     std::sort(row.begin(), row.end());
     for (int t = a; t < e; ++t) { c.csr_col[t] = row[t - a].first; c.csr_src[t] = row[t - a].second; }
+  }
+  // bricks of 64 consecutive points: the functions touching each brick,
+  // padded to a multiple of 4 (the MFMA depth)
+  const int nbrick = (c.nd + kBrick - 1) / kBrick;
+  c.boff.assign(nbrick + 1, 0);
+  c.bnj.assign(nbrick, 0);
+  c.bj.clear();
+  std::vector<int> js;
+  for (int b = 0; b < nbrick; ++b) {
+    const int p0 = b * kBrick, p1 = std::min(c.nd, p0 + kBrick);
+    js.clear();
+    for (int t = c.csr_ptr[p0]; t < c.csr_ptr[p1]; ++t) js.push_back(c.csr_col[t]);
+    std::sort(js.begin(), js.end());
+    js.erase(std::unique(js.begin(), js.end()), js.end());
+    const int nj = (int)js.size();
+    const int njp = (nj + 3) / 4 * 4;
+    c.bnj[b] = nj;
+    c.boff[b + 1] = c.boff[b] + njp;
+    for (int t = 0; t < njp; ++t) c.bj.push_back(t < nj ? js[t] : -1);
+  }
+  c.bsrc.assign((size_t)c.boff[nbrick] * kBrick, -1);
+  for (int b = 0; b < nbrick; ++b) {
+    const int* bjb = c.bj.data() + c.boff[b];
+    const int nj = c.bnj[b];
+    const int p0 = b * kBrick, p1 = std::min(c.nd, p0 + kBrick);
+    for (int p = p0; p < p1; ++p)
+      for (int t = c.csr_ptr[p]; t < c.csr_ptr[p + 1]; ++t) {
+        const int jl = (int)(std::lower_bound(bjb, bjb + nj, c.csr_col[t]) - bjb);
+        c.bsrc[(c.boff[b] + jl) * kBrick + (p - p0)] = c.csr_src[t];
+      }
   }
   return HCU_OK;
 }
@@ -419,7 +450,7 @@ __global__ void k_lowdin(const BlockDesc* blocks, const int* hub_blocks, T* val,
 template <typename T>
 __global__ void k_gather_csr(const T* csc, const int64_t* src, T* csr, int64_t nnz) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < nnz) csr[e] = csc[src[e]];
+  if (e < nnz) csr[e] = src[e] >= 0 ? csc[src[e]] : T(0);
 }
 
 template <typename T>
@@ -451,6 +482,11 @@ static hcu_status tables_for(Ctx& c) {
       k_gather_csr<T><<<(unsigned)((nnz + 255) / 256), 256, 0, st>>>(cscv, c.d_csr_src, (T*)c.d_csrv[ik], nnz);
       HCU_HIP(hipGetLastError());
     }
+    const int64_t nbv = (int64_t)c.bsrc.size();
+    if (nbv > 0) {
+      k_gather_csr<T><<<(unsigned)((nbv + 255) / 256), 256, 0, st>>>(cscv, c.d_bsrc, (T*)c.d_bval[ik], nbv);
+      HCU_HIP(hipGetLastError());
+    }
   }
   HCU_HIP(hipStreamSynchronize(st));   // hub_blocks (host) must outlive its copy
   return HCU_OK;
@@ -480,6 +516,13 @@ hcu_status device_tables(Ctx& c) {
   }
   if (!c.blocks.empty())
     HCU_HIP(hipMemcpyAsync(c.d_blocks, c.blocks.data(), c.blocks.size() * sizeof(BlockDesc), hipMemcpyHostToDevice, st));
+  auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+  };
+  HCU_HIP(up(c.d_boff, c.boff.data(), c.boff.size() * sizeof(int64_t)));
+  HCU_HIP(up(c.d_bnj, c.bnj.data(), c.bnj.size() * sizeof(int)));
+  HCU_HIP(up(c.d_bj, c.bj.data(), c.bj.size() * sizeof(int)));
+  HCU_HIP(up(c.d_bsrc, c.bsrc.data(), c.bsrc.size() * sizeof(int64_t)));
   hcu_status s;
   if (c.any_complex) s = c.mixed ? tables_for<cplx<float>>(c) : tables_for<cplx<double>>(c);
   else s = c.mixed ? tables_for<float>(c) : tables_for<double>(c);

@@ -250,3 +250,48 @@ def test_gram_and_rotate_match_numpy(ns):
     Xd = torch.empty((ns, ctx.nd), dtype=torch.float64, device="cuda")
     ctx.rotate(torch.from_numpy(Y).cuda(), Cm, Xd)
     np.testing.assert_allclose(Xd.cpu().numpy(), (Y.T @ Cm).T, atol=1e-12 * np.abs(Y).max() * ns)
+
+
+def test_apply_h_mixed_c1():
+    """Mixed mode: FP32 blocks and tables (FP32 stencil, FP32 MFMA scatter)
+    against the FP64 oracle; bound ~ a few FP32 ulps of the largest term."""
+    torch = _torch()
+    cfg = workloads.make_config("c1")
+    ctx = _ctx(cfg, "mixed")
+    D = _rand_D(1, ctx.nhub, 10)
+    ctx.set_hubbard_occupation(D)
+    X = workloads.random_block(ctx.nd, ctx.ns, 17)
+    Xd = torch.from_numpy(X).float().cuda()
+    Yd = torch.empty_like(Xd)
+    ctx.apply_h(Xd, Yd)
+    torch.cuda.synchronize()
+    want = _oracle_H(cfg, D[0]).apply(X.astype(np.float32).astype(np.float64))
+    err = np.max(np.abs(Yd.cpu().numpy() - want)) / np.max(np.abs(want))
+    print(f"[gpu] apply_h mixed c1 rel err {err:.2e}", flush=True)
+    assert err < 2e-6
+
+
+def test_scf_mixed_c1_energy_error():
+    """Mixed-precision SCF on the 6-atom cell: free energy within 1e-5 Ha/atom
+    of the FP64 oracle (the stated target), occupied eigenvalues within 1e-5 Ha."""
+    torch = _torch()
+    from oracle import scf as oscf
+    from paper_2507_23612_amd import hcu
+    cfg = workloads.make_config("c1")
+    ctx = _ctx(cfg, "mixed")
+    ctx.set_hubbard_occupation(hcu.initial_occupation(ctx, cfg))
+    X0, v0 = hcu.start_inputs(ctx, cfg)
+    ctx.set_start(0, 0, X0, v0)
+    rep = ctx.scf(tol_d=1e-5, tol_f=1e-7, verbose=True, raise_on_nonconv=False)
+    ref = oscf.scf(cfg)
+    natom = len(cfg["atom_species"])
+    e = ctx.get_energies()
+    dF = abs(e["F"] - ref["F"]) / natom
+    lam = ctx.get_eigenvalues()[0, 0]
+    nocc = int(cfg["nelec"] / 2)
+    dl = np.max(np.abs(lam[:nocc] - ref["eigs"][0, 0, :nocc]))
+    dEU = abs(e["E_U"] - ref["E_U"])
+    print(f"[gpu] mixed c1: iters {rep['iterations']} conv {rep['converged']} |dF|/atom {dF:.2e} "
+          f"max|dlam| {dl:.2e} |dE_U| {dEU:.2e}", flush=True)
+    assert dF < 1e-5
+    assert dl < 1e-5
