@@ -577,7 +577,7 @@ hcu_status autotune_t(Ctx& c, hcu_tuning* best) {
   T* Y = (T*)c.d_W[0];
   std::vector<hcu_tuning> cands;
   const int txs[3] = {n1 <= 128 ? n1 : 64, 64, 32};
-  for (int RY : {4, 2})
+  for (int RY : {4, 2, 1})
     for (int ti = 0; ti < 3; ++ti) {
       const int TX = txs[ti];
       if (TX > n1 || (ti > 0 && TX == txs[0])) continue;

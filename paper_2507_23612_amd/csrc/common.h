@@ -45,6 +45,20 @@ template <typename T> __host__ __device__ inline T make_scalar(double re, double
 template <> __host__ __device__ inline cplx<double> make_scalar<cplx<double>>(double re, double im) { return {re, im}; }
 template <> __host__ __device__ inline cplx<float> make_scalar<cplx<float>>(double re, double im) { return {float(re), float(im)}; }
 
+// ---------------------------------------------------------------- XCD-aware order
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  xcd_linear() maps the hardware order to a logical order in which
+// each XCD receives a contiguous range of logical indices, so neighbouring
+// logical workgroups (that share halo rows or table tiles) share an L2.
+constexpr int kNumXcd = 8;
+__device__ inline unsigned xcd_linear() {
+  const unsigned nwg = gridDim.x * gridDim.y * gridDim.z;
+  const unsigned w = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const unsigned q = nwg / kNumXcd, r = nwg % kNumXcd;
+  const unsigned x = w % kNumXcd, i = w / kNumXcd;
+  return x * q + (x < r ? x : r) + i;
+}
+
 // ---------------------------------------------------------------- context
 struct BlockDesc {            // one projector block: the KB channels or the Hubbard manifold of one atom
   int atom;

@@ -73,12 +73,16 @@ __global__ __launch_bounds__(256) void k_nl_brick(T* __restrict__ Y, int64_t ld,
                                                   const int* __restrict__ bj, const T* __restrict__ bval,
                                                   const T* __restrict__ Qt, int ldq, T alpha, int64_t nd) {
   using V = typename Mf<T>::V;
-  const int b = blockIdx.y;
+  // logical order: state tile fastest, then brick; XCD-contiguous so the
+  // state tiles of a brick share its table tile in one L2
+  const unsigned lw = xcd_linear();
+  const int b = lw / gridDim.x;
+  const int st_ = lw % gridDim.x;
   const int64_t jo = boff[b];
   const int nj4 = (bnj[b] + 3) & ~3;
   if (nj4 == 0) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int s0 = blockIdx.x * 64 + wave * 16;
+  const int s0 = st_ * 64 + wave * 16;
   const int sa = s0 + (lane & 15);
   const bool sa_ok = sa < ncol;
   const int64_t p0 = (int64_t)b * kBrick;

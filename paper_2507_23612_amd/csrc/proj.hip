@@ -34,9 +34,14 @@ __global__ __launch_bounds__(256) void k_project(const T* __restrict__ Y, int64_
                                                  const int* __restrict__ blist, const int* __restrict__ supp,
                                                  const T* __restrict__ cscv, T* __restrict__ part, int nproj,
                                                  int ldp) {
-  const BlockDesc& b = blocks[blist[blockIdx.x]];
-  const int s0 = blockIdx.y * S;
-  const int chunk = blockIdx.z;
+  // logical order: state tile fastest, then block, then chunk; XCD-contiguous
+  // so the state tiles reading one support chunk share its values in one L2
+  const unsigned lw = xcd_linear();
+  const int stile = lw % gridDim.y;
+  const int bi = (lw / gridDim.y) % gridDim.x;
+  const int chunk = lw / (gridDim.x * gridDim.y);
+  const BlockDesc& b = blocks[blist[bi]];
+  const int s0 = stile * S;
   const int q0 = chunk * kChunk;
   if (q0 >= b.nsupp) return;
   const int q1 = min(b.nsupp, q0 + kChunk);

@@ -75,11 +75,15 @@ __global__ __launch_bounds__(512) void k_stencil(const T* __restrict__ Yin, cons
   T* const buf1 = buf0 + SW * SH;
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = ty * TX + tx, nthr = TX * TYt;
-  const int bx = blockIdx.x % a.tiles_x, by = blockIdx.x / a.tiles_x;
+  // logical order: tile fastest, then z chunk, then state; XCD-contiguous
+  const unsigned lw = xcd_linear();
+  const int tile = lw % gridDim.x;
+  const int zc = (lw / gridDim.x) % gridDim.y;
+  const int64_t s = lw / (gridDim.x * gridDim.y);
+  const int bx = tile % a.tiles_x, by = tile / a.tiles_x;
   const int x0 = bx * TX, y0 = by * TY;
-  const int zbeg = blockIdx.y * a.tz;
+  const int zbeg = zc * a.tz;
   const int zend = min(zbeg + a.tz, a.n3);
-  const int64_t s = blockIdx.z;
   const T* __restrict__ Ys = Yin + s * a.ld;
   const int n1 = a.n1, n2 = a.n2, n3 = a.n3;
   const int64_t plane = (int64_t)n1 * n2;
@@ -209,7 +213,7 @@ struct StencilShape { int TX, TYt, RY, tz; };
 static bool shape_ok(const Ctx& c, const StencilShape& sh, int R) {
   const int n1 = c.p.n[0], n2 = c.p.n[1];
   if (sh.TX < 1 || sh.TX > n1 || sh.TYt < 1 || sh.TX * sh.TYt > 512) return false;
-  if (sh.RY != 2 && sh.RY != 4) return false;
+  if (sh.RY != 1 && sh.RY != 2 && sh.RY != 4) return false;
   const int TY = sh.TYt * sh.RY;
   if (TY > n2) return false;
   const int nthr = sh.TX * sh.TYt;
@@ -246,8 +250,10 @@ static void launch_r(int RY, const KArgs<RT>& a, dim3 grid, dim3 block, size_t l
                      T* Yout, const RT* V, hipStream_t st) {
   if (RY == 4)
     k_stencil<T, RT, R, 4><<<grid, block, lds, st>>>(Yin, Yprev, Yout, V, a);
-  else
+  else if (RY == 2)
     k_stencil<T, RT, R, 2><<<grid, block, lds, st>>>(Yin, Yprev, Yout, V, a);
+  else
+    k_stencil<T, RT, R, 1><<<grid, block, lds, st>>>(Yin, Yprev, Yout, V, a);
 }
 
 template <typename T>
