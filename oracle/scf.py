@@ -174,11 +174,15 @@ class Pulay:
 
 # ---------------------------------------------------------------- SCF
 def initial_occupation(cfg):
+    """Diagonal isolated-atom guess (Sec. II.B); complex Hermitian storage
+    when any k-point is not Gamma (D is then complex in general)."""
     hub = hubbard_atoms(cfg)
+    cplx = bool(np.any(np.asarray(cfg["kpts"]) != 0))
     D = []
     for s in range(cfg["nspin"]):
         diag = workloads.initial_occupation_diag(cfg, s)
-        D.append([g * np.eye(2 * cfg["species"][cfg["atom_species"][ia]]["hub_l"] + 1)
+        D.append([g * np.eye(2 * cfg["species"][cfg["atom_species"][ia]]["hub_l"] + 1,
+                             dtype=complex if cplx else float)
                   for g, ia in zip(diag, hub)])
     return D
 
