@@ -73,6 +73,57 @@ def cpu_baseline(cfg, nstates=8, degree=16):
                       f"{dt:.1f} s on host cores"}
 
 
+def bench_batch(args):
+    """Sixteen independent cells (4 each of 6, 12, 24 and 48 atoms), FP64,
+    degree 16: a step is one ChFSI pass (filter + Rayleigh-Ritz) on every
+    cell.  Timed batched (one persistent stencil launch per Chebyshev step
+    over all 16 blocks) and sequential (each cell's own launches)."""
+    import torch
+    import workloads
+    from paper_2507_23612_amd import hcu
+    cells = workloads.batch_cells()
+    ctxs = []
+    for cfg in cells:
+        ctx = hcu.HcuContext(cfg, "fp64")
+        ctx.set_hubbard_occupation(hcu.initial_occupation(ctx, cfg))
+        X0, v0 = hcu.start_inputs(ctx, cfg)
+        ctx.set_start(0, 0, X0, v0)
+        ctx.lanczos_bounds()
+        ctxs.append(ctx)
+    work = sum(int(np.prod(c["n"])) * int(c["ns"]) * (int(c["degree"]) + 1) for c in cells)
+    b = hcu.HcuBatch(ctxs)
+    for _ in range(args.warmup):
+        b.chfsi_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.chfsi_pass()
+    torch.cuda.synchronize()
+    dt_b = (time.perf_counter() - t0) / args.steps
+    for _ in range(args.warmup):
+        for ctx in ctxs:
+            ctx.chfsi_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for ctx in ctxs:
+            ctx.chfsi_pass()
+    torch.cuda.synchronize()
+    dt_s = (time.perf_counter() - t0) / args.steps
+    b.close()
+    for ctx in ctxs:
+        ctx.close()
+    return {"metric": "ChFSI H·X Gpts·states/s, 16 independent cells batched", "value": round(work / dt_b / 1e9, 3),
+            "unit": "Gpts·states/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(dt_b * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "batch16: 4 cells each of 6 atoms (36x36x24, 32 states), 12 atoms (36x36x48, 64), "
+                                   "24 atoms (72x72x24, 128), 48 atoms (72x72x96, 256); degree 16, Gamma",
+                       "precision": "fp64"},
+            "sequential": {"ms_per_step": round(dt_s * 1e3, 3), "value": round(work / dt_s / 1e9, 3)},
+            "batched_over_sequential": round(dt_s / dt_b, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +137,9 @@ def main():
                     help="run one plain 1 GiB device copy first (calibrates hardware byte counters)")
     ap.add_argument("--tile", default=None,
                     help="stencil tile shape TX,TYt,RY,TZ (skips the autotuner, e.g. for profiling)")
+    ap.add_argument("--batch", action="store_true",
+                    help="measure the 16-cell batched workload instead (one persistent stencil launch per "
+                         "Chebyshev step over all cells) against the same cells run one after another")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
@@ -104,6 +158,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.batch:
+        print(json.dumps(bench_batch(args)), flush=True)
+        return
     cfg = workloads.make_config(args.config)
     prec = args.precision or cfg["precision"]
     nd = int(np.prod(cfg["n"]))

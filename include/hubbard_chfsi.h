@@ -300,6 +300,26 @@ hcu_status hcu_get_orbitals(hcu_ctx* ctx, int spin, int ik, void* dst, int on_de
  * for nspin = 2; rho = (2/nspin) sum_k w_k sum_j f_j |x_j|^2. */
 hcu_status hcu_get_density(hcu_ctx* ctx, double* rho);
 
+/* ---------------------------------------------------------------- batches
+ * Independent problems (cells of different size, each with its spins and
+ * k-points) advanced together: in every Chebyshev step the stencil of every
+ * (cell, spin, k) block runs as ONE persistent launch that drains a work list
+ * of (block, tile, z-chunk, state) items; projections, scatters and the
+ * Rayleigh-Ritz steps run per block.  Members must be bound to the same
+ * stream and share the block element type (precision, real/complex), the
+ * filter degree and n0.  A batch does not own its contexts. */
+typedef struct hcu_batch hcu_batch;
+hcu_status hcu_batch_create(hcu_ctx* const* ctxs, int n, hcu_batch** out);
+void hcu_batch_destroy(hcu_batch* b);
+const char* hcu_batch_last_error(const hcu_batch* b);
+/* One filter + Rayleigh-Ritz pass on every (member, spin, k) (bounds must be
+ * set, e.g. by hcu_lanczos_bounds). */
+hcu_status hcu_batch_chfsi_pass(hcu_batch* b);
+/* SCF of every member in lockstep (same options; a converged member stops
+ * taking part); reps[i] is member i's report.  HCU_NOT_CONVERGED if any
+ * member reached max_iter. */
+hcu_status hcu_batch_scf(hcu_batch* b, const hcu_scf_opts* opts, hcu_scf_report* reps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,6 +15,11 @@ using namespace hcu;
 
 struct hcu_ctx : public Ctx {};
 
+struct hcu_batch {
+  std::vector<hcu_ctx*> m;
+  std::string err;
+};
+
 namespace {
 
 struct Bump {
@@ -29,6 +34,8 @@ struct Bump {
 };
 
 size_t esize(const Ctx& c) { return (c.mixed ? 4 : 8) * (c.any_complex ? 2 : 1); }
+
+constexpr size_t kBatchJobBytes = 256 * 1024;   // job table of a batched stencil launch
 
 size_t layout(Ctx& c, char* base) {
   Bump b{base};
@@ -69,10 +76,18 @@ size_t layout(Ctx& c, char* base) {
     b.take(c.d_v0[i], es * (size_t)c.nd);
     b.take(c.d_PX[i], es * (size_t)ns * c.nproj);
   }
-  for (int w = 0; w < 3; ++w) b.take(c.d_W[w], es * (size_t)c.nd * ns);
-  b.take(c.d_P, es * (size_t)ns * c.nproj);
-  b.take(c.d_Q, es * (size_t)ns * c.nproj);
-  b.take(c.d_PY, es * (size_t)ns * c.nproj);
+  c.d_W.assign(3 * nsk, nullptr);
+  c.d_P.assign(nsk, nullptr);
+  c.d_Q.assign(nsk, nullptr);
+  c.d_PY.assign(nsk, nullptr);
+  for (int i = 0; i < nsk; ++i) {
+    for (int w = 0; w < 3; ++w) b.take(c.d_W[3 * i + w], es * (size_t)c.nd * ns);
+    b.take(c.d_P[i], es * (size_t)ns * c.nproj);
+    b.take(c.d_Q[i], es * (size_t)ns * c.nproj);
+    b.take(c.d_PY[i], es * (size_t)ns * c.nproj);
+  }
+  b.take(c.d_jobs, kBatchJobBytes);
+  b.take(c.d_counters, sizeof(unsigned long long) * kNumXcd);
   b.take(c.d_ppart, es * (size_t)ns * c.nproj * project_max_chunks(c));
   c.part_elems = c.any_complex ? gram_partial_elems_c(ns, c.nd) : gram_partial_elems(ns, c.nd);
   b.take(c.d_part, sizeof(double) * c.part_elems);
@@ -213,14 +228,16 @@ hcu_status generalized_eig(Ctx& c, int n, bool cp, double* lam) {
 template <typename T>
 void project_t(Ctx& c, int spin, int ik, const T* y, int64_t ldy, int ncol) {
   ProfScope ps(c, PK_PROJECT);
-  launch_project<T>(c, y, ncol, ldy, (const T*)c.d_cscv[ik], c.d_coup[spin], (T*)c.d_P, (T*)c.d_Q, c.stream);
+  const int sk = sk_index(c, spin, ik);
+  launch_project<T>(c, y, ncol, ldy, (const T*)c.d_cscv[ik], c.d_coup[spin], (T*)c.d_P[sk], (T*)c.d_Q[sk],
+                    c.stream);
 }
 
 // Y (already holding the local part) += alpha Phi Q.
 template <typename T>
-void scatter_t(Ctx& c, int ik, T* Y, int64_t ldy, int ncol, double alpha) {
+void scatter_t(Ctx& c, int spin, int ik, T* Y, int64_t ldy, int ncol, double alpha) {
   ProfScope ps(c, PK_SCATTER);
-  launch_nl_scatter<T>(c, ik, Y, ldy, ncol, (const T*)c.d_Q, alpha, c.stream);
+  launch_nl_scatter<T>(c, ik, Y, ldy, ncol, (const T*)c.d_Q[sk_index(c, spin, ik)], alpha, c.stream);
 }
 
 template <typename T>
@@ -230,7 +247,7 @@ void apply_h_t(Ctx& c, int spin, int ik, const T* X, int64_t ldx, T* Y, int64_t 
     ProfScope ps(c, PK_STENCIL);
     launch_stencil<T>(c, ik, X, ldx, nullptr, 0, Y, ldy, ncol, 1.0, 0.0, 0.0, c.stream);
   }
-  if (c.nproj > 0) scatter_t<T>(c, ik, Y, ldy, ncol, 1.0);
+  if (c.nproj > 0) scatter_t<T>(c, spin, ik, Y, ldy, ncol, 1.0);
 }
 
 // One Chebyshev step: out = alpha (H y - c y) - beta yprev.
@@ -242,7 +259,7 @@ void cheb_step_t(Ctx& c, int spin, int ik, const T* y, int64_t ldy, const T* ypr
     ProfScope ps(c, PK_STENCIL);
     launch_stencil<T>(c, ik, y, ldy, yprev, ldp, out, ldo, ncol, alpha, cc, beta, c.stream);
   }
-  if (c.nproj > 0) scatter_t<T>(c, ik, out, ldo, ncol, alpha);
+  if (c.nproj > 0) scatter_t<T>(c, spin, ik, out, ldo, ncol, alpha);
 }
 
 // Returns the index of the work block that holds the filtered block.
@@ -252,16 +269,17 @@ int filter_t(Ctx& c, int spin, int ik, const T* X, int64_t ldx, int ncol, int m,
   double sigma = e / (aL - cc);
   const double tau = 2.0 / sigma;
   const int64_t nd = c.nd;
-  cheb_step_t<T>(c, spin, ik, X, ldx, nullptr, 0, (T*)c.d_W[0], nd, ncol, sigma / e, cc, 0.0);
+  void** W = &c.d_W[3 * sk_index(c, spin, ik)];
+  cheb_step_t<T>(c, spin, ik, X, ldx, nullptr, 0, (T*)W[0], nd, ncol, sigma / e, cc, 0.0);
   const T* prev = X;
   int64_t ldp = ldx;
   int cur = 0;
   for (int i = 2; i <= m; ++i) {
     const double s2 = 1.0 / (tau - sigma);
     const int out = (cur + 1) % 3;
-    cheb_step_t<T>(c, spin, ik, (const T*)c.d_W[cur], nd, prev, ldp, (T*)c.d_W[out], nd, ncol, 2.0 * s2 / e, cc,
+    cheb_step_t<T>(c, spin, ik, (const T*)W[cur], nd, prev, ldp, (T*)W[out], nd, ncol, 2.0 * s2 / e, cc,
                    sigma * s2);
-    prev = (const T*)c.d_W[cur];
+    prev = (const T*)W[cur];
     ldp = nd;
     cur = out;
     sigma = s2;
@@ -269,25 +287,17 @@ int filter_t(Ctx& c, int spin, int ik, const T* X, int64_t ldx, int ncol, int m,
   return cur;
 }
 
+// Queue Rayleigh-Ritz for (spin, k) block sk: S, Hs from Y and H Y, FP64
+// generalized eigensolve, X = Y C, projections of X; results read by
+// rr_finish after a stream synchronisation.
 template <typename T>
-hcu_status pass_t(Ctx& c, int spin, int ik, double* filter_ms) {
-  const int sk = sk_index(c, spin, ik);
+hcu_status rr_t(Ctx& c, int sk, T* Y, T* HY) {
   const int ns = c.p.ns;
   const int64_t nd = c.nd;
   T* X = (T*)c.d_X[sk];
-  const double a = c.bounds[3 * sk], b = c.bounds[3 * sk + 1], aL = c.bounds[3 * sk + 2];
-  hipEvent_t e0, e1;
-  HCU_HIP(hipEventCreate(&e0));
-  HCU_HIP(hipEventCreate(&e1));
-  HCU_HIP(hipEventRecord(e0, c.stream));
-  const int iy = filter_t<T>(c, spin, ik, X, nd, ns, c.p.degree, a, b, aL);
-  const int ih = (iy + 1) % 3;
-  T* Y = (T*)c.d_W[iy];
-  T* HY = (T*)c.d_W[ih];
-  apply_h_t<T>(c, spin, ik, Y, nd, HY, nd, ns);
-  HCU_HIP(hipEventRecord(e1, c.stream));
   if (c.nproj > 0)
-    HCU_HIP(hipMemcpyAsync(c.d_PY, c.d_P, esize(c) * (size_t)ns * c.nproj, hipMemcpyDeviceToDevice, c.stream));
+    HCU_HIP(hipMemcpyAsync(c.d_PY[sk], c.d_P[sk], esize(c) * (size_t)ns * c.nproj, hipMemcpyDeviceToDevice,
+                           c.stream));
   {
     ProfScope ps(c, PK_GRAM);
     launch_gram2<T>(c, Y, HY, ns, nd, c.d_S, c.d_Hs, c.stream);
@@ -304,28 +314,162 @@ hcu_status pass_t(Ctx& c, int spin, int ik, double* filter_ms) {
     ProfScope ps(c, PK_ROTATE);
     launch_rotate<T>(c, Y, nd, (const T*)c.d_Cb, X, ns, c.stream);
   }
-  if (c.nproj > 0) launch_rotate_proj<T>(c, (const T*)c.d_PY, (const T*)c.d_Cb, (T*)c.d_PX[sk], ns, c.stream);
+  if (c.nproj > 0) launch_rotate_proj<T>(c, (const T*)c.d_PY[sk], (const T*)c.d_Cb, (T*)c.d_PX[sk], ns, c.stream);
   HCU_HIP(hipGetLastError());
-  int info2[2] = {0, 0};
-  HCU_HIP(hipMemcpyAsync(info2, c.d_info, 2 * sizeof(int), hipMemcpyDeviceToHost, c.stream));
-  std::vector<double> lam(ns);
-  HCU_HIP(hipMemcpyAsync(lam.data(), c.d_lam + (size_t)sk * ns, sizeof(double) * ns, hipMemcpyDeviceToHost, c.stream));
-  HCU_HIP(hipStreamSynchronize(c.stream));
-  float ms = 0;
-  hipEventElapsedTime(&ms, e0, e1);
-  if (filter_ms) *filter_ms += ms;
-  prof_resolve(c);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  HCU_HIP(hipMemcpyAsync(c.h_info + 2 * sk, c.d_info, 2 * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+  return HCU_OK;
+}
+
+// After the stream has synchronised: check the eigensolve, update bounds.
+hcu_status rr_finish(Ctx& c, int sk) {
+  const int ns = c.p.ns;
+  const int* info2 = c.h_info + 2 * sk;
   if (info2[0] != 0)
     return fail(c, HCU_NOT_SPD, "Gram matrix of the filtered block not positive definite (potrf info=" +
                                     std::to_string(info2[0]) + ")");
   if (info2[1] != 0)
     return fail(c, HCU_DEVICE, "subspace eigensolver did not converge (info=" + std::to_string(info2[1]) + ")");
+  std::vector<double> lam(ns);
+  hipError_t e = hipMemcpy(lam.data(), c.d_lam + (size_t)sk * ns, sizeof(double) * ns, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(c, HCU_DEVICE, hipGetErrorString(e));
   for (int i = 0; i < ns; ++i)
     if (!std::isfinite(lam[i])) return fail(c, HCU_NAN, "non-finite Ritz value");
   c.bounds[3 * sk] = lam[ns - 1];
   c.bounds[3 * sk + 2] = lam[0];
+  prof_resolve(c);
+  return HCU_OK;
+}
+
+template <typename T>
+hcu_status pass_t(Ctx& c, int spin, int ik, double* filter_ms) {
+  const int sk = sk_index(c, spin, ik);
+  const int ns = c.p.ns;
+  const int64_t nd = c.nd;
+  T* X = (T*)c.d_X[sk];
+  const double a = c.bounds[3 * sk], b = c.bounds[3 * sk + 1], aL = c.bounds[3 * sk + 2];
+  hipEvent_t e0, e1;
+  HCU_HIP(hipEventCreate(&e0));
+  HCU_HIP(hipEventCreate(&e1));
+  HCU_HIP(hipEventRecord(e0, c.stream));
+  const int iy = filter_t<T>(c, spin, ik, X, nd, ns, c.p.degree, a, b, aL);
+  const int ih = (iy + 1) % 3;
+  T* Y = (T*)c.d_W[3 * sk + iy];
+  T* HY = (T*)c.d_W[3 * sk + ih];
+  apply_h_t<T>(c, spin, ik, Y, nd, HY, nd, ns);
+  HCU_HIP(hipEventRecord(e1, c.stream));
+  hcu_status s = rr_t<T>(c, sk, Y, HY);
+  if (s != HCU_OK) return s;
+  HCU_HIP(hipStreamSynchronize(c.stream));
+  float ms = 0;
+  hipEventElapsedTime(&ms, e0, e1);
+  if (filter_ms) *filter_ms += ms;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return rr_finish(c, sk);
+}
+
+// ------------------------------------------------------------------ batches
+struct BProb {
+  Ctx* c;
+  int spin, ik, sk;
+  double e, cc, sigma, tau;
+};
+
+// One filter + Rayleigh-Ritz pass on every problem of a batch in lockstep:
+// per Chebyshev step the projections and scatters run per problem and the
+// stencil of all problems runs as one persistent launch.  All contexts share
+// the stream and the filter degree.
+template <typename T>
+hcu_status batch_pass_t(std::vector<BProb>& probs, Ctx& lead) {
+  hipStream_t st = lead.stream;
+  const int np = (int)probs.size();
+  const int m = lead.p.degree;
+  std::vector<std::vector<unsigned char>> tables;   // host job tables, alive until the final sync
+  std::vector<StencilJob> jobs(np);
+  std::vector<const T*> prev(np);
+  std::vector<int> cur(np, 0);
+  auto launch = [&]() -> hcu_status {
+    tables.emplace_back();
+    ProfScope ps(lead, PK_STENCIL);
+    hcu_status s = launch_stencil_batch<T>(jobs, lead.d_jobs, kBatchJobBytes, lead.d_counters, tables.back(), st);
+    if (s != HCU_OK) return fail(lead, s, "batched stencil launch failed (shapes, job table or device)");
+    return HCU_OK;
+  };
+  for (BProb& q : probs) {
+    Ctx& c = *q.c;
+    const double a = c.bounds[3 * q.sk], b = c.bounds[3 * q.sk + 1], aL = c.bounds[3 * q.sk + 2];
+    q.e = (b - a) / 2;
+    q.cc = (b + a) / 2;
+    q.sigma = q.e / (aL - q.cc);
+    q.tau = 2.0 / q.sigma;
+  }
+  // first step: Y1 = (sigma/e)(H X - c X)
+  for (int i = 0; i < np; ++i) {
+    BProb& q = probs[i];
+    Ctx& c = *q.c;
+    const T* X = (const T*)c.d_X[q.sk];
+    if (c.nproj > 0) project_t<T>(c, q.spin, q.ik, X, c.nd, c.p.ns);
+    jobs[i] = StencilJob{&c, q.ik, X, c.nd, nullptr, 0, c.d_W[3 * q.sk], c.nd, c.p.ns, q.sigma / q.e, q.cc, 0.0};
+    prev[i] = X;
+  }
+  hcu_status s = launch();
+  if (s != HCU_OK) return s;
+  for (int i = 0; i < np; ++i) {
+    BProb& q = probs[i];
+    if (q.c->nproj > 0) scatter_t<T>(*q.c, q.spin, q.ik, (T*)q.c->d_W[3 * q.sk], q.c->nd, q.c->p.ns, q.sigma / q.e);
+  }
+  std::vector<double> alpha(np), beta(np);
+  for (int step = 2; step <= m; ++step) {
+    for (int i = 0; i < np; ++i) {
+      BProb& q = probs[i];
+      Ctx& c = *q.c;
+      const double s2 = 1.0 / (q.tau - q.sigma);
+      alpha[i] = 2.0 * s2 / q.e;
+      beta[i] = q.sigma * s2;
+      const int out = (cur[i] + 1) % 3;
+      const T* y = (const T*)c.d_W[3 * q.sk + cur[i]];
+      if (c.nproj > 0) project_t<T>(c, q.spin, q.ik, y, c.nd, c.p.ns);
+      jobs[i] = StencilJob{&c, q.ik, y, c.nd, prev[i], c.nd, c.d_W[3 * q.sk + out], c.nd, c.p.ns, alpha[i], q.cc,
+                           beta[i]};
+      q.sigma = s2;
+    }
+    s = launch();
+    if (s != HCU_OK) return s;
+    for (int i = 0; i < np; ++i) {
+      BProb& q = probs[i];
+      Ctx& c = *q.c;
+      const int out = (cur[i] + 1) % 3;
+      if (c.nproj > 0) scatter_t<T>(c, q.spin, q.ik, (T*)c.d_W[3 * q.sk + out], c.nd, c.p.ns, alpha[i]);
+      prev[i] = (const T*)c.d_W[3 * q.sk + cur[i]];
+      cur[i] = out;
+    }
+  }
+  // H Y for Rayleigh-Ritz
+  for (int i = 0; i < np; ++i) {
+    BProb& q = probs[i];
+    Ctx& c = *q.c;
+    const T* Y = (const T*)c.d_W[3 * q.sk + cur[i]];
+    if (c.nproj > 0) project_t<T>(c, q.spin, q.ik, Y, c.nd, c.p.ns);
+    jobs[i] = StencilJob{&c, q.ik, Y, c.nd, nullptr, 0, c.d_W[3 * q.sk + (cur[i] + 1) % 3], c.nd, c.p.ns, 1.0, 0.0, 0.0};
+  }
+  s = launch();
+  if (s != HCU_OK) return s;
+  for (int i = 0; i < np; ++i) {
+    BProb& q = probs[i];
+    Ctx& c = *q.c;
+    if (c.nproj > 0) scatter_t<T>(c, q.spin, q.ik, (T*)c.d_W[3 * q.sk + (cur[i] + 1) % 3], c.nd, c.p.ns, 1.0);
+  }
+  // Rayleigh-Ritz per problem
+  for (int i = 0; i < np; ++i) {
+    BProb& q = probs[i];
+    s = rr_t<T>(*q.c, q.sk, (T*)q.c->d_W[3 * q.sk + cur[i]], (T*)q.c->d_W[3 * q.sk + (cur[i] + 1) % 3]);
+    if (s != HCU_OK) return s;
+  }
+  HCU_HIP_CTX(lead, hipStreamSynchronize(st));
+  for (BProb& q : probs) {
+    s = rr_finish(*q.c, q.sk);
+    if (s != HCU_OK) return s;
+  }
   return HCU_OK;
 }
 
@@ -538,7 +682,8 @@ template <typename T>
 hcu_status filter_v(Ctx& c, int spin, int ik, const void* X, void* Y, int ncol, int64_t ld, int m, double a,
                     double b, double aL) {
   const int w = filter_t<T>(c, spin, ik, (const T*)X, ld, ncol, m, a, b, aL);
-  HCU_HIP(hipMemcpy2DAsync(Y, sizeof(T) * ld, c.d_W[w], sizeof(T) * c.nd, sizeof(T) * c.nd, ncol,
+  HCU_HIP(hipMemcpy2DAsync(Y, sizeof(T) * ld, c.d_W[3 * sk_index(c, spin, ik) + w], sizeof(T) * c.nd,
+                           sizeof(T) * c.nd, ncol,
                            hipMemcpyDeviceToDevice, c.stream));
   HCU_HIP(hipGetLastError());
   return HCU_OK;
@@ -574,7 +719,7 @@ hcu_status autotune_t(Ctx& c, hcu_tuning* best) {
   const int ns = c.p.ns;
   const T* X = (const T*)c.d_X[0];
   const T* Yp = (const T*)c.d_W[1];
-  T* Y = (T*)c.d_W[0];
+  T* Y = (T*)c.d_W[0];   // (spin 0, k 0) work blocks
   std::vector<hcu_tuning> cands;
   const int txs[3] = {n1 <= 128 ? n1 : 64, 64, 32};
   for (int RY : {4, 2, 1})
@@ -621,6 +766,43 @@ hcu_status get_orbitals_v(Ctx& c, int sk, void* dst, int on_device) {
   HCU_HIP(hipMemcpyAsync(dst, c.d_X[sk], sizeof(T) * (size_t)c.nd * c.p.ns,
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c.stream));
   HCU_HIP(hipStreamSynchronize(c.stream));
+  return HCU_OK;
+}
+
+// Second half of an SCF iteration (after the passes of every (spin, k)):
+// occupations, D_out, energies, convergence test, Pulay mixing of D.
+hcu_status scf_post(Ctx& c, hcu_scf_step_info* info) {
+  const hcu_scf_opts& o = c.scf_opts;
+  hcu_status s = DISPATCH(c, occupations_t, c);
+  if (s != HCU_OK) return s;
+  double res = 0;
+  for (size_t i = 0; i < c.D_in.size(); ++i) res += (c.D_out[i] - c.D_in[i]) * (c.D_out[i] - c.D_in[i]);
+  res = std::sqrt(res);
+  const int natom = std::max(c.p.natom, 1);
+  const double dF = c.scf_have_old ? std::fabs(c.en.F - c.scf_F_old) / natom : INFINITY;
+  if (o.verbose)
+    std::fprintf(stderr, "[hcu scf] it=%d F=%.12f E_U=%.6e res=%.3e dF=%.3e\n", c.scf_iter, c.en.F, c.en.E_U, res, dF);
+  c.scf_F_old = c.en.F;
+  c.scf_have_old = true;
+  const bool conv = res < o.tol_d && dF < o.tol_f;
+  if (info) {
+    info->iteration = c.scf_iter;
+    info->converged = conv ? 1 : 0;
+    info->F = c.en.F;
+    info->E_U = c.en.E_U;
+    info->residual = res;
+    info->dF = dF;
+  }
+  ++c.scf_iter;
+  if (!conv) {
+    Pulay mix{o.pulay_history, o.pulay_beta, c.mix_x, c.mix_f};
+    std::vector<double> x = d_to_vec(c, c.D_in), xo = d_to_vec(c, c.D_out), f(x.size());
+    for (size_t i = 0; i < x.size(); ++i) f[i] = xo[i] - x[i];
+    std::vector<double> xn = mix.step(x, f);
+    vec_to_d(c, xn, c.D_in);
+    s = upload_coupling(c);
+    if (s != HCU_OK) return s;
+  }
   return HCU_OK;
 }
 
@@ -702,6 +884,8 @@ hcu_status hcu_create(const hcu_problem* p, hcu_ctx** out) {
   int off = 0;
   for (int nm = 0; nm <= kMaxNm; ++nm) { c->nm_offset[nm] = off; off += c->nm_count[nm]; }
   c->D_in.assign((size_t)p->nspin * c->hub_atoms.size() * 25, 0.0);
+  c->h_info_store.assign((size_t)2 * p->nspin * p->nk, 0);
+  c->h_info = c->h_info_store.data();
   c->bounds.assign((size_t)3 * p->nspin * p->nk, 0.0);
   c->ws_bytes = layout(*c, nullptr);
   *out = c;
@@ -918,8 +1102,7 @@ hcu_status hcu_scf_step(hcu_ctx* ctx, hcu_scf_step_info* info) {
   if (s != HCU_OK) return s;
   Ctx& c = *ctx;
   if (!c.scf_ready) return fail(c, HCU_INVALID_ARG, "call hcu_scf_begin first");
-  const hcu_scf_opts& o = c.scf_opts;
-  const int passes = c.scf_iter == 0 ? o.first_passes : 1;
+  const int passes = c.scf_iter == 0 ? c.scf_opts.first_passes : 1;
   for (int sp = 0; sp < c.p.nspin; ++sp)
     for (int k = 0; k < c.p.nk; ++k)
       for (int ps = 0; ps < passes; ++ps) {
@@ -927,37 +1110,7 @@ hcu_status hcu_scf_step(hcu_ctx* ctx, hcu_scf_step_info* info) {
         if (s != HCU_OK) return s;
         c.scf_hx_cols += (double)c.p.ns * (c.p.degree + 1);
       }
-  s = DISPATCH(c, occupations_t, c);
-  if (s != HCU_OK) return s;
-  double res = 0;
-  for (size_t i = 0; i < c.D_in.size(); ++i) res += (c.D_out[i] - c.D_in[i]) * (c.D_out[i] - c.D_in[i]);
-  res = std::sqrt(res);
-  const int natom = std::max(c.p.natom, 1);
-  const double dF = c.scf_have_old ? std::fabs(c.en.F - c.scf_F_old) / natom : INFINITY;
-  if (o.verbose)
-    std::fprintf(stderr, "[hcu scf] it=%d F=%.12f E_U=%.6e res=%.3e dF=%.3e\n", c.scf_iter, c.en.F, c.en.E_U, res, dF);
-  c.scf_F_old = c.en.F;
-  c.scf_have_old = true;
-  const bool conv = res < o.tol_d && dF < o.tol_f;
-  if (info) {
-    info->iteration = c.scf_iter;
-    info->converged = conv ? 1 : 0;
-    info->F = c.en.F;
-    info->E_U = c.en.E_U;
-    info->residual = res;
-    info->dF = dF;
-  }
-  ++c.scf_iter;
-  if (!conv) {
-    Pulay mix{o.pulay_history, o.pulay_beta, c.mix_x, c.mix_f};
-    std::vector<double> x = d_to_vec(c, c.D_in), xo = d_to_vec(c, c.D_out), f(x.size());
-    for (size_t i = 0; i < x.size(); ++i) f[i] = xo[i] - x[i];
-    std::vector<double> xn = mix.step(x, f);
-    vec_to_d(c, xn, c.D_in);
-    s = upload_coupling(c);
-    if (s != HCU_OK) return s;
-  }
-  return HCU_OK;
+  return scf_post(c, info);
 }
 
 hcu_status hcu_scf(hcu_ctx* ctx, const hcu_scf_opts* o, hcu_scf_report* rep) {
@@ -1056,6 +1209,129 @@ hcu_status hcu_get_density(hcu_ctx* ctx, double* rho) {
   if (!rho) return fail(c, HCU_INVALID_ARG, "null rho");
   if (!c.have_results) return fail(c, HCU_INVALID_ARG, "no occupations yet");
   return DISPATCH(c, density_t, c, rho);
+}
+
+}  // extern "C"
+
+// ====================================================================== batches
+namespace {
+hcu_status batch_fail(hcu_batch* b, hcu_status s, const std::string& msg) {
+  b->err = msg;
+  return s;
+}
+
+std::vector<BProb> batch_problems(hcu_batch* b, const std::vector<int>& active) {
+  std::vector<BProb> pr;
+  for (size_t i = 0; i < b->m.size(); ++i) {
+    if (!active[i]) continue;
+    Ctx& c = *b->m[i];
+    for (int s = 0; s < c.p.nspin; ++s)
+      for (int k = 0; k < c.p.nk; ++k) pr.push_back(BProb{&c, s, k, sk_index(c, s, k), 0, 0, 0, 0});
+  }
+  return pr;
+}
+
+hcu_status batch_run_pass(hcu_batch* b, std::vector<BProb>& pr) {
+  if (pr.empty()) return HCU_OK;
+  Ctx& lead = *pr[0].c;
+  hcu_status s = DISPATCH(lead, batch_pass_t, pr, lead);
+  if (s != HCU_OK) {
+    std::string msg = lead.err;
+    for (BProb& q : pr)
+      if (!q.c->err.empty()) msg = q.c->err;
+    return batch_fail(b, s, msg);
+  }
+  return HCU_OK;
+}
+}  // namespace
+
+extern "C" {
+
+hcu_status hcu_batch_create(hcu_ctx* const* ctxs, int n, hcu_batch** out) {
+  if (!ctxs || n < 1 || !out) return HCU_INVALID_ARG;
+  *out = nullptr;
+  hcu_batch* b = new (std::nothrow) hcu_batch();
+  if (!b) return HCU_OOM;
+  *out = b;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return batch_fail(b, HCU_INVALID_ARG, "null context");
+    if (!ctxs[i]->bound) return batch_fail(b, HCU_NOT_BOUND, "every context must be bound");
+    b->m.push_back(ctxs[i]);
+  }
+  const Ctx& c0 = *ctxs[0];
+  for (int i = 1; i < n; ++i) {
+    const Ctx& c = *ctxs[i];
+    if (c.stream != c0.stream) return batch_fail(b, HCU_INVALID_ARG, "contexts must share one stream");
+    if (c.mixed != c0.mixed || c.any_complex != c0.any_complex)
+      return batch_fail(b, HCU_INVALID_ARG, "contexts must share the block element type");
+    if (c.p.degree != c0.p.degree || c.p.n0 != c0.p.n0)
+      return batch_fail(b, HCU_INVALID_ARG, "contexts must share the filter degree and FD order");
+  }
+  return HCU_OK;
+}
+
+void hcu_batch_destroy(hcu_batch* b) { delete b; }
+
+const char* hcu_batch_last_error(const hcu_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+hcu_status hcu_batch_chfsi_pass(hcu_batch* b) {
+  if (!b) return HCU_INVALID_ARG;
+  for (hcu_ctx* c : b->m)
+    for (int sk = 0; sk < c->p.nspin * c->p.nk; ++sk)
+      if (!(c->bounds[3 * sk + 1] > c->bounds[3 * sk]))
+        return batch_fail(b, HCU_INVALID_ARG, "bounds not set (run hcu_lanczos_bounds on every member)");
+  std::vector<int> active(b->m.size(), 1);
+  std::vector<BProb> pr = batch_problems(b, active);
+  return batch_run_pass(b, pr);
+}
+
+hcu_status hcu_batch_scf(hcu_batch* b, const hcu_scf_opts* o, hcu_scf_report* reps) {
+  if (!b || !o || !reps) return HCU_INVALID_ARG;
+  const size_t nm = b->m.size();
+  const auto t0 = std::chrono::steady_clock::now();
+  for (size_t i = 0; i < nm; ++i) {
+    std::memset(&reps[i], 0, sizeof(hcu_scf_report));
+    hcu_status s = hcu_scf_begin(b->m[i], o);
+    if (s != HCU_OK) return batch_fail(b, s, b->m[i]->err);
+  }
+  std::vector<int> active(nm, 1);
+  hcu_status final_status = HCU_OK;
+  for (int it = 0; it < o->max_iter; ++it) {
+    std::vector<BProb> pr = batch_problems(b, active);
+    if (pr.empty()) break;
+    const int passes = it == 0 ? o->first_passes : 1;
+    for (int ps = 0; ps < passes; ++ps) {
+      hcu_status s = batch_run_pass(b, pr);
+      if (s != HCU_OK) return s;
+    }
+    for (size_t i = 0; i < nm; ++i) {
+      if (!active[i]) continue;
+      Ctx& c = *b->m[i];
+      c.scf_hx_cols += (double)passes * c.p.nspin * c.p.nk * c.p.ns * (c.p.degree + 1);
+      hcu_scf_step_info si{};
+      hcu_status s = scf_post(c, &si);
+      if (s != HCU_OK) return batch_fail(b, s, c.err);
+      reps[i].iterations = it + 1;
+      reps[i].residual = si.residual;
+      reps[i].F = c.en.F;
+      reps[i].E_U = c.en.E_U;
+      reps[i].e_band = c.en.e_band;
+      reps[i].hx_columns = c.scf_hx_cols;
+      const bool done = o->fixed_iterations > 0 ? (it + 1 >= o->fixed_iterations) : (si.converged != 0);
+      if (done) {
+        active[i] = 0;
+        reps[i].converged = o->fixed_iterations > 0 ? 0 : 1;
+        reps[i].seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      }
+    }
+  }
+  for (size_t i = 0; i < nm; ++i)
+    if (active[i]) {
+      reps[i].seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (o->fixed_iterations <= 0) final_status = HCU_NOT_CONVERGED;
+    }
+  if (final_status != HCU_OK) b->err = "some members did not converge within max_iter";
+  return final_status;
 }
 
 }  // extern "C"

@@ -148,10 +148,12 @@ struct Ctx {
   std::vector<double*> d_coup;       // per spin: coupling matrices
   std::vector<void*> d_X;            // per (spin, k): orbitals nd x ns
   std::vector<void*> d_v0;           // per (spin, k): Lanczos start vector
-  void* d_W[3] = {nullptr, nullptr, nullptr};   // work blocks nd x ns
-  void* d_P = nullptr;               // projections [ns][nproj] (block type)
-  void* d_Q = nullptr;               // coupled projections, transposed: [nproj][ns]
-  void* d_PY = nullptr;              // projections of the filtered block (for D)
+  std::vector<void*> d_W;            // per (spin,k): 3 work blocks nd x ns (index 3 sk + i)
+  std::vector<void*> d_P;            // per (spin,k): projections [ns][nproj] (block type)
+  std::vector<void*> d_Q;            // per (spin,k): coupled projections, transposed [nproj][ns]
+  std::vector<void*> d_PY;           // per (spin,k): projections of the filtered block (for D)
+  void* d_jobs = nullptr;            // batched-stencil job table (used when this context leads a batch)
+  unsigned long long* d_counters = nullptr;
   void* d_ppart = nullptr;           // projection partial sums [chunk][nproj][ns]
   std::vector<void*> d_PX;           // per (spin,k) projections of X [ns][nproj]
   double* d_part = nullptr;          // split-K partials of the Gram matrices
@@ -165,6 +167,8 @@ struct Ctx {
   double* d_occ = nullptr;           // per (spin,k) occupations
   double* d_E = nullptr;             // rocsolver work (ns)
   int* d_info = nullptr;
+  std::vector<int> h_info_store;     // host copies of the eigensolve status per (spin,k)
+  int* h_info = nullptr;
   double* d_D = nullptr;             // D_out [nspin][nhub][25]
   double* d_red = nullptr;           // scalar reductions scratch
   double* d_scal = nullptr;          // scalars [0..63]: mu, e_band, dc, E_U, kT S, F, dot results;
@@ -241,6 +245,23 @@ template <typename T>
 void launch_stencil(const Ctx& c, int ik, const T* Yin, int64_t ld, const T* Yprev, int64_t ld_prev, T* Yout,
                     int64_t ld_out, int ncol, double alpha, double cshift, double beta, hipStream_t st);
 bool stencil_shape_ok(const Ctx& c, int TX, int TYt, int RY, int tz);
+// one block of a batched stencil step (stencil.hip, persistent launch)
+struct StencilJob {
+  const Ctx* c;
+  int ik;
+  const void* Yin;
+  int64_t ld;
+  const void* Yprev;
+  int64_t ld_prev;
+  void* Yout;
+  int64_t ld_out;
+  int ncol;
+  double alpha, cshift, beta;
+};
+template <typename T>
+hcu_status launch_stencil_batch(const std::vector<StencilJob>& jobs, void* d_jobs, size_t jobs_bytes,
+                                unsigned long long* d_counters, std::vector<unsigned char>& host, hipStream_t st);
+size_t stencil_job_bytes(int njobs, bool single);
 // nonlocal.hip: Y += alpha * sum_j phi_j Qt[j][s]  (64-point bricks on the
 // matrix cores for real blocks, per-point table for complex blocks)
 template <typename T>
@@ -283,6 +304,15 @@ void launch_density(const Ctx& c, const T* X, int64_t ld, const double* occ, dou
                     hipStream_t st);
 
 }  // namespace hcu
+
+#define HCU_HIP_CTX(ctx, call)                                               \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess) {                                                  \
+      (ctx).err = std::string("HIP error: ") + hipGetErrorString(e_);         \
+      return HCU_DEVICE;                                                     \
+    }                                                                        \
+  } while (0)
 
 #define HCU_HIP(call)                                                        \
   do {                                                                       \

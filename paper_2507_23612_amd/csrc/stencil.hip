@@ -33,6 +33,17 @@ struct KArgs {
   int64_t ld, ld_prev, ld_out;
 };
 
+template <typename RT>
+struct SJob {
+  const void* Yin;
+  const void* Yprev;
+  void* Yout;
+  const RT* V;
+  KArgs<RT> a;
+  int ntiles, nzc;
+  unsigned long long item_begin;
+};
+
 template <typename T> struct Ld {
   // value of the (possibly wrapped) node with wrap counts w (each -1, 0, 1)
   template <typename RT>
@@ -64,22 +75,17 @@ __device__ inline int wrap(int g, int n, int& w) {
 
 constexpr int kHaloSlots = 8;     // halo values a thread stages per plane (host checks the bound)
 
+// One work item: tile `tile` of the x-y plane, z chunk `zc`, state `s`.
 template <typename T, typename RT, int R, int RY>
-__global__ __launch_bounds__(512) void k_stencil(const T* __restrict__ Yin, const T* __restrict__ Yprev,
-                                                 T* __restrict__ Yout, const RT* __restrict__ V,
-                                                 const KArgs<RT> a) {
-  extern __shared__ unsigned char smem_raw[];
+__device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T* __restrict__ Yprev,
+                                             T* __restrict__ Yout, const RT* __restrict__ V, const KArgs<RT>& a,
+                                             int tile, int zc, int64_t s, unsigned char* smem_raw) {
   const int TX = blockDim.x, TYt = blockDim.y, TY = TYt * RY;
   const int SW = TX + 2 * R, SH = TY + 2 * R;
   T* const buf0 = reinterpret_cast<T*>(smem_raw);
   T* const buf1 = buf0 + SW * SH;
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = ty * TX + tx, nthr = TX * TYt;
-  // logical order: tile fastest, then z chunk, then state; XCD-contiguous
-  const unsigned lw = xcd_linear();
-  const int tile = lw % gridDim.x;
-  const int zc = (lw / gridDim.x) % gridDim.y;
-  const int64_t s = lw / (gridDim.x * gridDim.y);
   const int bx = tile % a.tiles_x, by = tile / a.tiles_x;
   const int x0 = bx * TX, y0 = by * TY;
   const int zbeg = zc * a.tz;
@@ -206,6 +212,56 @@ __global__ __launch_bounds__(512) void k_stencil(const T* __restrict__ Yin, cons
   }
 }
 
+template <typename T, typename RT, int R, int RY>
+__global__ __launch_bounds__(512) void k_stencil(const T* __restrict__ Yin, const T* __restrict__ Yprev,
+                                                 T* __restrict__ Yout, const RT* __restrict__ V,
+                                                 const KArgs<RT> a) {
+  extern __shared__ unsigned char smem_raw[];
+  // logical order: tile fastest, then z chunk, then state; XCD-contiguous
+  const unsigned lw = xcd_linear();
+  const int tile = lw % gridDim.x;
+  const int zc = (lw / gridDim.x) % gridDim.y;
+  const int64_t s = lw / (gridDim.x * gridDim.y);
+  stencil_item<T, RT, R, RY>(Yin, Yprev, Yout, V, a, tile, zc, s, smem_raw);
+}
+
+// Persistent form over a list of jobs (blocks of possibly different grids):
+// the item space [0, total) is cut into kNumXcd contiguous ranges with one
+// counter each; workgroup w starts on range w % kNumXcd (the XCD it runs on)
+// and moves to the next range when its own is exhausted.  Every workgroup
+// leaves after visiting all ranges, so the grid always drains.
+template <typename T, typename RT, int R, int RY>
+__global__ __launch_bounds__(512) void k_stencil_batch(const SJob<RT>* __restrict__ jobs, int njobs,
+                                                       unsigned long long total,
+                                                       unsigned long long* __restrict__ counters) {
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ unsigned long long s_item;
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const unsigned long long per = (total + kNumXcd - 1) / kNumXcd;
+  const int r0 = (int)(blockIdx.x % kNumXcd);
+  for (int rr = 0; rr < kNumXcd; ++rr) {
+    const int r = (r0 + rr) % kNumXcd;
+    const unsigned long long lo = per * r;
+    const unsigned long long hi = min(total, lo + per);
+    for (;;) {
+      if (tid == 0) s_item = lo + atomicAdd(&counters[r], 1ULL);
+      __syncthreads();
+      const unsigned long long item = s_item;
+      __syncthreads();
+      if (item >= hi) break;
+      int j = 0;
+      while (j + 1 < njobs && jobs[j + 1].item_begin <= item) ++j;
+      const SJob<RT>& jb = jobs[j];
+      const unsigned long long loc = item - jb.item_begin;
+      const int tile = (int)(loc % jb.ntiles);
+      const int zc = (int)((loc / jb.ntiles) % jb.nzc);
+      const int64_t s = (int64_t)(loc / ((unsigned long long)jb.ntiles * jb.nzc));
+      stencil_item<T, RT, R, RY>((const T*)jb.Yin, (const T*)jb.Yprev, (T*)jb.Yout, jb.V, jb.a, tile, zc, s,
+                                 smem_raw);
+    }
+  }
+}
+
 // Tile shape for a grid: TX threads along x, TYt thread rows, RY points per
 // thread along y, tz planes per workgroup.  Tuned values (hcu_autotune) win.
 struct StencilShape { int TX, TYt, RY, tz; };
@@ -297,9 +353,124 @@ void launch_stencil(const Ctx& c, int ik, const T* Yin, int64_t ld, const T* Ypr
   }
 }
 
+template <typename T, typename RT, int R>
+static void launch_batch_r(int RY, dim3 grid, dim3 block, size_t lds, const SJob<RT>* jobs, int njobs,
+                           unsigned long long total, unsigned long long* counters, hipStream_t st) {
+  if (RY == 4)
+    k_stencil_batch<T, RT, R, 4><<<grid, block, lds, st>>>(jobs, njobs, total, counters);
+  else if (RY == 2)
+    k_stencil_batch<T, RT, R, 2><<<grid, block, lds, st>>>(jobs, njobs, total, counters);
+  else
+    k_stencil_batch<T, RT, R, 1><<<grid, block, lds, st>>>(jobs, njobs, total, counters);
+}
+
+// Common tile shape for a set of grids: the autotuned shape of the first
+// context if every grid admits it, else the largest admissible built-in one.
+bool batch_shape(const std::vector<const Ctx*>& cs, int ncol, int elem, int& TX, int& TYt, int& RY) {
+  const Ctx& c0 = *cs[0];
+  StencilShape sh = pick_tiles(c0, ncol, elem);
+  auto ok_all = [&](const StencilShape& t) {
+    for (const Ctx* c : cs)
+      if (!shape_ok(*c, StencilShape{t.TX, t.TYt, t.RY, 1}, c->p.n0)) return false;
+    return true;
+  };
+  if (!ok_all(sh)) {
+    int n1min = 1 << 30, n2min = 1 << 30;
+    for (const Ctx* c : cs) { n1min = std::min(n1min, c->p.n[0]); n2min = std::min(n2min, c->p.n[1]); }
+    bool found = false;
+    for (int ry : {elem > 8 ? 2 : 4, 2, 1}) {
+      for (int tx : {std::min(n1min, 128), 64, 32, 16}) {
+        if (tx > n1min) continue;
+        for (int tyt = std::max(1, 256 / tx); tyt >= 1 && !found; --tyt) {
+          StencilShape t{tx, tyt, ry, 1};
+          if (tyt * ry <= n2min && ok_all(t)) { sh = t; found = true; }
+        }
+        if (found) break;
+      }
+      if (found) break;
+    }
+    if (!found) return false;
+  }
+  TX = sh.TX; TYt = sh.TYt; RY = sh.RY;
+  return true;
+}
+
+// One stencil step for many blocks in one persistent launch.  `host` holds
+// the job table until the caller synchronises the stream.
+template <typename T>
+hcu_status launch_stencil_batch(const std::vector<StencilJob>& jobs, void* d_jobs, size_t jobs_bytes,
+                                unsigned long long* d_counters, std::vector<unsigned char>& host, hipStream_t st) {
+  using RT = typename real_of<T>::type;
+  if (jobs.empty()) return HCU_OK;
+  std::vector<const Ctx*> cs;
+  int ncol = 0;
+  for (const StencilJob& j : jobs) { cs.push_back(j.c); ncol = std::max(ncol, j.ncol); }
+  const int R = cs[0]->p.n0;
+  for (const Ctx* c : cs)
+    if (c->p.n0 != R) return HCU_INVALID_ARG;
+  int TX, TYt, RY;
+  if (!batch_shape(cs, ncol, (int)sizeof(T), TX, TYt, RY)) return HCU_INVALID_ARG;
+  const int TY = TYt * RY;
+  host.assign(jobs.size() * sizeof(SJob<RT>), 0);
+  SJob<RT>* hj = reinterpret_cast<SJob<RT>*>(host.data());
+  unsigned long long total = 0;
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    const StencilJob& j = jobs[i];
+    const Ctx& c = *j.c;
+    StencilCoef sc;
+    fill_stencil_coef(c, j.ik, sc);
+    KArgs<RT> a{};
+    for (int p = 0; p <= kMaxR; ++p) {
+      a.kx[p] = (RT)sc.kin[0][p];
+      a.ky[p] = (RT)sc.kin[1][p];
+      a.kz[p] = (RT)sc.kin[2][p];
+    }
+    a.center = (RT)sc.center;
+    a.alpha = (RT)j.alpha; a.cshift = (RT)j.cshift; a.beta = (RT)j.beta;
+    for (int d = 0; d < 3; ++d) { a.ph_re[d] = (RT)sc.phase_re[d]; a.ph_im[d] = (RT)sc.phase_im[d]; }
+    a.n1 = c.p.n[0]; a.n2 = c.p.n[1]; a.n3 = c.p.n[2];
+    a.has_prev = (j.Yprev != nullptr && j.beta != 0.0) ? 1 : 0;
+    a.ld = j.ld; a.ld_prev = j.ld_prev; a.ld_out = j.ld_out;
+    a.tiles_x = (a.n1 + TX - 1) / TX;
+    const int tiles = a.tiles_x * ((a.n2 + TY - 1) / TY);
+    a.tz = std::max(8, std::min(a.n3, 24));
+    const int nzc = (a.n3 + a.tz - 1) / a.tz;
+    SJob<RT>& h = hj[i];
+    h.Yin = j.Yin; h.Yprev = j.Yprev; h.Yout = j.Yout;
+    if constexpr (sizeof(RT) == 4) h.V = c.d_Vf; else h.V = c.d_V;
+    h.a = a;
+    h.ntiles = tiles;
+    h.nzc = nzc;
+    h.item_begin = total;
+    total += (unsigned long long)tiles * nzc * j.ncol;
+  }
+  if (host.size() > jobs_bytes) return HCU_OOM;
+  hipError_t e = hipMemcpyAsync(d_jobs, host.data(), host.size(), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(d_counters, 0, kNumXcd * sizeof(unsigned long long), st);
+  if (e != hipSuccess) return HCU_DEVICE;
+  const size_t lds = 2 * (size_t)(TY + 2 * R) * (TX + 2 * R) * sizeof(T);
+  dim3 grid(1024), block(TX, TYt);
+  const SJob<RT>* dj = reinterpret_cast<const SJob<RT>*>(d_jobs);
+  switch (R) {
+    case 1: launch_batch_r<T, RT, 1>(RY, grid, block, lds, dj, (int)jobs.size(), total, d_counters, st); break;
+    case 2: launch_batch_r<T, RT, 2>(RY, grid, block, lds, dj, (int)jobs.size(), total, d_counters, st); break;
+    case 3: launch_batch_r<T, RT, 3>(RY, grid, block, lds, dj, (int)jobs.size(), total, d_counters, st); break;
+    case 4: launch_batch_r<T, RT, 4>(RY, grid, block, lds, dj, (int)jobs.size(), total, d_counters, st); break;
+    case 5: launch_batch_r<T, RT, 5>(RY, grid, block, lds, dj, (int)jobs.size(), total, d_counters, st); break;
+    default: launch_batch_r<T, RT, 6>(RY, grid, block, lds, dj, (int)jobs.size(), total, d_counters, st); break;
+  }
+  return hipGetLastError() == hipSuccess ? HCU_OK : HCU_DEVICE;
+}
+
+size_t stencil_job_bytes(int njobs, bool single) {
+  return (size_t)njobs * (single ? sizeof(SJob<float>) : sizeof(SJob<double>));
+}
+
 #define INST_STENCIL(T)                                                                                 \
   template void launch_stencil<T>(const Ctx&, int, const T*, int64_t, const T*, int64_t, T*, int64_t, int, \
-                                  double, double, double, hipStream_t);
+                                  double, double, double, hipStream_t);                                \
+  template hcu_status launch_stencil_batch<T>(const std::vector<StencilJob>&, void*, size_t,             \
+                                              unsigned long long*, std::vector<unsigned char>&, hipStream_t);
 INST_STENCIL(double)
 INST_STENCIL(float)
 INST_STENCIL(cplx<double>)

@@ -121,6 +121,11 @@ def load_library(path=LIB_PATH):
         "hcu_get_energies": (C.c_int, [P, C.POINTER(hcu_energies)]),
         "hcu_get_orbitals": (C.c_int, [P, C.c_int, C.c_int, P, C.c_int]),
         "hcu_get_density": (C.c_int, [P, C.POINTER(C.c_double)]),
+        "hcu_batch_create": (C.c_int, [C.POINTER(P), C.c_int, C.POINTER(P)]),
+        "hcu_batch_destroy": (None, [P]),
+        "hcu_batch_last_error": (C.c_char_p, [P]),
+        "hcu_batch_chfsi_pass": (C.c_int, [P]),
+        "hcu_batch_scf": (C.c_int, [P, C.POINTER(hcu_scf_opts), C.POINTER(hcu_scf_report)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -374,6 +379,52 @@ class HcuContext:
         out = np.zeros((self.nspin, self.nd))
         self._check(self.lib.hcu_get_density(self.h, _dptr(out)))
         return out
+
+
+class HcuBatch:
+    """Several bound contexts advanced together (one persistent stencil
+    launch per Chebyshev step over all their blocks).  Holds references to
+    the contexts; does not own them."""
+
+    def __init__(self, ctxs):
+        self.lib = load_library()
+        self.ctxs = list(ctxs)
+        arr = (C.c_void_p * len(self.ctxs))(*[c.h for c in self.ctxs])
+        self.h = C.c_void_p()
+        st = self.lib.hcu_batch_create(arr, len(self.ctxs), C.byref(self.h))
+        if st != HCU_OK:
+            msg = self.lib.hcu_batch_last_error(self.h).decode() if self.h else "batch create failed"
+            self.lib.hcu_batch_destroy(self.h)
+            self.h = None
+            raise HcuError(st, msg)
+
+    def _check(self, st):
+        if st != HCU_OK:
+            raise HcuError(st, self.lib.hcu_batch_last_error(self.h).decode())
+
+    def close(self):
+        if self.h:
+            self.lib.hcu_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def chfsi_pass(self):
+        self._check(self.lib.hcu_batch_chfsi_pass(self.h))
+
+    def scf(self, max_iter=100, first_passes=4, lanczos_steps=10, pulay_history=7, pulay_beta=0.3, tol_d=1e-7,
+            tol_f=1e-7, fixed_iterations=0, verbose=False, raise_on_nonconv=True):
+        o = hcu_scf_opts(max_iter, first_passes, lanczos_steps, pulay_history, pulay_beta, tol_d, tol_f,
+                         fixed_iterations, 1 if verbose else 0)
+        reps = (hcu_scf_report * len(self.ctxs))()
+        st = self.lib.hcu_batch_scf(self.h, C.byref(o), reps)
+        if st != HCU_OK and not (st == HCU_NOT_CONVERGED and not raise_on_nonconv):
+            self._check(st)
+        return [{k: getattr(r, k) for k, _ in hcu_scf_report._fields_} for r in reps]
 
 
 def start_inputs(ctx, cfg, spin=0, ik=0):

@@ -1,0 +1,159 @@
+"""Batched execution of independent cells (one persistent stencil launch per
+Chebyshev step over every member's blocks) against the unbatched path and
+the oracle.
+
+A batched member runs the same per-point arithmetic as its unbatched twin;
+only the assignment of tiles to workgroups differs, so FP64 results agree to
+rounding (1e-10) and the SCF against the oracle keeps the unbatched bars
+(free energy 1e-8 Ha/atom, Ritz values 1e-8 Ha, D 1e-6).
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _ragged(degree=12):
+    cfg = workloads.make_config("tiny", seed=5)
+    cfg["n"] = np.array([20, 18, 14], np.int32)
+    cfg["ns"] = 10
+    cfg["degree"] = degree
+    return cfg
+
+
+def _c1(degree=12):
+    cfg = workloads.make_config("c1", seed=2)
+    cfg["degree"] = degree
+    return cfg
+
+
+def _prepared(cfg, precision=None, d_seed=None):
+    from paper_2507_23612_amd import hcu
+    ctx = hcu.HcuContext(cfg, precision)
+    if d_seed is None:
+        ctx.set_hubbard_occupation(hcu.initial_occupation(ctx, cfg))
+    else:
+        rng = np.random.default_rng(d_seed)
+        D = np.zeros((ctx.nspin, ctx.nhub, 5, 5))
+        for s in range(ctx.nspin):
+            for h in range(ctx.nhub):
+                A = rng.normal(size=(5, 5)) * 0.05
+                D[s, h] = 0.2 * np.eye(5) + A + A.T
+        ctx.set_hubbard_occupation(D)
+    for s in range(ctx.nspin):
+        for ik in range(ctx.nk):
+            X0, v0 = hcu.start_inputs(ctx, cfg, s, ik)
+            ctx.set_start(s, ik, X0, v0)
+    return ctx
+
+
+def _cols_close(A, B, tol):
+    """Columns of A and B (rows of the (ns, nd) arrays) equal up to a unit
+    phase each (eigenvectors of simple eigenvalues)."""
+    for a, b in zip(A, B):
+        ph = np.vdot(b, a)
+        ph = ph / abs(ph) if abs(ph) > 0 else 1.0
+        assert np.max(np.abs(a - ph * b)) <= tol * max(np.max(np.abs(a)), 1e-300)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_pass_equals_single_passes(precision):
+    torch = _torch()
+    from paper_2507_23612_amd import hcu
+    cfgs = [workloads.make_config("tiny"), _ragged(), _c1()]
+    print(f"[gpu] batch pass {precision}: {[list(c['n']) for c in cfgs]}", flush=True)
+    single = [_prepared(c, precision, d_seed=10 + i) for i, c in enumerate(cfgs)]
+    batched = [_prepared(c, precision, d_seed=10 + i) for i, c in enumerate(cfgs)]
+    for ctx in single + batched:
+        ctx.lanczos_bounds()
+    for ctx in single:
+        ctx.chfsi_pass()
+    b = hcu.HcuBatch(batched)
+    b.chfsi_pass()
+    for ctx in single + batched:
+        ctx.update_occupations()
+    torch.cuda.synchronize()
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    for i, (s, t) in enumerate(zip(single, batched)):
+        ls, lt = s.get_eigenvalues(), t.get_eigenvalues()
+        err = np.max(np.abs(ls - lt))
+        print(f"[gpu] batch pass member {i}: max |d lambda| {err:.2e}", flush=True)
+        assert err < tol
+        np.testing.assert_allclose(t.get_hubbard_occupation(), s.get_hubbard_occupation(), atol=tol)
+        nocc = int(cfgs[i]["nelec"] / 2)
+        Xs = s.get_orbitals().cpu().numpy()[:nocc]
+        Xt = t.get_orbitals().cpu().numpy()[:nocc]
+        _cols_close(Xt, Xs, 1e-8 if precision == "fp64" else 1e-3)
+    b.close()
+
+
+def test_batched_scf_matches_oracle():
+    """Three cells of different grids converged together; each member
+    against the oracle's SCF from the same inputs."""
+    _torch()
+    from oracle import scf as oscf
+    from paper_2507_23612_amd import hcu
+    cfgs = [workloads.make_config("tiny"), _ragged(), workloads.make_config("tiny", seed=9, jitter=0.1)]
+    ctxs = [_prepared(c) for c in cfgs]
+    b = hcu.HcuBatch(ctxs)
+    reps = b.scf()
+    for i, (cfg, ctx, rep) in enumerate(zip(cfgs, ctxs, reps)):
+        ref = oscf.scf(cfg)
+        e = ctx.get_energies()
+        natom = len(cfg["atom_species"])
+        print(f"[gpu] batch scf member {i}: F gpu {e['F']:.12f} oracle {ref['F']:.12f} "
+              f"iters {rep['iterations']} vs {ref['iterations']}", flush=True)
+        assert rep["converged"] and ref["converged"]
+        assert abs(e["F"] - ref["F"]) / natom < 1e-8
+        assert abs(e["E_U"] - ref["E_U"]) < 1e-7
+        nocc = int(cfg["nelec"] / 2)
+        m = min(nocc + 2, cfg["ns"])
+        np.testing.assert_allclose(ctx.get_eigenvalues()[0, 0, :m], ref["eigs"][0, 0, :m], atol=1e-8)
+        Dg = ctx.get_hubbard_occupation()[0]
+        for h in range(ctx.nhub):
+            np.testing.assert_allclose(Dg[h], ref["D"][0][h], atol=1e-6)
+    b.close()
+
+
+def test_batched_scf_kpoints_equals_single():
+    """Complex members (spin-polarised, 8 k-points each: 32 Bloch blocks per
+    launch) against their unbatched SCF (the unbatched spin-polarised
+    k-point SCF is held to the oracle in the parity suite)."""
+    _torch()
+    from paper_2507_23612_amd import hcu
+    cfgs = [workloads.with_kpoints(workloads.make_config("tiny")), workloads.with_kpoints(_ragged())]
+    single = [_prepared(c) for c in cfgs]
+    rs = [ctx.scf() for ctx in single]
+    batched = [_prepared(c) for c in cfgs]
+    b = hcu.HcuBatch(batched)
+    rb = b.scf()
+    for i in range(len(cfgs)):
+        es, eb = single[i].get_energies(), batched[i].get_energies()
+        print(f"[gpu] batch k member {i}: F single {es['F']:.12f} batched {eb['F']:.12f} "
+              f"iters {rs[i]['iterations']} / {rb[i]['iterations']}", flush=True)
+        assert rb[i]["converged"]
+        assert rb[i]["iterations"] == rs[i]["iterations"]
+        assert abs(es["F"] - eb["F"]) < 1e-10
+        np.testing.assert_allclose(batched[i].get_eigenvalues(), single[i].get_eigenvalues(), atol=1e-10)
+    b.close()
+
+
+def test_batch_rejects_mismatched_members():
+    _torch()
+    from paper_2507_23612_amd import hcu
+    a = _prepared(workloads.make_config("tiny"))
+    c = _prepared(workloads.make_config("c1"))     # degree 20 against 12
+    with pytest.raises(hcu.HcuError):
+        hcu.HcuBatch([a, c])
+    k = _prepared(workloads.with_kpoints(workloads.make_config("tiny")))   # complex against real
+    with pytest.raises(hcu.HcuError):
+        hcu.HcuBatch([a, k])
