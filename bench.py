@@ -40,14 +40,36 @@ WORKLOADS = {
 }
 
 
-def stencil_bytes(cfg, ctx_nproj_nnz, elem):
-    """Algorithmic HBM bytes of one fused Chebyshev-step launch: read Y_i and
-    Y_{i-1}, write Y_{i+1} (3 words per point-state), plus V once and the
-    per-point projector table (value + column) once."""
+def stencil_bytes(cfg, elem):
+    """Algorithmic HBM bytes of one fused Chebyshev-step stencil launch over
+    the block: read Y_i and Y_{i-1}, write Y_{i+1} (3 words per point-state),
+    plus V_loc once."""
     nd = int(np.prod(cfg["n"]))
     ns = int(cfg["ns"])
-    nnz = ctx_nproj_nnz
-    return 3 * elem * nd * ns + elem * nd + nnz * (elem + 4) + 4 * (nd + 1)
+    return 3 * elem * nd * ns + elem * nd
+
+
+def measured_traffic(config, prec, tile):
+    """HBM bytes per stencil launch from the committed counter summary
+    profiles/k_stencil_<config>_<prec>.md (FETCH_SIZE and WRITE_SIZE runs,
+    calibrated on a plain copy), or None if there is none for this tile shape
+    or the kernel sources changed since it was taken."""
+    from paper_2507_23612_amd.tracesum import kernel_source_digest
+    path = os.path.join(ROOT, "profiles", f"k_stencil_{config}_{prec}.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- record "):
+                k, _, v = line[len("- record "):].partition(":")
+                rec[k.strip()] = v.strip()
+    try:
+        if rec.get("source_sha256") != kernel_source_digest() or rec.get("tile") != tile:
+            return None
+        return int(float(rec["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(cfg, nstates=8, degree=16):
@@ -195,14 +217,16 @@ def main():
     value = nd * ns * (m + 1) / (dt / args.steps) / 1e9
 
     elem = 4 if prec == "mixed" else 8
-    nnz = ctx.get_sizes()["table_nnz"]
-    bytes_launch = stencil_bytes(cfg, nnz, elem)
+    bytes_launch = stencil_bytes(cfg, elem)
     st_ms = kt["stencil_ms"] / max(kt["stencil_launches"], 1)
     achieved = bytes_launch / (st_ms * 1e-3) / 1e9
+    tile = f'{tuning["tile_x"]},{tuning["tile_yt"]},{tuning["ry"]},{tuning["tile_z"]}'
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_stencil (fused stencil + V + projector scatter + Chebyshev step)",
-                "avg_launch_ms": round(st_ms, 4), "algorithmic_bytes_per_launch": int(bytes_launch)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(args.config, prec, tile),
+                "kernel": "k_stencil (12th-order FD stencil + V_loc + Chebyshev three-term step)",
+                "avg_launch_ms": round(st_ms, 4), "algorithmic_bytes_per_launch": int(bytes_launch),
+                "tile": tile}
     breakdown = {k: round(v / args.steps, 3) for k, v in kt.items() if k.endswith("_ms")}
 
     out = {"metric": METRIC, "value": round(value, 3), "unit": "Gpts·states/s", "n_gpus": 1,

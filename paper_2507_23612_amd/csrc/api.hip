@@ -380,8 +380,14 @@ struct BProb {
 // stencil of all problems runs as one persistent launch.  All contexts share
 // the stream and the filter degree.
 template <typename T>
-hcu_status batch_pass_t(std::vector<BProb>& probs, Ctx& lead) {
+hcu_status batch_pass_t(std::vector<BProb>& probs, Ctx& lead, double* filter_ms) {
   hipStream_t st = lead.stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (filter_ms) {
+    HCU_HIP_CTX(lead, hipEventCreate(&e0));
+    HCU_HIP_CTX(lead, hipEventCreate(&e1));
+    HCU_HIP_CTX(lead, hipEventRecord(e0, st));
+  }
   const int np = (int)probs.size();
   const int m = lead.p.degree;
   std::vector<std::vector<unsigned char>> tables;   // host job tables, alive until the final sync
@@ -459,6 +465,7 @@ hcu_status batch_pass_t(std::vector<BProb>& probs, Ctx& lead) {
     Ctx& c = *q.c;
     if (c.nproj > 0) scatter_t<T>(c, q.spin, q.ik, (T*)c.d_W[3 * q.sk + (cur[i] + 1) % 3], c.nd, c.p.ns, 1.0);
   }
+  if (filter_ms) HCU_HIP_CTX(lead, hipEventRecord(e1, st));
   // Rayleigh-Ritz per problem
   for (int i = 0; i < np; ++i) {
     BProb& q = probs[i];
@@ -466,6 +473,13 @@ hcu_status batch_pass_t(std::vector<BProb>& probs, Ctx& lead) {
     if (s != HCU_OK) return s;
   }
   HCU_HIP_CTX(lead, hipStreamSynchronize(st));
+  if (filter_ms) {
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    *filter_ms += ms;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+  }
   for (BProb& q : probs) {
     s = rr_finish(*q.c, q.sk);
     if (s != HCU_OK) return s;
@@ -1103,13 +1117,23 @@ hcu_status hcu_scf_step(hcu_ctx* ctx, hcu_scf_step_info* info) {
   Ctx& c = *ctx;
   if (!c.scf_ready) return fail(c, HCU_INVALID_ARG, "call hcu_scf_begin first");
   const int passes = c.scf_iter == 0 ? c.scf_opts.first_passes : 1;
-  for (int sp = 0; sp < c.p.nspin; ++sp)
-    for (int k = 0; k < c.p.nk; ++k)
-      for (int ps = 0; ps < passes; ++ps) {
-        s = DISPATCH(c, pass_t, c, sp, k, &c.scf_filter_ms);
-        if (s != HCU_OK) return s;
-        c.scf_hx_cols += (double)c.p.ns * (c.p.degree + 1);
-      }
+  const int nsk = c.p.nspin * c.p.nk;
+  if (nsk == 1) {
+    for (int ps = 0; ps < passes; ++ps) {
+      s = DISPATCH(c, pass_t, c, 0, 0, &c.scf_filter_ms);
+      if (s != HCU_OK) return s;
+    }
+  } else {
+    // every (spin, k) block of the context in one persistent stencil launch per Chebyshev step
+    std::vector<BProb> pr;
+    for (int sp = 0; sp < c.p.nspin; ++sp)
+      for (int k = 0; k < c.p.nk; ++k) pr.push_back(BProb{&c, sp, k, sk_index(c, sp, k), 0, 0, 0, 0});
+    for (int ps = 0; ps < passes; ++ps) {
+      s = DISPATCH(c, batch_pass_t, pr, c, &c.scf_filter_ms);
+      if (s != HCU_OK) return s;
+    }
+  }
+  c.scf_hx_cols += (double)passes * nsk * c.p.ns * (c.p.degree + 1);
   return scf_post(c, info);
 }
 
@@ -1234,7 +1258,7 @@ std::vector<BProb> batch_problems(hcu_batch* b, const std::vector<int>& active) 
 hcu_status batch_run_pass(hcu_batch* b, std::vector<BProb>& pr) {
   if (pr.empty()) return HCU_OK;
   Ctx& lead = *pr[0].c;
-  hcu_status s = DISPATCH(lead, batch_pass_t, pr, lead);
+  hcu_status s = DISPATCH(lead, batch_pass_t, pr, lead, (double*)nullptr);
   if (s != HCU_OK) {
     std::string msg = lead.err;
     for (BProb& q : pr)
