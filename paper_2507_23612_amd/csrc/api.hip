@@ -58,10 +58,17 @@ size_t layout(Ctx& c, char* base) {
   b.take(c.d_bnj, sizeof(int) * c.bnj.size());
   b.take(c.d_bj, sizeof(int) * c.bj.size());
   b.take(c.d_bsrc, sizeof(int64_t) * c.bsrc.size());
+  b.take(c.d_pboff, sizeof(int64_t) * c.pboff.size());
+  b.take(c.d_pbnj, sizeof(int) * c.pbnj.size());
+  b.take(c.d_pbsrc, sizeof(int64_t) * c.pbsrc.size());
+  b.take(c.d_pdest, sizeof(int64_t) * c.pdest.size());
+  b.take(c.d_jrow, sizeof(int64_t) * c.jrow.size());
   c.d_cscv.assign(c.p.nk, nullptr);
   c.d_csrv.assign(c.p.nk, nullptr);
   c.d_bval.assign(c.p.nk, nullptr);
+  c.d_pbval.assign(c.p.nk, nullptr);
   for (int k = 0; k < c.p.nk; ++k) {
+    b.take(c.d_pbval[k], es * c.pbsrc.size());
     b.take(c.d_cscv[k], es * c.nval);
     b.take(c.d_csrv[k], es * nnz);
     b.take(c.d_bval[k], es * c.bsrc.size());
@@ -88,7 +95,7 @@ size_t layout(Ctx& c, char* base) {
   }
   b.take(c.d_jobs, kBatchJobBytes);
   b.take(c.d_counters, sizeof(unsigned long long) * kNumXcd);
-  b.take(c.d_ppart, es * (size_t)ns * c.nproj * project_max_chunks(c));
+  b.take(c.d_ppart, es * std::max((size_t)ns * c.nproj * project_max_chunks(c), project_partial_elems(c)));
   c.part_elems = c.any_complex ? gram_partial_elems_c(ns, c.nd) : gram_partial_elems(ns, c.nd);
   b.take(c.d_part, sizeof(double) * c.part_elems);
   b.take(c.d_tiles, sizeof(int2) * gram_tiles(ns, c.any_complex).size());
@@ -229,8 +236,11 @@ template <typename T>
 void project_t(Ctx& c, int spin, int ik, const T* y, int64_t ldy, int ncol) {
   ProfScope ps(c, PK_PROJECT);
   const int sk = sk_index(c, spin, ik);
-  launch_project<T>(c, y, ncol, ldy, (const T*)c.d_cscv[ik], c.d_coup[spin], (T*)c.d_P[sk], (T*)c.d_Q[sk],
-                    c.stream);
+  if constexpr (sizeof(T) == sizeof(typename real_of<T>::type))
+    launch_project_brick<T>(c, ik, y, ncol, ldy, c.d_coup[spin], (T*)c.d_P[sk], (T*)c.d_Q[sk], c.stream);
+  else
+    launch_project<T>(c, y, ncol, ldy, (const T*)c.d_cscv[ik], c.d_coup[spin], (T*)c.d_P[sk], (T*)c.d_Q[sk],
+                      c.stream);
 }
 
 // Y (already holding the local part) += alpha Phi Q.
@@ -852,7 +862,8 @@ hcu_status hcu_create(const hcu_problem* p, hcu_ctx** out) {
     if (p->n[a] < 2) return bad("each n_a must be >= 2");
     if (!(p->L[a] > 0)) return bad("cell lengths must be positive");
   }
-  if ((int64_t)p->n[0] * p->n[1] * p->n[2] > (int64_t)1 << 30) return bad("grid too large");
+  if ((int64_t)p->n[0] * p->n[1] * p->n[2] > (int64_t)65535 * 64)
+    return bad("grid too large (at most 4194240 points)");
   if (p->nspin != 1 && p->nspin != 2) return bad("nspin must be 1 or 2");
   if (p->nk < 1 || !p->kpts || !p->kw) return bad("need nk >= 1 k-points and weights");
   if (p->natom < 0 || (p->natom > 0 && (!p->atom_species || !p->pos))) return bad("bad atom arrays");

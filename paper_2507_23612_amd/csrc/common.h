@@ -124,6 +124,19 @@ struct Ctx {
   int* d_bj = nullptr;
   int64_t* d_bsrc = nullptr;
   std::vector<void*> d_bval;         // per k: [slot][point]
+  // Projection bricks (real blocks): runs of kPBrick consecutive points with
+  // the union of their functions, laid out like the bricks.  Each slot's
+  // partial sum goes to row pdest[slot] of a function-major partial array;
+  // function j owns rows jrow[j] .. jrow[j+1] (its bricks in ascending order).
+  std::vector<int64_t> pboff;
+  std::vector<int> pbnj;
+  std::vector<int64_t> pbsrc, pdest, jrow;
+  int64_t* d_pboff = nullptr;
+  int* d_pbnj = nullptr;
+  int64_t* d_pbsrc = nullptr;
+  int64_t* d_pdest = nullptr;
+  int64_t* d_jrow = nullptr;
+  std::vector<void*> d_pbval;        // per k: [slot][kPBrick points]
   int nm_count[kMaxNm + 1] = {0};    // projector blocks per function count
   int nm_offset[kMaxNm + 1] = {0};   // offset of each count's list in d_nm_lists
   int* d_nm_lists = nullptr;
@@ -267,12 +280,35 @@ size_t stencil_job_bytes(int njobs, bool single);
 template <typename T>
 void launch_nl_scatter(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T* Qt, double alpha, hipStream_t st);
 constexpr int kBrick = 64;
+constexpr int kPBrick = 256;
+
+// 16x16x4 matrix-core step D += A B per wave.  Operands: lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; result column l%16, rows row(l, r).
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+template <typename T> struct Mf;
+template <> struct Mf<double> {
+  using V = d4;
+  __device__ static inline V mfma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <> struct Mf<float> {
+  using V = f4;
+  __device__ static inline V mfma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
 
 // proj.hip: P = Phi^H Y dV (per block, chunked support) and Q = C_b P (transposed)
 template <typename T>
 void launch_project(const Ctx& c, const T* Y, int ncol, int64_t ld, const T* cscv, const double* coup,
                     T* P, T* Q, hipStream_t st);
 int project_max_chunks(const Ctx& c);
+// Real blocks: per-brick partials on the matrix cores (every point of the
+// block read once), then per-function sums over the function's slots.
+template <typename T>
+void launch_project_brick(const Ctx& c, int ik, const T* Y, int ncol, int64_t ld, const double* coup, T* P, T* Q,
+                          hipStream_t st);
+size_t project_partial_elems(const Ctx& c);
 
 // gemm.hip
 size_t gram_partial_elems(int n, int64_t nd);

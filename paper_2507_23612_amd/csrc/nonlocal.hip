@@ -48,20 +48,6 @@ __global__ __launch_bounds__(256) void k_nl_scatter(T* __restrict__ Y, int64_t l
     if (s < nh) Yp[(int64_t)s * ld] += alpha * acc[s];
 }
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-template <typename T> struct Mf;
-template <> struct Mf<double> {
-  using V = d4;
-  __device__ static inline V mfma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-  __device__ static inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
-};
-template <> struct Mf<float> {
-  using V = f4;
-  __device__ static inline V mfma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-  __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-};
-
 // Workgroup: 4 waves x 16 states = 64 states, one brick of 64 points.
 // Wave w owns states s0 + 16 w .. + 16 and computes
 // D'(16 s x 16 p) += A'(16 s x 4 j) B'(4 j x 16 p) for the brick's 4 point
@@ -71,13 +57,13 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_nl_brick(T* __restrict__ Y, int64_t ld, int ncol,
                                                   const int64_t* __restrict__ boff, const int* __restrict__ bnj,
                                                   const int* __restrict__ bj, const T* __restrict__ bval,
-                                                  const T* __restrict__ Qt, int ldq, T alpha, int64_t nd) {
+                                                  const T* __restrict__ Qt, int ldq, T alpha, int64_t nd, int nst) {
   using V = typename Mf<T>::V;
-  // logical order: state tile fastest, then brick; XCD-contiguous so the
-  // state tiles of a brick share its table tile in one L2
+  // 1-D grid, logical order: state tile fastest, then brick; XCD-contiguous
+  // so the state tiles of a brick share its table tile in one L2
   const unsigned lw = xcd_linear();
-  const int b = lw / gridDim.x;
-  const int st_ = lw % gridDim.x;
+  const int b = lw / nst;
+  const int st_ = lw % nst;
   const int64_t jo = boff[b];
   const int nj4 = (bnj[b] + 3) & ~3;
   if (nj4 == 0) return;
@@ -117,9 +103,9 @@ void launch_nl_scatter(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T
   if (c.nproj == 0) return;
   if constexpr (sizeof(T) == sizeof(typename real_of<T>::type)) {
     const int nbrick = (int)c.boff.size() - 1;
-    dim3 grid((ncol + 63) / 64, nbrick);
-    k_nl_brick<T><<<grid, 256, 0, st>>>(Y, ld, ncol, c.d_boff, c.d_bnj, c.d_bj, (const T*)c.d_bval[ik], Qt, c.p.ns,
-                                       (T)alpha, c.nd);
+    const int nst = (ncol + 63) / 64;
+    k_nl_brick<T><<<(unsigned)nbrick * nst, 256, 0, st>>>(Y, ld, ncol, c.d_boff, c.d_bnj, c.d_bj,
+                                                           (const T*)c.d_bval[ik], Qt, c.p.ns, (T)alpha, c.nd, nst);
     return;
   }
   constexpr int S = 8;

@@ -230,6 +230,56 @@ hcu_status build_structure(Ctx& c) {
         c.bsrc[(c.boff[b] + jl) * kBrick + (p - p0)] = c.csr_src[t];
       }
   }
+  // projection bricks (real blocks only): the function list of each brick
+  // is padded to a multiple of 16 (one matrix-core tile), and the value tile
+  // is stored in operand order [tile][64-point piece][lane][16]: lane l of a
+  // wave holds row 16 tile + l%16 at the 16 consecutive points
+  // piece*64 + 16*(l/16) .. +15, so that each lane's operands are contiguous.
+  c.pboff.assign(1, 0);
+  c.pbnj.clear();
+  c.pbsrc.clear();
+  c.pdest.clear();
+  c.jrow.assign(c.nproj + 1, 0);
+  if (!c.any_complex) {
+    const int npb = (c.nd + kPBrick - 1) / kPBrick;
+    std::vector<int> pbj;   // padded slots, -1 for padding
+    for (int b = 0; b < npb; ++b) {
+      const int p0 = b * kPBrick, p1 = std::min(c.nd, p0 + kPBrick);
+      js.clear();
+      for (int t = c.csr_ptr[p0]; t < c.csr_ptr[p1]; ++t) js.push_back(c.csr_col[t]);
+      std::sort(js.begin(), js.end());
+      js.erase(std::unique(js.begin(), js.end()), js.end());
+      const int nj = (int)js.size();
+      const int njp = (nj + 15) / 16 * 16;
+      c.pbnj.push_back(nj);
+      c.pboff.push_back(c.pboff.back() + njp);
+      for (int t = 0; t < njp; ++t) {
+        pbj.push_back(t < nj ? js[t] : -1);
+        if (t < nj) ++c.jrow[js[t] + 1];
+      }
+    }
+    for (int j = 0; j < c.nproj; ++j) c.jrow[j + 1] += c.jrow[j];
+    c.pdest.assign(pbj.size(), -1);
+    std::vector<int64_t> fill(c.jrow.begin(), c.jrow.end() - 1);
+    for (size_t sl = 0; sl < pbj.size(); ++sl)
+      if (pbj[sl] >= 0) c.pdest[sl] = fill[pbj[sl]]++;
+    c.pbsrc.assign((size_t)c.pboff.back() * kPBrick, -1);
+    for (int b = 0; b < npb; ++b) {
+      const int* jb = pbj.data() + c.pboff[b];
+      const int nj = c.pbnj[b];
+      const int p0 = b * kPBrick, p1 = std::min(c.nd, p0 + kPBrick);
+      const int64_t tile0 = c.pboff[b] / 16;
+      for (int p = p0; p < p1; ++p) {
+        const int pl = p - p0, piece = pl / 64, q = (pl % 64) / 16, kk = pl % 16;
+        for (int t = c.csr_ptr[p]; t < c.csr_ptr[p + 1]; ++t) {
+          const int jl = (int)(std::lower_bound(jb, jb + nj, c.csr_col[t]) - jb);
+          const int64_t lane = q * 16 + jl % 16;
+          const int64_t flat = (((tile0 + jl / 16) * (kPBrick / 64) + piece) * 64 + lane) * 16 + kk;
+          c.pbsrc[flat] = c.csr_src[t];
+        }
+      }
+    }
+  }
   return HCU_OK;
 }
 
@@ -487,6 +537,11 @@ static hcu_status tables_for(Ctx& c) {
       k_gather_csr<T><<<(unsigned)((nbv + 255) / 256), 256, 0, st>>>(cscv, c.d_bsrc, (T*)c.d_bval[ik], nbv);
       HCU_HIP(hipGetLastError());
     }
+    const int64_t npv = (int64_t)c.pbsrc.size();
+    if (npv > 0) {
+      k_gather_csr<T><<<(unsigned)((npv + 255) / 256), 256, 0, st>>>(cscv, c.d_pbsrc, (T*)c.d_pbval[ik], npv);
+      HCU_HIP(hipGetLastError());
+    }
   }
   HCU_HIP(hipStreamSynchronize(st));   // hub_blocks (host) must outlive its copy
   return HCU_OK;
@@ -523,6 +578,11 @@ hcu_status device_tables(Ctx& c) {
   HCU_HIP(up(c.d_bnj, c.bnj.data(), c.bnj.size() * sizeof(int)));
   HCU_HIP(up(c.d_bj, c.bj.data(), c.bj.size() * sizeof(int)));
   HCU_HIP(up(c.d_bsrc, c.bsrc.data(), c.bsrc.size() * sizeof(int64_t)));
+  HCU_HIP(up(c.d_pboff, c.pboff.data(), c.pboff.size() * sizeof(int64_t)));
+  HCU_HIP(up(c.d_pbnj, c.pbnj.data(), c.pbnj.size() * sizeof(int)));
+  HCU_HIP(up(c.d_pbsrc, c.pbsrc.data(), c.pbsrc.size() * sizeof(int64_t)));
+  HCU_HIP(up(c.d_pdest, c.pdest.data(), c.pdest.size() * sizeof(int64_t)));
+  HCU_HIP(up(c.d_jrow, c.jrow.data(), c.jrow.size() * sizeof(int64_t)));
   hcu_status s;
   if (c.any_complex) s = c.mixed ? tables_for<cplx<float>>(c) : tables_for<cplx<double>>(c);
   else s = c.mixed ? tables_for<float>(c) : tables_for<double>(c);

@@ -57,12 +57,11 @@ def counters(path, kernel_sub, counter):
 
 
 def kernel_source_digest():
-    """sha256 of the stencil kernel's sources (the kernel file and the
-    header it includes): a counter record applies only to the code it was
-    taken on."""
+    """sha256 of the stencil kernel's source file: a counter record applies
+    only to the kernel code it was taken on."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("stencil.hip", "common.h"):
+    for f in ("stencil.hip",):
         with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
