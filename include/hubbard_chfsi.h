@@ -320,6 +320,81 @@ hcu_status hcu_batch_chfsi_pass(hcu_batch* b);
  * member reached max_iter. */
 hcu_status hcu_batch_scf(hcu_batch* b, const hcu_scf_opts* opts, hcu_scf_report* reps);
 
+/* ------------------------------------------------------------ learned guess
+ * A start for the Hubbard occupation matrices predicted from each site's
+ * environment, in place of the isolated-atom average occupation with which
+ * the paper begins the SCF (Sec. II.B, initial guess of the occupation
+ * matrices).
+ *
+ * Site descriptor of Hubbard atom I (32 entries per species, table order):
+ *   G[32 S + k] = sum over atoms J of species S and lattice images with
+ *   0 < r < 6.5 bohr of exp(-(r - mu_k)^2 / (2 * 0.25^2)) * (cos(pi r/6.5)+1)/2,
+ *   mu_k = 1 + 5.5 k / 31 bohr, r = |R_J + T - R_I|.
+ * Site frame flag: 1 when the site's apical neighbours without a Hubbard
+ * manifold (r < 4.5 bohr, |dz| < 1 bohr) lie along (1, -1, 0), i.e. the
+ * rutile sublattice rotated by 90 degrees about z; such a site's occupation
+ * matrix is learned in the rotated frame D_loc = M D M^T, M the signed
+ * permutation of the real d orbitals (xy, yz, z^2, xz, x^2-y^2) under
+ * (x, y, z) -> (y, -x, z).
+ * Density shells: c_k = sum_x rho(x) g_k(x) / sum_x g_k(x), g_k(x) = sum over
+ * images of exp(-(|x - R_I - T| - r_k)^2 / (2 * 0.25^2)), r_k = 0.5 + 3.5 k/14
+ * (k = 0..14), rho summed over spins. */
+
+/* desc: device float [nhub][32 * nspecies]; frame: host int [nhub]. */
+hcu_status hcu_descriptor(hcu_ctx* ctx, float* desc, int* frame);
+/* Shell averages of the density of the current orbitals and occupations
+ * (after an SCF or hcu_update_occupations): host double [nhub][15]. */
+hcu_status hcu_shell_density(hcu_ctx* ctx, double* out);
+
+/* Training targets of ctx's Hubbard sites after an SCF: host float
+ * [nhub][30], the 15 upper-triangle entries (row-major) of the spin-averaged
+ * occupation matrix in the site frame, then the 15 density shells. */
+hcu_status hcu_site_targets(hcu_ctx* ctx, float* out);
+
+/* MLP dims[0] -> dims[1] -> ... -> dims[nlayers], SiLU (z / (1 + e^-z))
+ * after every layer but the last.  Parameters: FP32, flat, per layer the
+ * weight W [dims[l+1]][dims[l]] (row-major) followed by the bias.  Inputs
+ * and targets are standardised with per-column means and deviations held by
+ * the object.  Training: loss = mean over rows and outputs of
+ * (y - t_standardised)^2, gradients by the backward pass, Adam (beta1 0.9,
+ * beta2 0.999, eps 1e-8, bias-corrected).  Rows of X / T are selected by a
+ * device index array (NULL = rows 0..batch-1); X [rows][dims[0]] and T
+ * [rows][dims[L]] are device FP32.  Inference in FP32, or with BF16 weights
+ * and activations and FP32 accumulation (bf16 = 1).  An object is bound to
+ * a caller-provided workspace and stream like a context. */
+typedef struct hcu_mlp hcu_mlp;
+hcu_status hcu_mlp_create(const int* dims, int nlayers, int max_batch, hcu_mlp** out);
+void hcu_mlp_destroy(hcu_mlp* m);
+const char* hcu_mlp_last_error(const hcu_mlp* m);
+hcu_status hcu_mlp_param_count(const hcu_mlp* m, int64_t* n);
+hcu_status hcu_mlp_workspace_size(hcu_mlp* m, size_t* bytes);
+hcu_status hcu_mlp_bind(hcu_mlp* m, void* dev, size_t bytes, void* hip_stream);
+/* host float [param_count]; resets the Adam moments */
+hcu_status hcu_mlp_set_params(hcu_mlp* m, const float* params);
+hcu_status hcu_mlp_get_params(hcu_mlp* m, float* params);
+/* host float vectors of lengths dims[0], dims[0], dims[L], dims[L] */
+hcu_status hcu_mlp_set_scaling(hcu_mlp* m, const float* in_mean, const float* in_sd, const float* out_mean,
+                               const float* out_sd);
+hcu_status hcu_mlp_get_scaling(hcu_mlp* m, float* in_mean, float* in_sd, float* out_mean, float* out_sd);
+/* scaling from the column statistics of `rows` device rows (deviations
+ * below 1e-6 are replaced by 1) */
+hcu_status hcu_mlp_fit_scaling(hcu_mlp* m, const float* X, const float* T, int rows);
+/* Y (device float [batch][dims[L]]) = de-standardised network output */
+hcu_status hcu_mlp_forward(hcu_mlp* m, const float* X, int batch, float* Y, int bf16);
+/* loss (host) and its gradient (host float [param_count]) at the current
+ * parameters, without an update */
+hcu_status hcu_mlp_gradient(hcu_mlp* m, const float* X, const float* T, const int* idx, int batch, float* grad,
+                            double* loss);
+/* one Adam step; *loss (if non-NULL) is the loss before the step */
+hcu_status hcu_mlp_train_step(hcu_mlp* m, const float* X, const float* T, const int* idx, int batch, float lr,
+                              double* loss);
+/* Descriptors of ctx's Hubbard sites -> network -> occupation matrices
+ * (first 15 outputs: upper triangle of D_loc, row-major), rotated back,
+ * symmetrised, spectrum clipped to [0, 1], set as the context's D for every
+ * spin.  outputs (optional, host float [nhub][dims[L]]) receives the raw
+ * physical outputs (entries 15..29: predicted density shells). */
+hcu_status hcu_mlp_guess(hcu_ctx* ctx, hcu_mlp* m, int bf16, float* outputs);
+
 #ifdef __cplusplus
 }
 #endif

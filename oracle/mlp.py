@@ -40,6 +40,8 @@ from __future__ import annotations
 
 import numpy as np
 
+import workloads
+
 NG = 32
 MU = 1.0 + 5.5 * np.arange(NG) / (NG - 1)
 WIDTH = 0.25
@@ -154,16 +156,8 @@ def param_count(dims=DIMS):
 
 
 def init_params(seed, dims=DIMS):
-    """Seeded uniform(-1/sqrt(K), 1/sqrt(K)) initialisation (drawn on the host
-    and handed to both implementations)."""
-    rng = np.random.default_rng(seed)
-    out = []
-    for i in range(len(dims) - 1):
-        k, n = dims[i], dims[i + 1]
-        bound = 1.0 / np.sqrt(k)
-        out.append(rng.uniform(-bound, bound, size=n * k))
-        out.append(rng.uniform(-bound, bound, size=n))
-    return np.concatenate(out)
+    """Seeded initial parameters (the shared input generator)."""
+    return workloads.mlp_init_params(seed, dims)
 
 
 def unflatten(theta, dims=DIMS):

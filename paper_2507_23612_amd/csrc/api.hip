@@ -13,7 +13,6 @@
 
 using namespace hcu;
 
-struct hcu_ctx : public Ctx {};
 
 struct hcu_batch {
   std::vector<hcu_ctx*> m;
@@ -599,7 +598,8 @@ hcu_status density_t(Ctx& c, double* rho) {
       launch_density<T>(c, (const T*)c.d_X[sk], c.nd, c.d_occ + (size_t)sk * c.p.ns, g * c.kw[k],
                         c.d_rho + (size_t)s * c.nd, c.stream);
     }
-  HCU_HIP(hipMemcpyAsync(rho, c.d_rho, sizeof(double) * c.p.nspin * c.nd, hipMemcpyDeviceToHost, c.stream));
+  if (rho)
+    HCU_HIP(hipMemcpyAsync(rho, c.d_rho, sizeof(double) * c.p.nspin * c.nd, hipMemcpyDeviceToHost, c.stream));
   HCU_HIP(hipStreamSynchronize(c.stream));
   return HCU_OK;
 }
@@ -833,6 +833,8 @@ hcu_status scf_post(Ctx& c, hcu_scf_step_info* info) {
 }  // namespace
 
 namespace hcu {
+hcu_status compute_density(Ctx& c) { return DISPATCH(c, density_t, c, (double*)nullptr); }
+
 void prof_resolve(Ctx& c) {
   for (auto& pe : c.ev_pending) {
     float ms = 0;

@@ -240,7 +240,9 @@ struct ProfScope {
     return e;
   }
 };
-void prof_resolve(Ctx& c);   // after a stream sync: accumulate and recycle events
+void prof_resolve(Ctx& c);
+// the density of the current orbitals and occupations into d_rho (api.hip)
+hcu_status compute_density(Ctx& c);   // after a stream sync: accumulate and recycle events
 
 inline int sk_index(const Ctx& c, int spin, int ik) { return spin * c.p.nk + ik; }
 inline bool k_complex(const Ctx& c, int ik) {
@@ -340,6 +342,10 @@ void launch_density(const Ctx& c, const T* X, int64_t ld, const double* occ, dou
                     hipStream_t st);
 
 }  // namespace hcu
+
+// the opaque handle of the C ABI
+struct hcu_ctx : public hcu::Ctx {};
+
 
 #define HCU_HIP_CTX(ctx, call)                                               \
   do {                                                                       \

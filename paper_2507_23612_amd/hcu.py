@@ -126,6 +126,24 @@ def load_library(path=LIB_PATH):
         "hcu_batch_last_error": (C.c_char_p, [P]),
         "hcu_batch_chfsi_pass": (C.c_int, [P]),
         "hcu_batch_scf": (C.c_int, [P, C.POINTER(hcu_scf_opts), C.POINTER(hcu_scf_report)]),
+        "hcu_descriptor": (C.c_int, [P, P, C.POINTER(C.c_int)]),
+        "hcu_shell_density": (C.c_int, [P, C.POINTER(C.c_double)]),
+        "hcu_site_targets": (C.c_int, [P, C.POINTER(C.c_float)]),
+        "hcu_mlp_create": (C.c_int, [C.POINTER(C.c_int), C.c_int, C.c_int, C.POINTER(P)]),
+        "hcu_mlp_destroy": (None, [P]),
+        "hcu_mlp_last_error": (C.c_char_p, [P]),
+        "hcu_mlp_param_count": (C.c_int, [P, C.POINTER(C.c_int64)]),
+        "hcu_mlp_workspace_size": (C.c_int, [P, C.POINTER(C.c_size_t)]),
+        "hcu_mlp_bind": (C.c_int, [P, P, C.c_size_t, P]),
+        "hcu_mlp_set_params": (C.c_int, [P, C.POINTER(C.c_float)]),
+        "hcu_mlp_get_params": (C.c_int, [P, C.POINTER(C.c_float)]),
+        "hcu_mlp_set_scaling": (C.c_int, [P] + [C.POINTER(C.c_float)] * 4),
+        "hcu_mlp_get_scaling": (C.c_int, [P] + [C.POINTER(C.c_float)] * 4),
+        "hcu_mlp_fit_scaling": (C.c_int, [P, P, P, C.c_int]),
+        "hcu_mlp_forward": (C.c_int, [P, P, C.c_int, P, C.c_int]),
+        "hcu_mlp_gradient": (C.c_int, [P, P, P, P, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_double)]),
+        "hcu_mlp_train_step": (C.c_int, [P, P, P, P, C.c_int, C.c_float, C.POINTER(C.c_double)]),
+        "hcu_mlp_guess": (C.c_int, [P, P, C.c_int, C.POINTER(C.c_float)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -375,6 +393,26 @@ class HcuContext:
         self._check(self.lib.hcu_get_orbitals(self.h, spin, ik, C.c_void_p(X.data_ptr()), 1))
         return X
 
+    def descriptor(self):
+        """Site descriptors (device float32 tensor [nhub][32 nspecies]) and
+        frame flags (numpy int32 [nhub])."""
+        nsp = len(self.cfg["species"])
+        d = self.torch.empty((max(self.nhub, 1), 32 * nsp), dtype=self.torch.float32, device=self.device)
+        fl = np.zeros(max(self.nhub, 1), np.int32)
+        self._check(self.lib.hcu_descriptor(self.h, C.c_void_p(d.data_ptr()),
+                                            fl.ctypes.data_as(C.POINTER(C.c_int))))
+        return d[:self.nhub], fl[:self.nhub]
+
+    def site_targets(self):
+        out = np.zeros((max(self.nhub, 1), 30), np.float32)
+        self._check(self.lib.hcu_site_targets(self.h, out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out[:self.nhub]
+
+    def shell_density(self):
+        out = np.zeros((max(self.nhub, 1), 15))
+        self._check(self.lib.hcu_shell_density(self.h, _dptr(out)))
+        return out[:self.nhub]
+
     def get_density(self):
         out = np.zeros((self.nspin, self.nd))
         self._check(self.lib.hcu_get_density(self.h, _dptr(out)))
@@ -425,6 +463,117 @@ class HcuBatch:
         if st != HCU_OK and not (st == HCU_NOT_CONVERGED and not raise_on_nonconv):
             self._check(st)
         return [{k: getattr(r, k) for k, _ in hcu_scf_report._fields_} for r in reps]
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class HcuMlp:
+    """The site MLP of the learned occupation guess, bound to a torch
+    workspace on the current stream."""
+
+    def __init__(self, dims, max_batch, device="cuda:0"):
+        import torch
+        self.lib = load_library()
+        self.torch = torch
+        self.dims = list(dims)
+        d = (C.c_int * len(self.dims))(*self.dims)
+        self.h = C.c_void_p()
+        st = self.lib.hcu_mlp_create(d, len(self.dims) - 1, int(max_batch), C.byref(self.h))
+        if st != HCU_OK:
+            msg = self.lib.hcu_mlp_last_error(self.h).decode() if self.h else "create failed"
+            self.lib.hcu_mlp_destroy(self.h)
+            self.h = None
+            raise HcuError(st, msg)
+        n = C.c_int64()
+        self._check(self.lib.hcu_mlp_param_count(self.h, C.byref(n)))
+        self.nparam = n.value
+        nb = C.c_size_t()
+        self._check(self.lib.hcu_mlp_workspace_size(self.h, C.byref(nb)))
+        self.device = torch.device(device)
+        self.ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device)
+        self._check(self.lib.hcu_mlp_bind(self.h, C.c_void_p(ptr), C.c_size_t(nb.value),
+                                          C.c_void_p(self.stream.cuda_stream)))
+
+    def _check(self, st):
+        if st != HCU_OK:
+            raise HcuError(st, self.lib.hcu_mlp_last_error(self.h).decode())
+
+    def close(self):
+        if self.h:
+            self.lib.hcu_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        p = np.ascontiguousarray(np.asarray(theta, np.float32))
+        assert p.size == self.nparam
+        self._check(self.lib.hcu_mlp_set_params(self.h, _fptr(p)))
+
+    def get_params(self):
+        p = np.zeros(self.nparam, np.float32)
+        self._check(self.lib.hcu_mlp_get_params(self.h, _fptr(p)))
+        return p
+
+    def set_scaling(self, in_mean, in_sd, out_mean, out_sd):
+        a = [np.ascontiguousarray(np.asarray(v, np.float32)) for v in (in_mean, in_sd, out_mean, out_sd)]
+        self._check(self.lib.hcu_mlp_set_scaling(self.h, *[_fptr(v) for v in a]))
+
+    def get_scaling(self):
+        a = [np.zeros(self.dims[0], np.float32), np.zeros(self.dims[0], np.float32),
+             np.zeros(self.dims[-1], np.float32), np.zeros(self.dims[-1], np.float32)]
+        self._check(self.lib.hcu_mlp_get_scaling(self.h, *[_fptr(v) for v in a]))
+        return a
+
+    def fit_scaling(self, X, T):
+        assert X.is_cuda and T.is_cuda and X.dtype == self.torch.float32 and T.dtype == self.torch.float32
+        self._check(self.lib.hcu_mlp_fit_scaling(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+                                                 int(X.shape[0])))
+
+    def forward(self, X, bf16=False):
+        X = X.contiguous()
+        Y = self.torch.empty((X.shape[0], self.dims[-1]), dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.hcu_mlp_forward(self.h, C.c_void_p(X.data_ptr()), int(X.shape[0]),
+                                             C.c_void_p(Y.data_ptr()), 1 if bf16 else 0))
+        return Y
+
+    @staticmethod
+    def _idx_ptr(idx):
+        return C.c_void_p(idx.data_ptr()) if idx is not None else C.c_void_p(0)
+
+    def gradient(self, X, T, idx=None, batch=None):
+        batch = int(idx.shape[0]) if idx is not None else int(X.shape[0]) if batch is None else batch
+        g = np.zeros(self.nparam, np.float32)
+        loss = C.c_double()
+        self._check(self.lib.hcu_mlp_gradient(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+                                              self._idx_ptr(idx), batch, _fptr(g), C.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, X, T, idx=None, lr=1e-3, want_loss=True):
+        batch = int(idx.shape[0]) if idx is not None else int(X.shape[0])
+        loss = C.c_double()
+        self._check(self.lib.hcu_mlp_train_step(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+                                                self._idx_ptr(idx), batch, C.c_float(lr),
+                                                C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def guess(self, ctx, bf16=True):
+        """Set ctx's occupation matrices from the network; returns the raw
+        outputs [nhub][dims[-1]]."""
+        out = np.zeros((max(ctx.nhub, 1), self.dims[-1]), np.float32)
+        st = self.lib.hcu_mlp_guess(ctx.h, self.h, 1 if bf16 else 0, _fptr(out))
+        if st != HCU_OK:
+            msg = self.lib.hcu_mlp_last_error(self.h).decode() or self.lib.hcu_last_error(ctx.h).decode()
+            raise HcuError(st, msg)
+        return out[:ctx.nhub]
 
 
 def start_inputs(ctx, cfg, spin=0, ik=0):

@@ -16,4 +16,5 @@ from .tio2 import (  # noqa: F401
     with_kpoints,
     batch_cells,
     species_table,
+    mlp_init_params,
 )

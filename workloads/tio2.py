@@ -236,3 +236,18 @@ def initial_occupation_diag(cfg, spin):
             g = g + (0.1 if spin == 0 else -0.1)
         out.append(g)
     return out
+
+
+def mlp_init_params(seed, dims):
+    """Seeded initial parameters of an MLP with layer widths dims, flat
+    [W1 (dims[1] x dims[0], row-major), b1, W2, b2, ...], each entry uniform
+    in (-1/sqrt(fan_in), 1/sqrt(fan_in))."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(len(dims) - 1):
+        k, n = dims[i], dims[i + 1]
+        bound = 1.0 / np.sqrt(k)
+        out.append(rng.uniform(-bound, bound, size=n * k))
+        out.append(rng.uniform(-bound, bound, size=n))
+    return np.concatenate(out)
+
