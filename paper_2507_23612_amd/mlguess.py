@@ -168,24 +168,34 @@ def summarise(rows):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train", type=int, default=2000, help="training cells (seeds 1000..)")
+    ap.add_argument("--train", type=int, default=2000, help="training cells")
+    ap.add_argument("--seed0", type=int, default=TRAIN_SEED0, help="first training cell seed")
     ap.add_argument("--heldout", type=int, default=200, help="held-out cells (seeds 3000..)")
     ap.add_argument("--epochs", type=int, default=300)
-    ap.add_argument("--data", default=None, help="npz with X, T from an earlier run (skips generation)")
+    ap.add_argument("--gen-only", action="store_true", help="generate and save training data, then stop")
+    ap.add_argument("--data", default=None,
+                    help="comma-separated npz files with X, T from earlier runs (skips generation)")
     ap.add_argument("--save-data", default=None)
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     t0 = time.perf_counter()
     if args.data:
-        z = np.load(args.data)
-        X, T = z["X"], z["T"]
-        gen = {"cells": int(z["ncells"]), "seconds": None}
+        zs = [np.load(f) for f in args.data.split(",")]
+        X = np.concatenate([z["X"] for z in zs])
+        T = np.concatenate([z["T"] for z in zs])
+        gen = {"cells": int(sum(int(z["ncells"]) for z in zs)), "sites": int(X.shape[0]),
+               "seconds": float(sum(float(z["seconds"]) for z in zs)),
+               "iterations_mean": float(np.mean(np.concatenate([z["iterations"] for z in zs])))}
     else:
-        X, T, cells = generate(list(range(TRAIN_SEED0, TRAIN_SEED0 + args.train)))
+        X, T, cells = generate(list(range(args.seed0, args.seed0 + args.train)))
+        its = np.array([c["iterations"] for c in cells])
         gen = {"cells": len(cells), "sites": int(X.shape[0]), "seconds": time.perf_counter() - t0,
-               "iterations_mean": float(np.mean([c["iterations"] for c in cells]))}
+               "iterations_mean": float(its.mean())}
         if args.save_data:
-            np.savez(args.save_data, X=X, T=T, ncells=len(cells))
+            np.savez(args.save_data, X=X, T=T, ncells=len(cells), seconds=gen["seconds"], iterations=its)
+        if args.gen_only:
+            print(json.dumps({"data": gen}), flush=True)
+            return
     t1 = time.perf_counter()
     m, hist = train(X, T, epochs=args.epochs)
     t_train = time.perf_counter() - t1
