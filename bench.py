@@ -37,16 +37,28 @@ WORKLOADS = {
     "c3": "108-atom TiO2-like cell (36 Ti + 72 O), 26.1x26.1x22.4 bohr, grid 108x108x96, 640 states, "
           "Chebyshev degree 16, 12th-order FD, Gamma, spin-unpolarised",
     "c1": "6-atom TiO2-like cell, 8.7x8.7x5.6 bohr, grid 36x36x24, 32 states, Chebyshev degree 20",
+    "c2k": "c2 cell spin-polarised with the shifted 2x2x2 k-point set: 16 complex (spin, k) blocks of "
+           "497664 x 256 in one context, one persistent stencil launch per Chebyshev step over all of them",
 }
 
 
+def make_workload(name):
+    import workloads
+    if name == "c2k":
+        cfg = workloads.with_kpoints(workloads.make_config("c2"))
+        cfg["precision"] = "mixed"
+        return cfg
+    return workloads.make_config(name)
+
+
 def stencil_bytes(cfg, elem):
-    """Algorithmic HBM bytes of one fused Chebyshev-step stencil launch over
-    the block: read Y_i and Y_{i-1}, write Y_{i+1} (3 words per point-state),
-    plus V_loc once."""
+    """Algorithmic HBM bytes of one fused Chebyshev-step stencil launch: read
+    Y_i and Y_{i-1}, write Y_{i+1} (3 words per point-state) for every
+    (spin, k) block of the launch, plus V_loc once per block."""
     nd = int(np.prod(cfg["n"]))
     ns = int(cfg["ns"])
-    return 3 * elem * nd * ns + elem * nd
+    nsk = int(cfg["nspin"]) * len(cfg["kw"])
+    return nsk * (3 * elem * nd * ns + elem * nd)
 
 
 def measured_traffic(config, prec, tile):
@@ -183,17 +195,20 @@ def main():
     if args.batch:
         print(json.dumps(bench_batch(args)), flush=True)
         return
-    cfg = workloads.make_config(args.config)
+    cfg = make_workload(args.config)
     prec = args.precision or cfg["precision"]
     nd = int(np.prod(cfg["n"]))
     ns = int(cfg["ns"])
     m = int(cfg["degree"])
+    nsk = int(cfg["nspin"]) * len(cfg["kw"])
 
     ctx = hcu.HcuContext(cfg, prec)
     ctx.set_hubbard_occupation(hcu.initial_occupation(ctx, cfg))
-    X0, v0 = hcu.start_inputs(ctx, cfg)
-    ctx.set_start(0, 0, X0, v0)
-    del X0, v0
+    for sp in range(ctx.nspin):
+        for ik in range(ctx.nk):
+            X0, v0 = hcu.start_inputs(ctx, cfg, sp, ik)
+            ctx.set_start(sp, ik, X0, v0)
+            del X0, v0
     torch.cuda.synchronize()
     if args.tile:
         tx, tyt, ry, tz = (int(v) for v in args.tile.split(","))
@@ -214,9 +229,9 @@ def main():
     kt = ctx.get_kernel_times()
     ctx.set_profiling(False)
     ms_step = dt / args.steps * 1e3
-    value = nd * ns * (m + 1) / (dt / args.steps) / 1e9
+    value = nsk * nd * ns * (m + 1) / (dt / args.steps) / 1e9
 
-    elem = 4 if prec == "mixed" else 8
+    elem = (4 if prec == "mixed" else 8) * (2 if ctx.complex else 1)
     bytes_launch = stencil_bytes(cfg, elem)
     st_ms = kt["stencil_ms"] / max(kt["stencil_launches"], 1)
     achieved = bytes_launch / (st_ms * 1e-3) / 1e9
@@ -224,7 +239,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(args.config, prec, tile),
-                "kernel": "k_stencil (12th-order FD stencil + V_loc + Chebyshev three-term step)",
+                "kernel": ("k_stencil_batch (persistent, all (spin, k) blocks)" if nsk > 1 else "k_stencil")
+                          + " (12th-order FD stencil + V_loc + Chebyshev three-term step)",
                 "avg_launch_ms": round(st_ms, 4), "algorithmic_bytes_per_launch": int(bytes_launch),
                 "tile": tile}
     breakdown = {k: round(v / args.steps, 3) for k, v in kt.items() if k.endswith("_ms")}
@@ -232,7 +248,8 @@ def main():
     out = {"metric": METRIC, "value": round(value, 3), "unit": "Gpts·states/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32" if prec == "mixed" else "f64", "data": "synthetic",
+           "dtype": ("c64" if prec == "mixed" else "c128") if ctx.complex else ("f32" if prec == "mixed" else "f64"),
+           "data": "synthetic",
            "config": {"workload": f"{args.config}: {WORKLOADS.get(args.config, args.config)}",
                       "precision": prec, "nd": nd, "ns": ns, "degree": m},
            "roofline": roofline, "kernel_ms_per_step": breakdown, "stencil_tuning": tuning}
@@ -241,9 +258,11 @@ def main():
         ctx2 = hcu.HcuContext(cfg, prec)
         ctx2.set_tuning(tuning["tile_x"], tuning["tile_yt"], tuning["ry"], tuning["tile_z"])
         ctx2.set_hubbard_occupation(hcu.initial_occupation(ctx2, cfg))
-        X0, v0 = hcu.start_inputs(ctx2, cfg)
-        ctx2.set_start(0, 0, X0, v0)
-        del X0, v0
+        for sp in range(ctx2.nspin):
+            for ik in range(ctx2.nk):
+                X0, v0 = hcu.start_inputs(ctx2, cfg, sp, ik)
+                ctx2.set_start(sp, ik, X0, v0)
+                del X0, v0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         tol_d = 1e-5 if prec == "mixed" else 1e-7

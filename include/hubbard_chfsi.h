@@ -300,6 +300,19 @@ hcu_status hcu_get_orbitals(hcu_ctx* ctx, int spin, int ik, void* dst, int on_de
  * for nspin = 2; rho = (2/nspin) sum_k w_k sum_j f_j |x_j|^2. */
 hcu_status hcu_get_density(hcu_ctx* ctx, double* rho);
 
+/* ------------------------------------------------------------ save / resume
+ * Snapshot of the SCF state in a caller-owned host buffer: input occupation
+ * matrices and the Pulay history (Sec. II.B mixing), iteration counter and
+ * convergence bookkeeping, filter bounds per (spin, k), last eigenvalues,
+ * occupations and energies, and the orbital blocks.  A context of the same
+ * problem (same shape, precision and real/complex type) that loads it
+ * continues with hcu_scf_step exactly as the saved one would have.
+ * Errors: HCU_NOT_BOUND, HCU_INVALID_ARG (buffer too small, foreign or
+ * corrupt state, shape mismatch). */
+hcu_status hcu_state_size(const hcu_ctx* ctx, size_t* bytes);
+hcu_status hcu_save_state(hcu_ctx* ctx, void* host, size_t bytes);
+hcu_status hcu_load_state(hcu_ctx* ctx, const void* host, size_t bytes);
+
 /* ---------------------------------------------------------------- batches
  * Independent problems (cells of different size, each with its spins and
  * k-points) advanced together: in every Chebyshev step the stencil of every

@@ -126,6 +126,9 @@ def load_library(path=LIB_PATH):
         "hcu_batch_last_error": (C.c_char_p, [P]),
         "hcu_batch_chfsi_pass": (C.c_int, [P]),
         "hcu_batch_scf": (C.c_int, [P, C.POINTER(hcu_scf_opts), C.POINTER(hcu_scf_report)]),
+        "hcu_state_size": (C.c_int, [P, C.POINTER(C.c_size_t)]),
+        "hcu_save_state": (C.c_int, [P, P, C.c_size_t]),
+        "hcu_load_state": (C.c_int, [P, P, C.c_size_t]),
         "hcu_descriptor": (C.c_int, [P, P, C.POINTER(C.c_int)]),
         "hcu_shell_density": (C.c_int, [P, C.POINTER(C.c_double)]),
         "hcu_site_targets": (C.c_int, [P, C.POINTER(C.c_float)]),
@@ -392,6 +395,18 @@ class HcuContext:
         X = self.torch.empty((self.ns, self.nd), dtype=self.dtype, device=self.device)
         self._check(self.lib.hcu_get_orbitals(self.h, spin, ik, C.c_void_p(X.data_ptr()), 1))
         return X
+
+    def save_state(self):
+        """The SCF state as a host byte array."""
+        n = C.c_size_t()
+        self._check(self.lib.hcu_state_size(self.h, C.byref(n)))
+        buf = np.zeros(n.value, np.uint8)
+        self._check(self.lib.hcu_save_state(self.h, C.c_void_p(buf.ctypes.data), n))
+        return buf
+
+    def load_state(self, buf):
+        buf = np.ascontiguousarray(buf, np.uint8)
+        self._check(self.lib.hcu_load_state(self.h, C.c_void_p(buf.ctypes.data), C.c_size_t(buf.size)))
 
     def descriptor(self):
         """Site descriptors (device float32 tensor [nhub][32 nspecies]) and

@@ -60,4 +60,29 @@ def test_create_validates_on_host():
     # compute calls before binding report HCU_NOT_BOUND
     assert lib.hcu_chfsi_pass(h, 0, 0) == hcu.HCU_NOT_BOUND
     assert lib.hcu_apply_h(h, 0, 0, None, None, 1, 10) == hcu.HCU_NOT_BOUND
+    assert lib.hcu_state_size(h, ctypes.byref(n)) == hcu.HCU_NOT_BOUND
+    assert lib.hcu_save_state(h, None, 0) == hcu.HCU_INVALID_ARG
+    assert lib.hcu_descriptor(h, None, None) == hcu.HCU_INVALID_ARG
     lib.hcu_destroy(h)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_batch_and_mlp_validate_on_host():
+    from paper_2507_23612_amd import hcu
+    lib = hcu.load_library()
+    h = ctypes.c_void_p()
+    assert lib.hcu_batch_create(None, 0, ctypes.byref(h)) == hcu.HCU_INVALID_ARG
+    m = ctypes.c_void_p()
+    dims = (ctypes.c_int * 4)(64, 128, 128, 30)
+    assert lib.hcu_mlp_create(dims, 0, 16, ctypes.byref(m)) == hcu.HCU_INVALID_ARG
+    assert lib.hcu_mlp_create(dims, 3, 16, ctypes.byref(m)) == hcu.HCU_OK
+    n = ctypes.c_int64()
+    assert lib.hcu_mlp_param_count(m, ctypes.byref(n)) == hcu.HCU_OK
+    assert n.value == 64 * 128 + 128 + 128 * 128 + 128 + 128 * 30 + 30
+    # compute before binding
+    assert lib.hcu_mlp_forward(m, None, 1, None, 0) == hcu.HCU_NOT_BOUND
+    lib.hcu_mlp_destroy(m)
+    bad = (ctypes.c_int * 4)(64, 0, 128, 30)
+    assert lib.hcu_mlp_create(bad, 3, 16, ctypes.byref(m)) == hcu.HCU_INVALID_ARG
+    assert lib.hcu_mlp_last_error(m)
+    lib.hcu_mlp_destroy(m)
