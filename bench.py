@@ -84,7 +84,7 @@ def measured_traffic(config, prec, tile):
         return None
 
 
-def cpu_baseline(cfg, nstates=8, degree=16):
+def cpu_baseline(cfg, nstates=24, degree=16):
     """The oracle's Chebyshev filter on a bounded sample of the workload:
     `nstates` states of the same grid and operator, degree-`degree` filter."""
     import psutil
