@@ -107,6 +107,60 @@ def cpu_baseline(cfg, nstates=24, degree=16):
                       f"{dt:.1f} s on host cores"}
 
 
+MODEL = os.path.join(ROOT, "paper_2507_23612_amd", "models", "site_mlp_c5.npz")
+
+
+def bench_scf_compare(args):
+    """Held-out c5 cells (seeds 3000..): SCF in FP64 from the isolated-atom
+    start (tolerances 1e-7) against SCF in mixed precision from the learned
+    start (BF16 inference; ||dD|| < 1e-5, |dF|/atom < 1e-7), cells converged
+    together in one batch per setting.  Reports both wall times and the
+    largest |F_mixed - F_fp64| per atom."""
+    import torch
+    import workloads
+    from paper_2507_23612_amd import hcu, mlguess
+    if not os.path.exists(MODEL):
+        raise FileNotFoundError(f"{MODEL} missing: train it with python -m paper_2507_23612_amd.mlguess --save-model")
+    seeds = list(range(mlguess.HELDOUT_SEED0, mlguess.HELDOUT_SEED0 + args.cells))
+    cfgs = [workloads.make_config("c5", seed=s) for s in seeds]
+    m = mlguess.load_model(MODEL)
+
+    def run(precision, learned, tol_d):
+        ctxs = [mlguess._context(c, precision) for c in cfgs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for ctx, cfg in zip(ctxs, cfgs):
+            if learned:
+                m.guess(ctx, bf16=True)
+            else:
+                ctx.set_hubbard_occupation(hcu.initial_occupation(ctx, cfg))
+        b = hcu.HcuBatch(ctxs)
+        reps = b.scf(max_iter=100, tol_d=tol_d, tol_f=1e-7, raise_on_nonconv=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        b.close()
+        for ctx in ctxs:
+            ctx.close()
+        return reps, dt
+
+    r64, t64 = run("fp64", False, 1e-7)
+    rmx, tmx = run("mixed", True, 1e-5)
+    natom = len(cfgs[0]["atom_species"])
+    dF = max(abs(a["F"] - b["F"]) / natom for a, b in zip(r64, rmx))
+    return {"metric": "SCF wall-time to 1e-5 Ha/atom (mixed + learned start vs FP64 + isolated-atom start)",
+            "value": round(tmx, 3), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+            "ms_per_step": round(1e3 * tmx, 1), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{args.cells} held-out c5 cells (24 atoms, 72x72x24, 128 states, jitter 0.1), "
+                                   "converged together in one batch"},
+            "fp64_isolated_atom": {"seconds": round(t64, 3),
+                                   "iterations": [int(r["iterations"]) for r in r64],
+                                   "converged": all(bool(r["converged"]) for r in r64)},
+            "mixed_learned": {"seconds": round(tmx, 3), "iterations": [int(r["iterations"]) for r in rmx],
+                              "converged": all(bool(r["converged"]) for r in rmx)},
+            "speedup": round(t64 / tmx, 3), "max_abs_dF_per_atom_Ha": dF}
+
+
 def bench_batch(args):
     """Sixteen independent cells (4 each of 6, 12, 24 and 48 atoms), FP64,
     degree 16: a step is one ChFSI pass (filter + Rayleigh-Ritz) on every
@@ -171,6 +225,10 @@ def main():
                     help="run one plain 1 GiB device copy first (calibrates hardware byte counters)")
     ap.add_argument("--tile", default=None,
                     help="stencil tile shape TX,TYt,RY,TZ (skips the autotuner, e.g. for profiling)")
+    ap.add_argument("--scf-compare", action="store_true",
+                    help="SCF wall time on held-out 24-atom cells: mixed precision with the learned start against "
+                         "FP64 with the isolated-atom start (needs the trained site network)")
+    ap.add_argument("--cells", type=int, default=8, help="cells for --scf-compare")
     ap.add_argument("--batch", action="store_true",
                     help="measure the 16-cell batched workload instead (one persistent stencil launch per "
                          "Chebyshev step over all cells) against the same cells run one after another")
@@ -194,6 +252,9 @@ def main():
         del a, b
     if args.batch:
         print(json.dumps(bench_batch(args)), flush=True)
+        return
+    if args.scf_compare:
+        print(json.dumps(bench_scf_compare(args)), flush=True)
         return
     cfg = make_workload(args.config)
     prec = args.precision or cfg["precision"]

@@ -40,16 +40,12 @@ size_t layout(Ctx& c, char* base) {
   Bump b{base};
   const size_t es = esize(c);
   const int nsk = c.p.nspin * c.p.nk;
-  const int64_t nnz = c.csr_ptr.empty() ? 0 : c.csr_ptr[c.nd];
   const int ns = c.p.ns;
   const int nh = (int)c.hub_atoms.size();
   const int cp = c.any_complex ? 2 : 1;
   b.take(c.d_V, sizeof(double) * c.nd);
   if (c.mixed) b.take(c.d_Vf, sizeof(float) * c.nd);
   b.take(c.d_supp, sizeof(int) * c.supp.size());
-  b.take(c.d_csr_ptr, sizeof(int) * (c.nd + 1));
-  b.take(c.d_csr_col, sizeof(int) * nnz);
-  b.take(c.d_csr_src, sizeof(int64_t) * nnz);
   b.take(c.d_blocks, sizeof(BlockDesc) * c.blocks.size());
   b.take(c.d_nm_lists, sizeof(int) * c.blocks.size());
   b.take(c.d_hub_blocks, sizeof(int) * nh);
@@ -63,13 +59,11 @@ size_t layout(Ctx& c, char* base) {
   b.take(c.d_pdest, sizeof(int64_t) * c.pdest.size());
   b.take(c.d_jrow, sizeof(int64_t) * c.jrow.size());
   c.d_cscv.assign(c.p.nk, nullptr);
-  c.d_csrv.assign(c.p.nk, nullptr);
   c.d_bval.assign(c.p.nk, nullptr);
   c.d_pbval.assign(c.p.nk, nullptr);
   for (int k = 0; k < c.p.nk; ++k) {
     b.take(c.d_pbval[k], es * c.pbsrc.size());
     b.take(c.d_cscv[k], es * c.nval);
-    b.take(c.d_csrv[k], es * nnz);
     b.take(c.d_bval[k], es * c.bsrc.size());
   }
   c.d_coup.assign(c.p.nspin, nullptr);
@@ -94,7 +88,7 @@ size_t layout(Ctx& c, char* base) {
   }
   b.take(c.d_jobs, kBatchJobBytes);
   b.take(c.d_counters, sizeof(unsigned long long) * kNumXcd);
-  b.take(c.d_ppart, es * std::max((size_t)ns * c.nproj * project_max_chunks(c), project_partial_elems(c)));
+  b.take(c.d_ppart, es * project_partial_elems(c));
   c.part_elems = c.any_complex ? gram_partial_elems_c(ns, c.nd) : gram_partial_elems(ns, c.nd);
   b.take(c.d_part, sizeof(double) * c.part_elems);
   b.take(c.d_tiles, sizeof(int2) * gram_tiles(ns, c.any_complex).size());
@@ -235,11 +229,7 @@ template <typename T>
 void project_t(Ctx& c, int spin, int ik, const T* y, int64_t ldy, int ncol) {
   ProfScope ps(c, PK_PROJECT);
   const int sk = sk_index(c, spin, ik);
-  if constexpr (sizeof(T) == sizeof(typename real_of<T>::type))
-    launch_project_brick<T>(c, ik, y, ncol, ldy, c.d_coup[spin], (T*)c.d_P[sk], (T*)c.d_Q[sk], c.stream);
-  else
-    launch_project<T>(c, y, ncol, ldy, (const T*)c.d_cscv[ik], c.d_coup[spin], (T*)c.d_P[sk], (T*)c.d_Q[sk],
-                      c.stream);
+  launch_project_brick<T>(c, ik, y, ncol, ldy, c.d_coup[spin], (T*)c.d_P[sk], (T*)c.d_Q[sk], c.stream);
 }
 
 // Y (already holding the local part) += alpha Phi Q.
@@ -750,8 +740,8 @@ hcu_status autotune_t(Ctx& c, hcu_tuning* best) {
     for (int ti = 0; ti < 3; ++ti) {
       const int TX = txs[ti];
       if (TX > n1 || (ti > 0 && TX == txs[0])) continue;
-      for (int TYt : {1, 2, 3, 4, 6, 8, 12, 16}) {
-        if (TX * TYt > 512 || TX * TYt < 64) continue;
+      for (int TYt : {1, 2, 3, 4, 6, 8, 9, 12, 14, 16}) {
+        if (TX * TYt > 1024 || TX * TYt < 64) continue;
         for (int zd : {1, 2, 4}) {
           const int tz = (n3 + zd - 1) / zd;
           if (zd > 1 && tz < 8) continue;

@@ -152,12 +152,8 @@ struct Ctx {
   double* d_V = nullptr;             // V_loc (double)
   float* d_Vf = nullptr;             // V_loc (float, mixed)
   int* d_supp = nullptr;
-  int* d_csr_ptr = nullptr;
-  int* d_csr_col = nullptr;
-  int64_t* d_csr_src = nullptr;
   BlockDesc* d_blocks = nullptr;
   std::vector<void*> d_cscv;         // per k: csc values (block element type)
-  std::vector<void*> d_csrv;         // per k: csr values
   std::vector<double*> d_coup;       // per spin: coupling matrices
   std::vector<void*> d_X;            // per (spin, k): orbitals nd x ns
   std::vector<void*> d_v0;           // per (spin, k): Lanczos start vector
@@ -300,13 +296,9 @@ template <> struct Mf<float> {
   __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-// proj.hip: P = Phi^H Y dV (per block, chunked support) and Q = C_b P (transposed)
-template <typename T>
-void launch_project(const Ctx& c, const T* Y, int ncol, int64_t ld, const T* cscv, const double* coup,
-                    T* P, T* Q, hipStream_t st);
-int project_max_chunks(const Ctx& c);
-// Real blocks: per-brick partials on the matrix cores (every point of the
-// block read once), then per-function sums over the function's slots.
+// proj.hip: P = Phi^H Y dV and Q = C_b P (transposed)
+// per-brick partials on the matrix cores (every point of the block read
+// once), then per-function sums over the function's slots.
 template <typename T>
 void launch_project_brick(const Ctx& c, int ik, const T* Y, int ncol, int64_t ld, const double* coup, T* P, T* Q,
                           hipStream_t st);

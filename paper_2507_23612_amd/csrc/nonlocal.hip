@@ -6,47 +6,16 @@
 // Sec. II.B: implemented like the nonlocal projectors).  Each point owns its
 // output (no atomics, deterministic).
 //
-// Real blocks: the grid is cut into bricks of 64 consecutive points; each
-// brick stores the dense tile Phi_b over the functions touching it (padded
-// to a multiple of 4).  A workgroup updates one brick for 64 states as a
-// small GEMM on the matrix cores,
+// The grid is cut into bricks of 64 consecutive points; each brick stores
+// the dense tile Phi_b over the functions touching it (padded to a multiple
+// of 4).  A workgroup updates one brick for 64 states as a small GEMM on the
+// matrix cores,
 //   Y_b^T (64 states x 64 pts) += alpha Q^T (64 x nj) Phi_b (nj x 64),
-// so every table value is read once per 64 states.
-// Complex blocks: a thread reads the point's list of (function, value) pairs
-// once and applies it to S states.
+// so every table value is read once per 64 states (complex blocks: four real
+// products per step).
 #include "common.h"
 
 namespace hcu {
-
-template <typename T, int S>
-__global__ __launch_bounds__(256) void k_nl_scatter(T* __restrict__ Y, int64_t ld, int ncol,
-                                                    const int* __restrict__ csr_ptr,
-                                                    const int* __restrict__ csr_col,
-                                                    const T* __restrict__ csr_val, const T* __restrict__ Qt,
-                                                    int ldq, typename real_of<T>::type alpha, int64_t nd) {
-  const int s0 = blockIdx.x * S;
-  const int64_t p = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
-  if (p >= nd) return;
-  const int e0 = csr_ptr[p], e1 = csr_ptr[p + 1];
-  if (e0 == e1) return;
-  const int nh = min(S, ncol - s0);
-  T acc[S];
-  for (int s = 0; s < S; ++s) acc[s] = T(0);
-  const T* __restrict__ Q0 = Qt + s0;
-  for (int e = e0; e < e1; ++e) {
-    const T v = csr_val[e];
-    const T* __restrict__ q = Q0 + (int64_t)csr_col[e] * ldq;
-    if (nh == S) {
-      for (int s = 0; s < S; ++s) acc[s] += v * q[s];
-    } else {
-      for (int s = 0; s < S; ++s)
-        if (s < nh) acc[s] += v * q[s];
-    }
-  }
-  T* __restrict__ Yp = Y + (int64_t)s0 * ld + p;
-  for (int s = 0; s < S; ++s)
-    if (s < nh) Yp[(int64_t)s * ld] += alpha * acc[s];
-}
 
 // Workgroup: 4 waves x 16 states = 64 states, one brick of 64 points.
 // Wave w owns states s0 + 16 w .. + 16 and computes
@@ -97,6 +66,61 @@ __global__ __launch_bounds__(256) void k_nl_brick(T* __restrict__ Y, int64_t ld,
     }
 }
 
+// Complex (Bloch) blocks: the same brick GEMM in four real products,
+//   Re Y += Re(aQ) Re Phi - Im(aQ) Im Phi,  Im Y += Re(aQ) Im Phi + Im(aQ) Re Phi.
+template <typename R>
+__global__ __launch_bounds__(256) void k_nl_brick_c(cplx<R>* __restrict__ Y, int64_t ld, int ncol,
+                                                    const int64_t* __restrict__ boff, const int* __restrict__ bnj,
+                                                    const int* __restrict__ bj, const cplx<R>* __restrict__ bval,
+                                                    const cplx<R>* __restrict__ Qt, int ldq, R alpha, int64_t nd,
+                                                    int nst) {
+  using V = typename Mf<R>::V;
+  const unsigned lw = xcd_linear();
+  const int b = lw / nst;
+  const int st_ = lw % nst;
+  const int64_t jo = boff[b];
+  const int nj4 = (bnj[b] + 3) & ~3;
+  if (nj4 == 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int s0 = st_ * 64 + wave * 16;
+  const int sa = s0 + (lane & 15);
+  const bool sa_ok = sa < ncol;
+  const int64_t p0 = (int64_t)b * kBrick;
+  const cplx<R>* __restrict__ vb = bval + jo * kBrick;
+  V ar[4], ai[4];
+  for (int pt = 0; pt < 4; ++pt)
+    for (int q = 0; q < 4; ++q) {
+      const int s = s0 + Mf<R>::row(lane, q);
+      const int64_t p = p0 + pt * 16 + (lane & 15);
+      const cplx<R> y = (s < ncol && p < nd) ? Y[(int64_t)s * ld + p] : cplx<R>();
+      ar[pt][q] = y.re;
+      ai[pt][q] = y.im;
+    }
+  for (int jj = 0; jj < nj4; jj += 4) {
+    const int jl = jj + (lane >> 4);
+    const int jg = bj[jo + jl];
+    const cplx<R> qv = (sa_ok && jg >= 0) ? Qt[(int64_t)jg * ldq + sa] : cplx<R>();
+    const R qr = alpha * qv.re, qi = alpha * qv.im;
+    cplx<R> f[4];
+    for (int pt = 0; pt < 4; ++pt) f[pt] = vb[(int64_t)jl * kBrick + pt * 16 + (lane & 15)];
+    // independent accumulators between dependent matrix-core ops
+    for (int pt = 0; pt < 4; ++pt) {
+      ar[pt] = Mf<R>::mfma(qr, f[pt].re, ar[pt]);
+      ai[pt] = Mf<R>::mfma(qr, f[pt].im, ai[pt]);
+    }
+    for (int pt = 0; pt < 4; ++pt) {
+      ar[pt] = Mf<R>::mfma(-qi, f[pt].im, ar[pt]);
+      ai[pt] = Mf<R>::mfma(qi, f[pt].re, ai[pt]);
+    }
+  }
+  for (int pt = 0; pt < 4; ++pt)
+    for (int q = 0; q < 4; ++q) {
+      const int s = s0 + Mf<R>::row(lane, q);
+      const int64_t p = p0 + pt * 16 + (lane & 15);
+      if (s < ncol && p < nd) Y[(int64_t)s * ld + p] = cplx<R>(ar[pt][q], ai[pt][q]);
+    }
+}
+
 template <typename T>
 void launch_nl_scatter(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T* Qt, double alpha,
                        hipStream_t st) {
@@ -108,10 +132,14 @@ void launch_nl_scatter(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T
                                                            (const T*)c.d_bval[ik], Qt, c.p.ns, (T)alpha, c.nd, nst);
     return;
   }
-  constexpr int S = 8;
-  dim3 grid((ncol + S - 1) / S, (unsigned)((c.nd + 255) / 256));
-  k_nl_scatter<T, S><<<grid, 256, 0, st>>>(Y, ld, ncol, c.d_csr_ptr, c.d_csr_col, (const T*)c.d_csrv[ik], Qt,
-                                            c.p.ns, (typename real_of<T>::type)alpha, c.nd);
+  else {
+    using R = typename real_of<T>::type;
+    const int nbrick = (int)c.boff.size() - 1;
+    const int nst = (ncol + 63) / 64;
+    k_nl_brick_c<R><<<(unsigned)nbrick * nst, 256, 0, st>>>(Y, ld, ncol, c.d_boff, c.d_bnj, c.d_bj,
+                                                            (const T*)c.d_bval[ik], Qt, c.p.ns, (R)alpha, c.nd, nst);
+    return;
+  }
 }
 
 

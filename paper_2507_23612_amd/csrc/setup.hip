@@ -230,7 +230,7 @@ hcu_status build_structure(Ctx& c) {
         c.bsrc[(c.boff[b] + jl) * kBrick + (p - p0)] = c.csr_src[t];
       }
   }
-  // projection bricks (real blocks only): the function list of each brick
+  // projection bricks: the function list of each brick
   // is padded to a multiple of 16 (one matrix-core tile), and the value tile
   // is stored in operand order [tile][64-point piece][lane][16]: lane l of a
   // wave holds row 16 tile + l%16 at the 16 consecutive points
@@ -240,7 +240,7 @@ hcu_status build_structure(Ctx& c) {
   c.pbsrc.clear();
   c.pdest.clear();
   c.jrow.assign(c.nproj + 1, 0);
-  if (!c.any_complex) {
+  {
     const int npb = (c.nd + kPBrick - 1) / kPBrick;
     std::vector<int> pbj;   // padded slots, -1 for padding
     for (int b = 0; b < npb; ++b) {
@@ -514,7 +514,6 @@ static hcu_status tables_for(Ctx& c) {
   int* d_hb = (int*)c.d_red;   // scratch (sized >= nblocks ints)
   if (!hub_blocks.empty())
     HCU_HIP(hipMemcpyAsync(d_hb, hub_blocks.data(), hub_blocks.size() * sizeof(int), hipMemcpyHostToDevice, st));
-  int64_t nnz = c.csr_ptr[c.nd];
   for (int ik = 0; ik < c.p.nk; ++ik) {
     T* cscv = (T*)c.d_cscv[ik];
     if (nblk > 0 && maxs > 0) {
@@ -526,10 +525,6 @@ static hcu_status tables_for(Ctx& c) {
     }
     if (c.p.lowdin && !hub_blocks.empty()) {
       k_lowdin<T><<<(int)hub_blocks.size(), 256, 0, st>>>(c.d_blocks, d_hb, cscv, c.dv);
-      HCU_HIP(hipGetLastError());
-    }
-    if (nnz > 0) {
-      k_gather_csr<T><<<(unsigned)((nnz + 255) / 256), 256, 0, st>>>(cscv, c.d_csr_src, (T*)c.d_csrv[ik], nnz);
       HCU_HIP(hipGetLastError());
     }
     const int64_t nbv = (int64_t)c.bsrc.size();
@@ -564,11 +559,6 @@ hcu_status device_tables(Ctx& c) {
   HCU_HIP(hipStreamSynchronize(st));   // d_red is reused below
   if (!c.supp.empty())
     HCU_HIP(hipMemcpyAsync(c.d_supp, c.supp.data(), c.supp.size() * sizeof(int), hipMemcpyHostToDevice, st));
-  HCU_HIP(hipMemcpyAsync(c.d_csr_ptr, c.csr_ptr.data(), c.csr_ptr.size() * sizeof(int), hipMemcpyHostToDevice, st));
-  if (!c.csr_col.empty()) {
-    HCU_HIP(hipMemcpyAsync(c.d_csr_col, c.csr_col.data(), c.csr_col.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    HCU_HIP(hipMemcpyAsync(c.d_csr_src, c.csr_src.data(), c.csr_src.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
-  }
   if (!c.blocks.empty())
     HCU_HIP(hipMemcpyAsync(c.d_blocks, c.blocks.data(), c.blocks.size() * sizeof(BlockDesc), hipMemcpyHostToDevice, st));
   auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {

@@ -225,6 +225,22 @@ __global__ __launch_bounds__(512) void k_stencil(const T* __restrict__ Yin, cons
   stencil_item<T, RT, R, RY>(Yin, Yprev, Yout, V, a, tile, zc, s, smem_raw);
 }
 
+// Large-workgroup form (up to 1024 threads, e.g. a 72 x 12 tile with one
+// point per thread): fewer halo rows per tile row at the price of a
+// 128-register budget, so only the light variants (real blocks, RY = 1 in
+// FP64, RY <= 2 in FP32) use it.
+template <typename T, typename RT, int R, int RY>
+__global__ __launch_bounds__(1024) void k_stencil_big(const T* __restrict__ Yin, const T* __restrict__ Yprev,
+                                                      T* __restrict__ Yout, const RT* __restrict__ V,
+                                                      const KArgs<RT> a) {
+  extern __shared__ unsigned char smem_raw[];
+  const unsigned lw = xcd_linear();
+  const int tile = lw % gridDim.x;
+  const int zc = (lw / gridDim.x) % gridDim.y;
+  const int64_t s = lw / (gridDim.x * gridDim.y);
+  stencil_item<T, RT, R, RY>(Yin, Yprev, Yout, V, a, tile, zc, s, smem_raw);
+}
+
 // Persistent form over a list of jobs (blocks of possibly different grids):
 // the item space [0, total) is cut into kNumXcd contiguous ranges with one
 // counter each; workgroup w starts on range w % kNumXcd (the XCD it runs on)
@@ -266,9 +282,16 @@ __global__ __launch_bounds__(512) void k_stencil_batch(const SJob<RT>* __restric
 // thread along y, tz planes per workgroup.  Tuned values (hcu_autotune) win.
 struct StencilShape { int TX, TYt, RY, tz; };
 
+// workgroups above 512 threads run k_stencil_big (128 registers per thread)
+static bool big_ok(const Ctx& c, int RY) {
+  if (c.any_complex) return false;
+  return c.mixed ? RY <= 2 : RY == 1;
+}
+
 static bool shape_ok(const Ctx& c, const StencilShape& sh, int R) {
   const int n1 = c.p.n[0], n2 = c.p.n[1];
-  if (sh.TX < 1 || sh.TX > n1 || sh.TYt < 1 || sh.TX * sh.TYt > 512) return false;
+  if (sh.TX < 1 || sh.TX > n1 || sh.TYt < 1 || sh.TX * sh.TYt > 1024) return false;
+  if (sh.TX * sh.TYt > 512 && !big_ok(c, sh.RY)) return false;
   if (sh.RY != 1 && sh.RY != 2 && sh.RY != 4) return false;
   const int TY = sh.TYt * sh.RY;
   if (TY > n2) return false;
@@ -304,6 +327,15 @@ static StencilShape pick_tiles(const Ctx& c, int ncol, int elem) {
 template <typename T, typename RT, int R>
 static void launch_r(int RY, const KArgs<RT>& a, dim3 grid, dim3 block, size_t lds, const T* Yin, const T* Yprev,
                      T* Yout, const RT* V, hipStream_t st) {
+  if constexpr (sizeof(T) == sizeof(RT)) {
+    if (block.x * block.y > 512) {
+      if (RY == 2)
+        k_stencil_big<T, RT, R, 2><<<grid, block, lds, st>>>(Yin, Yprev, Yout, V, a);
+      else
+        k_stencil_big<T, RT, R, 1><<<grid, block, lds, st>>>(Yin, Yprev, Yout, V, a);
+      return;
+    }
+  }
   if (RY == 4)
     k_stencil<T, RT, R, 4><<<grid, block, lds, st>>>(Yin, Yprev, Yout, V, a);
   else if (RY == 2)
@@ -370,6 +402,7 @@ bool batch_shape(const std::vector<const Ctx*>& cs, int ncol, int elem, int& TX,
   const Ctx& c0 = *cs[0];
   StencilShape sh = pick_tiles(c0, ncol, elem);
   auto ok_all = [&](const StencilShape& t) {
+    if (t.TX * t.TYt > 512) return false;   // the persistent kernel is built for 512 threads
     for (const Ctx* c : cs)
       if (!shape_ok(*c, StencilShape{t.TX, t.TYt, t.RY, 1}, c->p.n0)) return false;
     return true;

@@ -151,6 +151,23 @@ def compare(m, seeds, group=8, tol_d=1e-6, tol_f=1e-7, bf16=True, log=print):
     return out
 
 
+def save_model(m, path):
+    """Parameters and scaling of a trained site MLP, with its layer widths."""
+    in_mean, in_sd, out_mean, out_sd = m.get_scaling()
+    np.savez(path, dims=np.array(m.dims, np.int32), params=m.get_params(), in_mean=in_mean, in_sd=in_sd,
+             out_mean=out_mean, out_sd=out_sd)
+
+
+def load_model(path, max_batch=64):
+    """A bound site MLP from a file written by save_model."""
+    from paper_2507_23612_amd import hcu
+    z = np.load(path)
+    m = hcu.HcuMlp(tuple(int(d) for d in z["dims"]), max_batch)
+    m.set_params(z["params"])
+    m.set_scaling(z["in_mean"], z["in_sd"], z["out_mean"], z["out_sd"])
+    return m
+
+
 def summarise(rows):
     ia = np.array([r["it_atomic"] for r in rows], float)
     il = np.array([r["it_learned"] for r in rows], float)
@@ -176,6 +193,7 @@ def main():
     ap.add_argument("--data", default=None,
                     help="comma-separated npz files with X, T from earlier runs (skips generation)")
     ap.add_argument("--save-data", default=None)
+    ap.add_argument("--save-model", default=None, help="write the trained network (npz)")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     t0 = time.perf_counter()
@@ -199,10 +217,12 @@ def main():
     t1 = time.perf_counter()
     m, hist = train(X, T, epochs=args.epochs)
     t_train = time.perf_counter() - t1
-    rows = compare(m, list(range(HELDOUT_SEED0, HELDOUT_SEED0 + args.heldout)))
+    if args.save_model:
+        save_model(m, args.save_model)
+    rows = compare(m, list(range(HELDOUT_SEED0, HELDOUT_SEED0 + args.heldout))) if args.heldout > 0 else []
     res = {"data": gen, "train": {"samples": int(X.shape[0]), "epochs": args.epochs, "seconds": t_train,
                                    "loss_first": hist[0], "loss_last": hist[-1]},
-           "heldout": summarise(rows), "rows": rows}
+           "heldout": summarise(rows) if rows else None, "rows": rows}
     print(json.dumps({k: v for k, v in res.items() if k != "rows"}), flush=True)
     if args.out:
         with open(args.out, "w") as fh:

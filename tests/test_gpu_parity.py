@@ -86,6 +86,29 @@ def test_apply_h_tile_shapes_ragged(shape):
     assert err < 1e-12
 
 
+@pytest.mark.parametrize("precision,shape", [("fp64", (36, 16, 1, 24)), ("fp64", (36, 28, 1, 7)),
+                                             ("mixed", (36, 16, 2, 12)), ("mixed", (36, 20, 1, 24))])
+def test_apply_h_large_workgroups_c1(precision, shape):
+    """Workgroups above 512 threads (the 1024-thread stencil variant), ragged
+    in y, against the oracle."""
+    torch = _torch()
+    cfg = workloads.make_config("c1")
+    ctx = _ctx(cfg, precision)
+    ctx.set_tuning(*shape)
+    D = _rand_D(1, ctx.nhub, 9)
+    ctx.set_hubbard_occupation(D)
+    X = workloads.random_block(ctx.nd, ctx.ns, 21)
+    Xd = torch.from_numpy(X).cuda().to(ctx.dtype)
+    Yd = torch.empty_like(Xd)
+    ctx.apply_h(Xd, Yd)
+    torch.cuda.synchronize()
+    got = Yd.double().cpu().numpy()
+    want = _oracle_H(cfg, D[0]).apply(X)
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    print(f"[gpu] apply_h c1 {precision} shape {shape}: rel err {err:.2e}", flush=True)
+    assert err < (1e-12 if precision == "fp64" else 2e-6)
+
+
 def test_apply_h_after_autotune_c1():
     torch = _torch()
     cfg = workloads.make_config("c1")
