@@ -171,11 +171,17 @@ def bench_batch(args):
     from paper_2507_23612_amd import hcu
     cells = workloads.batch_cells()
     ctxs = []
+    tuned = {}
     for cfg in cells:
         ctx = hcu.HcuContext(cfg, "fp64")
         ctx.set_hubbard_occupation(hcu.initial_occupation(ctx, cfg))
         X0, v0 = hcu.start_inputs(ctx, cfg)
         ctx.set_start(0, 0, X0, v0)
+        key = (tuple(int(v) for v in cfg["n"]), int(cfg["ns"]))
+        if key not in tuned:                      # one autotuning per cell type
+            tuned[key] = ctx.autotune()
+        t = tuned[key]
+        ctx.set_tuning(t["tile_x"], t["tile_yt"], t["ry"], t["tile_z"])
         ctx.lanczos_bounds()
         ctxs.append(ctx)
     work = sum(int(np.prod(c["n"])) * int(c["ns"]) * (int(c["degree"]) + 1) for c in cells)

@@ -195,6 +195,8 @@ typedef struct hcu_sizes {
   int64_t support_points;   /* sum of block support sizes                    */
   int64_t table_nnz;        /* (point, function) pairs of the per-point table */
   size_t  workspace_bytes;
+  int     max_brick_functions;  /* most functions touching one 256-point brick */
+  int64_t brick_slots;      /* sum over 256-point bricks of their function counts */
 } hcu_sizes;
 hcu_status hcu_get_sizes(const hcu_ctx* ctx, hcu_sizes* out);
 

@@ -34,7 +34,8 @@ struct Bump {
 
 size_t esize(const Ctx& c) { return (c.mixed ? 4 : 8) * (c.any_complex ? 2 : 1); }
 
-constexpr size_t kBatchJobBytes = 256 * 1024;   // job table of a batched stencil launch
+constexpr size_t kBatchJobBytes = 1 << 20;   // stencil job records of one batched pass (~2900 jobs)
+constexpr unsigned long long kPersistentMinItems = 4096;   // smaller batched launches use one workgroup per item
 
 size_t layout(Ctx& c, char* base) {
   Bump b{base};
@@ -376,30 +377,16 @@ struct BProb {
 
 // One filter + Rayleigh-Ritz pass on every problem of a batch in lockstep:
 // per Chebyshev step the projections and scatters run per problem and the
-// stencil of all problems runs as one persistent launch.  All contexts share
-// the stream and the filter degree.
+// stencils of all problems run as persistent launches (one per tile shape).
+// The launches of the whole pass are planned first and their job tables
+// uploaded once, so the host never waits on the device inside the pass.
+// All contexts share the stream and the filter degree.
 template <typename T>
 hcu_status batch_pass_t(std::vector<BProb>& probs, Ctx& lead, double* filter_ms) {
   hipStream_t st = lead.stream;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (filter_ms) {
-    HCU_HIP_CTX(lead, hipEventCreate(&e0));
-    HCU_HIP_CTX(lead, hipEventCreate(&e1));
-    HCU_HIP_CTX(lead, hipEventRecord(e0, st));
-  }
   const int np = (int)probs.size();
   const int m = lead.p.degree;
-  std::vector<std::vector<unsigned char>> tables;   // host job tables, alive until the final sync
-  std::vector<StencilJob> jobs(np);
-  std::vector<const T*> prev(np);
-  std::vector<int> cur(np, 0);
-  auto launch = [&]() -> hcu_status {
-    tables.emplace_back();
-    ProfScope ps(lead, PK_STENCIL);
-    hcu_status s = launch_stencil_batch<T>(jobs, lead.d_jobs, kBatchJobBytes, lead.d_counters, tables.back(), st);
-    if (s != HCU_OK) return fail(lead, s, "batched stencil launch failed (shapes, job table or device)");
-    return HCU_OK;
-  };
+  // ---- plan: per step (1..m filter steps, m+1 = H Y) the jobs of every problem
   for (BProb& q : probs) {
     Ctx& c = *q.c;
     const double a = c.bounds[3 * q.sk], b = c.bounds[3 * q.sk + 1], aL = c.bounds[3 * q.sk + 2];
@@ -408,67 +395,77 @@ hcu_status batch_pass_t(std::vector<BProb>& probs, Ctx& lead, double* filter_ms)
     q.sigma = q.e / (aL - q.cc);
     q.tau = 2.0 / q.sigma;
   }
-  // first step: Y1 = (sigma/e)(H X - c X)
-  for (int i = 0; i < np; ++i) {
-    BProb& q = probs[i];
-    Ctx& c = *q.c;
-    const T* X = (const T*)c.d_X[q.sk];
-    if (c.nproj > 0) project_t<T>(c, q.spin, q.ik, X, c.nd, c.p.ns);
-    jobs[i] = StencilJob{&c, q.ik, X, c.nd, nullptr, 0, c.d_W[3 * q.sk], c.nd, c.p.ns, q.sigma / q.e, q.cc, 0.0};
-    prev[i] = X;
-  }
-  hcu_status s = launch();
-  if (s != HCU_OK) return s;
-  for (int i = 0; i < np; ++i) {
-    BProb& q = probs[i];
-    if (q.c->nproj > 0) scatter_t<T>(*q.c, q.spin, q.ik, (T*)q.c->d_W[3 * q.sk], q.c->nd, q.c->p.ns, q.sigma / q.e);
-  }
-  std::vector<double> alpha(np), beta(np);
-  for (int step = 2; step <= m; ++step) {
+  struct StepOp { const void* in; void* out; double alpha; };   // per (step, problem): scatter target and scale
+  std::vector<std::vector<StepOp>> ops(m + 1, std::vector<StepOp>(np));
+  std::vector<unsigned char> host;
+  std::vector<BatchLaunch> launches;
+  std::vector<size_t> first(m + 2, 0);
+  std::vector<int> cur(np, 0);
+  std::vector<const void*> prev(np);
+  std::vector<StencilJob> jobs(np);
+  for (int step = 1; step <= m + 1; ++step) {
     for (int i = 0; i < np; ++i) {
       BProb& q = probs[i];
       Ctx& c = *q.c;
-      const double s2 = 1.0 / (q.tau - q.sigma);
-      alpha[i] = 2.0 * s2 / q.e;
-      beta[i] = q.sigma * s2;
-      const int out = (cur[i] + 1) % 3;
-      const T* y = (const T*)c.d_W[3 * q.sk + cur[i]];
-      if (c.nproj > 0) project_t<T>(c, q.spin, q.ik, y, c.nd, c.p.ns);
-      jobs[i] = StencilJob{&c, q.ik, y, c.nd, prev[i], c.nd, c.d_W[3 * q.sk + out], c.nd, c.p.ns, alpha[i], q.cc,
-                           beta[i]};
-      q.sigma = s2;
+      void** W = &c.d_W[3 * q.sk];
+      if (step == 1) {
+        const void* X = c.d_X[q.sk];
+        jobs[i] = StencilJob{&c, q.ik, X, c.nd, nullptr, 0, W[0], c.nd, c.p.ns, q.sigma / q.e, q.cc, 0.0};
+        ops[0][i] = StepOp{X, W[0], q.sigma / q.e};
+        prev[i] = X;
+      } else if (step <= m) {
+        const double s2 = 1.0 / (q.tau - q.sigma);
+        const double alpha = 2.0 * s2 / q.e, beta = q.sigma * s2;
+        const int out = (cur[i] + 1) % 3;
+        jobs[i] = StencilJob{&c, q.ik, W[cur[i]], c.nd, prev[i], c.nd, W[out], c.nd, c.p.ns, alpha, q.cc, beta};
+        ops[step - 1][i] = StepOp{W[cur[i]], W[out], alpha};
+        prev[i] = W[cur[i]];
+        cur[i] = out;
+        q.sigma = s2;
+      } else {
+        const int out = (cur[i] + 1) % 3;
+        jobs[i] = StencilJob{&c, q.ik, W[cur[i]], c.nd, nullptr, 0, W[out], c.nd, c.p.ns, 1.0, 0.0, 0.0};
+        ops[m][i] = StepOp{W[cur[i]], W[out], 1.0};
+      }
     }
-    s = launch();
-    if (s != HCU_OK) return s;
+    first[step - 1] = launches.size();
+    hcu_status s = plan_stencil_batch<T>(jobs, host, launches);
+    if (s != HCU_OK) return fail(lead, s, "batched stencil plan failed (shapes)");
+  }
+  first[m + 1] = launches.size();
+  if (host.size() > kBatchJobBytes) return fail(lead, HCU_OOM, "batched stencil job table too large");
+  HCU_HIP_CTX(lead, hipMemcpyAsync(lead.d_jobs, host.data(), host.size(), hipMemcpyHostToDevice, st));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (filter_ms) {
+    HCU_HIP_CTX(lead, hipEventCreate(&e0));
+    HCU_HIP_CTX(lead, hipEventCreate(&e1));
+    HCU_HIP_CTX(lead, hipEventRecord(e0, st));
+  }
+  // ---- execute
+  for (int step = 0; step <= m; ++step) {
     for (int i = 0; i < np; ++i) {
       BProb& q = probs[i];
-      Ctx& c = *q.c;
-      const int out = (cur[i] + 1) % 3;
-      if (c.nproj > 0) scatter_t<T>(c, q.spin, q.ik, (T*)c.d_W[3 * q.sk + out], c.nd, c.p.ns, alpha[i]);
-      prev[i] = (const T*)c.d_W[3 * q.sk + cur[i]];
-      cur[i] = out;
+      if (q.c->nproj > 0) project_t<T>(*q.c, q.spin, q.ik, (const T*)ops[step][i].in, q.c->nd, q.c->p.ns);
     }
+    for (size_t l = first[step]; l < first[step + 1]; ++l) {
+      ProfScope ps(lead, PK_STENCIL);
+      // small launches (a few thousand items) run one workgroup per item: a
+      // persistent grid costs more to start and drain than it balances
+      const bool persistent = launches[l].total >= kPersistentMinItems;
+      hcu_status s = run_stencil_batch<T>(launches[l], lead.d_jobs, persistent ? lead.d_counters : nullptr, st);
+      if (s != HCU_OK) return fail(lead, s, "batched stencil launch failed");
+    }
+    for (int i = 0; i < np; ++i) {
+      BProb& q = probs[i];
+      if (q.c->nproj > 0)
+        scatter_t<T>(*q.c, q.spin, q.ik, (T*)ops[step][i].out, q.c->nd, q.c->p.ns, ops[step][i].alpha);
+    }
+    if (step == m - 1 && filter_ms) HCU_HIP_CTX(lead, hipEventRecord(e1, st));
   }
-  // H Y for Rayleigh-Ritz
+  // ---- Rayleigh-Ritz per problem: Y = the last filter output, H Y = the last output
   for (int i = 0; i < np; ++i) {
     BProb& q = probs[i];
-    Ctx& c = *q.c;
-    const T* Y = (const T*)c.d_W[3 * q.sk + cur[i]];
-    if (c.nproj > 0) project_t<T>(c, q.spin, q.ik, Y, c.nd, c.p.ns);
-    jobs[i] = StencilJob{&c, q.ik, Y, c.nd, nullptr, 0, c.d_W[3 * q.sk + (cur[i] + 1) % 3], c.nd, c.p.ns, 1.0, 0.0, 0.0};
-  }
-  s = launch();
-  if (s != HCU_OK) return s;
-  for (int i = 0; i < np; ++i) {
-    BProb& q = probs[i];
-    Ctx& c = *q.c;
-    if (c.nproj > 0) scatter_t<T>(c, q.spin, q.ik, (T*)c.d_W[3 * q.sk + (cur[i] + 1) % 3], c.nd, c.p.ns, 1.0);
-  }
-  if (filter_ms) HCU_HIP_CTX(lead, hipEventRecord(e1, st));
-  // Rayleigh-Ritz per problem
-  for (int i = 0; i < np; ++i) {
-    BProb& q = probs[i];
-    s = rr_t<T>(*q.c, q.sk, (T*)q.c->d_W[3 * q.sk + cur[i]], (T*)q.c->d_W[3 * q.sk + (cur[i] + 1) % 3]);
+    hcu_status s = rr_t<T>(*q.c, q.sk, (T*)ops[m - 1][i].out, (T*)ops[m][i].out);
     if (s != HCU_OK) return s;
   }
   HCU_HIP_CTX(lead, hipStreamSynchronize(st));
@@ -480,7 +477,7 @@ hcu_status batch_pass_t(std::vector<BProb>& probs, Ctx& lead, double* filter_ms)
     hipEventDestroy(e1);
   }
   for (BProb& q : probs) {
-    s = rr_finish(*q.c, q.sk);
+    hcu_status s = rr_finish(*q.c, q.sk);
     if (s != HCU_OK) return s;
   }
   return HCU_OK;
@@ -955,6 +952,8 @@ hcu_status hcu_get_sizes(const hcu_ctx* ctx, hcu_sizes* out) {
   out->support_points = (int64_t)ctx->supp.size();
   out->table_nnz = ctx->csr_ptr.empty() ? 0 : ctx->csr_ptr[ctx->nd];
   out->workspace_bytes = ctx->ws_bytes;
+  out->max_brick_functions = ctx->pbnj.empty() ? 0 : *std::max_element(ctx->pbnj.begin(), ctx->pbnj.end());
+  out->brick_slots = ctx->jrow.empty() ? 0 : ctx->jrow.back();
   return HCU_OK;
 }
 

@@ -269,12 +269,26 @@ struct StencilJob {
   int ncol;
   double alpha, cshift, beta;
 };
+// Persistent stencil launches over many blocks, planned ahead: plan appends
+// the job records of one step (grouped by tile shape, one launch per group)
+// to `host` and the launches to `out`; after the caller has copied `host` to
+// the device job table, run issues one planned launch: persistent (fixed
+// grid draining per-XCD counters) when d_counters is given, else one
+// workgroup per work item.
+struct BatchLaunch {
+  size_t first;                 // first job record of the launch
+  int njob;
+  unsigned long long total;     // work items
+  int TX, TYt, RY, R;
+};
 template <typename T>
-hcu_status launch_stencil_batch(const std::vector<StencilJob>& jobs, void* d_jobs, size_t jobs_bytes,
-                                unsigned long long* d_counters, std::vector<unsigned char>& host, hipStream_t st);
-size_t stencil_job_bytes(int njobs, bool single);
+hcu_status plan_stencil_batch(const std::vector<StencilJob>& jobs, std::vector<unsigned char>& host,
+                              std::vector<BatchLaunch>& out);
+template <typename T>
+hcu_status run_stencil_batch(const BatchLaunch& L, const void* d_jobs, unsigned long long* d_counters,
+                             hipStream_t st);
 // nonlocal.hip: Y += alpha * sum_j phi_j Qt[j][s]  (64-point bricks on the
-// matrix cores for real blocks, per-point table for complex blocks)
+// matrix cores)
 template <typename T>
 void launch_nl_scatter(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T* Qt, double alpha, hipStream_t st);
 constexpr int kBrick = 64;

@@ -44,19 +44,37 @@ struct SJob {
   unsigned long long item_begin;
 };
 
+// global-memory pointer (job records hold generic pointers; the explicit
+// address space keeps the accesses global rather than flat)
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+
+// element access through generic or global pointers (complex values by
+// components: the class type has no address-space-qualified copy)
+template <typename T> __device__ inline T ldv(const T* p, int64_t i) { return p[i]; }
+template <typename T> __device__ inline T ldv(gptr<const T> p, int64_t i) { return p[i]; }
+template <typename R> __device__ inline cplx<R> ldv(gptr<const cplx<R>> p, int64_t i) {
+  const gptr<const R> q = (gptr<const R>)p;
+  return cplx<R>(q[2 * i], q[2 * i + 1]);
+}
+template <typename T> __device__ inline void stv(gptr<T> p, int64_t i, T v) { p[i] = v; }
+template <typename R> __device__ inline void stv(gptr<cplx<R>> p, int64_t i, cplx<R> v) {
+  const gptr<R> q = (gptr<R>)p;
+  q[2 * i] = v.re;
+  q[2 * i + 1] = v.im;
+}
+
 template <typename T> struct Ld {
   // value of the (possibly wrapped) node with wrap counts w (each -1, 0, 1)
-  template <typename RT>
-  __device__ static inline T get(const T* __restrict__ y, int64_t idx, int wx, int wy, int wz, const KArgs<RT>&) {
+  template <typename RT, typename PT>
+  __device__ static inline T get(PT y, int64_t idx, int wx, int wy, int wz, const KArgs<RT>&) {
     (void)wx; (void)wy; (void)wz;
-    return y[idx];
+    return ldv(y, idx);
   }
 };
 template <typename R> struct Ld<cplx<R>> {
-  template <typename RT>
-  __device__ static inline cplx<R> get(const cplx<R>* __restrict__ y, int64_t idx, int wx, int wy, int wz,
-                                       const KArgs<RT>& a) {
-    cplx<R> v = y[idx];
+  template <typename RT, typename PT>
+  __device__ static inline cplx<R> get(PT y, int64_t idx, int wx, int wy, int wz, const KArgs<RT>& a) {
+    cplx<R> v = ldv(y, idx);
     int w[3] = {wx, wy, wz};
     for (int d = 0; d < 3; ++d) {
       if (w[d] == 0) continue;
@@ -90,7 +108,10 @@ __device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T*
   const int x0 = bx * TX, y0 = by * TY;
   const int zbeg = zc * a.tz;
   const int zend = min(zbeg + a.tz, a.n3);
-  const T* __restrict__ Ys = Yin + s * a.ld;
+  const gptr<const T> Ys = (gptr<const T>)(Yin + s * a.ld);
+  const gptr<const T> Yp = (gptr<const T>)Yprev;
+  const gptr<T> Yo = (gptr<T>)Yout;
+  const gptr<const RT> Vg = (gptr<const RT>)V;
   const int n1 = a.n1, n2 = a.n2, n3 = a.n3;
   const int64_t plane = (int64_t)n1 * n2;
   // x halo from the LDS row itself when the tile spans the whole x range
@@ -180,8 +201,9 @@ __device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T*
     T yp[RY];
     for (int r = 0; r < RY; ++r) {
       const int64_t pidx = gx + (int64_t)n1 * gy[r] + zoff;
-      vv[r] = V[pidx];
-      yp[r] = a.has_prev ? Yprev[s * a.ld_prev + pidx] : T(0);
+      vv[r] = Vg[pidx];
+      yp[r] = T(0);
+      if (a.has_prev) yp[r] = ldv(Yp, s * a.ld_prev + pidx);
     }
     const T* B = cur ? buf1 : buf0;
     for (int r = 0; r < RY; ++r) {
@@ -199,7 +221,7 @@ __device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T*
         acc += (a.center + vv[r] - a.cshift) * q[r][R];
         T out = a.alpha * acc;
         if (a.has_prev) out += (-a.beta) * yp[r];
-        Yout[s * a.ld_out + pidx] = out;
+        stv(Yo, s * a.ld_out + pidx, out);
       }
     }
     for (int r = 0; r < RY; ++r) {
@@ -262,11 +284,17 @@ __global__ __launch_bounds__(512) void k_stencil_batch(const SJob<RT>* __restric
     for (;;) {
       if (tid == 0) s_item = lo + atomicAdd(&counters[r], 1ULL);
       __syncthreads();
-      const unsigned long long item = s_item;
+      // the item is the same for the whole workgroup: make it wave-uniform so
+      // the job record is read into scalar registers
+      const unsigned long long it = s_item;
+      const unsigned long long item =
+          ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(it >> 32)) << 32) |
+          (unsigned)__builtin_amdgcn_readfirstlane((unsigned)it);
       __syncthreads();
       if (item >= hi) break;
       int j = 0;
       while (j + 1 < njobs && jobs[j + 1].item_begin <= item) ++j;
+      j = __builtin_amdgcn_readfirstlane(j);
       const SJob<RT>& jb = jobs[j];
       const unsigned long long loc = item - jb.item_begin;
       const int tile = (int)(loc % jb.ntiles);
@@ -276,6 +304,27 @@ __global__ __launch_bounds__(512) void k_stencil_batch(const SJob<RT>* __restric
                                  smem_raw);
     }
   }
+}
+
+// Grid form over a list of jobs: one workgroup per work item (job, tile,
+// z chunk, state), XCD-contiguous item order, the job found by bisection on
+// the items' start indices.  No counters: the hardware dispatcher balances.
+template <typename T, typename RT, int R, int RY>
+__global__ __launch_bounds__(512) void k_stencil_multi(const SJob<RT>* __restrict__ jobs, int njobs) {
+  extern __shared__ unsigned char smem_raw[];
+  const unsigned long long item = xcd_linear();
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (jobs[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+  }
+  const int j = __builtin_amdgcn_readfirstlane(lo);
+  const SJob<RT>& jb = jobs[j];
+  const unsigned long long loc = item - jb.item_begin;
+  const int tile = (int)(loc % jb.ntiles);
+  const int zc = (int)((loc / jb.ntiles) % jb.nzc);
+  const int64_t s = (int64_t)(loc / ((unsigned long long)jb.ntiles * jb.nzc));
+  stencil_item<T, RT, R, RY>((const T*)jb.Yin, (const T*)jb.Yprev, (T*)jb.Yout, jb.V, jb.a, tile, zc, s, smem_raw);
 }
 
 // Tile shape for a grid: TX threads along x, TYt thread rows, RY points per
@@ -388,6 +437,16 @@ void launch_stencil(const Ctx& c, int ik, const T* Yin, int64_t ld, const T* Ypr
 template <typename T, typename RT, int R>
 static void launch_batch_r(int RY, dim3 grid, dim3 block, size_t lds, const SJob<RT>* jobs, int njobs,
                            unsigned long long total, unsigned long long* counters, hipStream_t st) {
+  if (!counters) {   // one workgroup per item
+    dim3 g((unsigned)total);
+    if (RY == 4)
+      k_stencil_multi<T, RT, R, 4><<<g, block, lds, st>>>(jobs, njobs);
+    else if (RY == 2)
+      k_stencil_multi<T, RT, R, 2><<<g, block, lds, st>>>(jobs, njobs);
+    else
+      k_stencil_multi<T, RT, R, 1><<<g, block, lds, st>>>(jobs, njobs);
+    return;
+  }
   if (RY == 4)
     k_stencil_batch<T, RT, R, 4><<<grid, block, lds, st>>>(jobs, njobs, total, counters);
   else if (RY == 2)
@@ -398,7 +457,7 @@ static void launch_batch_r(int RY, dim3 grid, dim3 block, size_t lds, const SJob
 
 // Common tile shape for a set of grids: the autotuned shape of the first
 // context if every grid admits it, else the largest admissible built-in one.
-bool batch_shape(const std::vector<const Ctx*>& cs, int ncol, int elem, int& TX, int& TYt, int& RY) {
+bool batch_shape(const std::vector<const Ctx*>& cs, int ncol, int elem, int& TX, int& TYt, int& RY, int* TZ) {
   const Ctx& c0 = *cs[0];
   StencilShape sh = pick_tiles(c0, ncol, elem);
   auto ok_all = [&](const StencilShape& t) {
@@ -425,85 +484,110 @@ bool batch_shape(const std::vector<const Ctx*>& cs, int ncol, int elem, int& TX,
     if (!found) return false;
   }
   TX = sh.TX; TYt = sh.TYt; RY = sh.RY;
+  if (TZ) *TZ = sh.tz;
   return true;
 }
 
-// One stencil step for many blocks in one persistent launch.  `host` holds
-// the job table until the caller synchronises the stream.
+// One stencil step for many blocks: the blocks are grouped by the tile shape
+// their own grid prefers (tuned or built-in, at most 512 threads, the job's
+// own z chunk), each group becoming one persistent launch.
 template <typename T>
-hcu_status launch_stencil_batch(const std::vector<StencilJob>& jobs, void* d_jobs, size_t jobs_bytes,
-                                unsigned long long* d_counters, std::vector<unsigned char>& host, hipStream_t st) {
+hcu_status plan_stencil_batch(const std::vector<StencilJob>& jobs, std::vector<unsigned char>& host,
+                              std::vector<BatchLaunch>& out) {
   using RT = typename real_of<T>::type;
   if (jobs.empty()) return HCU_OK;
-  std::vector<const Ctx*> cs;
-  int ncol = 0;
-  for (const StencilJob& j : jobs) { cs.push_back(j.c); ncol = std::max(ncol, j.ncol); }
-  const int R = cs[0]->p.n0;
-  for (const Ctx* c : cs)
-    if (c->p.n0 != R) return HCU_INVALID_ARG;
-  int TX, TYt, RY;
-  if (!batch_shape(cs, ncol, (int)sizeof(T), TX, TYt, RY)) return HCU_INVALID_ARG;
-  const int TY = TYt * RY;
-  host.assign(jobs.size() * sizeof(SJob<RT>), 0);
-  SJob<RT>* hj = reinterpret_cast<SJob<RT>*>(host.data());
-  unsigned long long total = 0;
+  const int R = jobs[0].c->p.n0;
+  for (const StencilJob& j : jobs)
+    if (j.c->p.n0 != R) return HCU_INVALID_ARG;
+  std::vector<StencilShape> shp(jobs.size());
+  std::vector<int> gid(jobs.size());
+  std::vector<StencilShape> groups;
   for (size_t i = 0; i < jobs.size(); ++i) {
-    const StencilJob& j = jobs[i];
-    const Ctx& c = *j.c;
-    StencilCoef sc;
-    fill_stencil_coef(c, j.ik, sc);
-    KArgs<RT> a{};
-    for (int p = 0; p <= kMaxR; ++p) {
-      a.kx[p] = (RT)sc.kin[0][p];
-      a.ky[p] = (RT)sc.kin[1][p];
-      a.kz[p] = (RT)sc.kin[2][p];
+    int TX, TYt, RY, TZ = 0;
+    std::vector<const Ctx*> one{jobs[i].c};
+    if (!batch_shape(one, jobs[i].ncol, (int)sizeof(T), TX, TYt, RY, &TZ)) return HCU_INVALID_ARG;
+    shp[i] = StencilShape{TX, TYt, RY, TZ};
+    int g = -1;
+    for (size_t k = 0; k < groups.size(); ++k)
+      if (groups[k].TX == TX && groups[k].TYt == TYt && groups[k].RY == RY) g = (int)k;
+    if (g < 0) {
+      g = (int)groups.size();
+      groups.push_back(shp[i]);
     }
-    a.center = (RT)sc.center;
-    a.alpha = (RT)j.alpha; a.cshift = (RT)j.cshift; a.beta = (RT)j.beta;
-    for (int d = 0; d < 3; ++d) { a.ph_re[d] = (RT)sc.phase_re[d]; a.ph_im[d] = (RT)sc.phase_im[d]; }
-    a.n1 = c.p.n[0]; a.n2 = c.p.n[1]; a.n3 = c.p.n[2];
-    a.has_prev = (j.Yprev != nullptr && j.beta != 0.0) ? 1 : 0;
-    a.ld = j.ld; a.ld_prev = j.ld_prev; a.ld_out = j.ld_out;
-    a.tiles_x = (a.n1 + TX - 1) / TX;
-    const int tiles = a.tiles_x * ((a.n2 + TY - 1) / TY);
-    a.tz = std::max(8, std::min(a.n3, 24));
-    const int nzc = (a.n3 + a.tz - 1) / a.tz;
-    SJob<RT>& h = hj[i];
-    h.Yin = j.Yin; h.Yprev = j.Yprev; h.Yout = j.Yout;
-    if constexpr (sizeof(RT) == 4) h.V = c.d_Vf; else h.V = c.d_V;
-    h.a = a;
-    h.ntiles = tiles;
-    h.nzc = nzc;
-    h.item_begin = total;
-    total += (unsigned long long)tiles * nzc * j.ncol;
+    gid[i] = g;
   }
-  if (host.size() > jobs_bytes) return HCU_OOM;
-  hipError_t e = hipMemcpyAsync(d_jobs, host.data(), host.size(), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemsetAsync(d_counters, 0, kNumXcd * sizeof(unsigned long long), st);
-  if (e != hipSuccess) return HCU_DEVICE;
-  const size_t lds = 2 * (size_t)(TY + 2 * R) * (TX + 2 * R) * sizeof(T);
-  dim3 grid(1024), block(TX, TYt);
-  const SJob<RT>* dj = reinterpret_cast<const SJob<RT>*>(d_jobs);
-  switch (R) {
-    case 1: launch_batch_r<T, RT, 1>(RY, grid, block, lds, dj, (int)jobs.size(), total, d_counters, st); break;
-    case 2: launch_batch_r<T, RT, 2>(RY, grid, block, lds, dj, (int)jobs.size(), total, d_counters, st); break;
-    case 3: launch_batch_r<T, RT, 3>(RY, grid, block, lds, dj, (int)jobs.size(), total, d_counters, st); break;
-    case 4: launch_batch_r<T, RT, 4>(RY, grid, block, lds, dj, (int)jobs.size(), total, d_counters, st); break;
-    case 5: launch_batch_r<T, RT, 5>(RY, grid, block, lds, dj, (int)jobs.size(), total, d_counters, st); break;
-    default: launch_batch_r<T, RT, 6>(RY, grid, block, lds, dj, (int)jobs.size(), total, d_counters, st); break;
+  size_t slot = host.size() / sizeof(SJob<RT>);
+  host.resize(host.size() + jobs.size() * sizeof(SJob<RT>), 0);
+  SJob<RT>* hj = reinterpret_cast<SJob<RT>*>(host.data());
+  for (size_t g = 0; g < groups.size(); ++g) {
+    const int TX = groups[g].TX, TYt = groups[g].TYt, RY = groups[g].RY;
+    const int TY = TYt * RY;
+    BatchLaunch L{slot, 0, 0, TX, TYt, RY, R};
+    for (size_t i = 0; i < jobs.size(); ++i) {
+      if (gid[i] != (int)g) continue;
+      const StencilJob& j = jobs[i];
+      const Ctx& c = *j.c;
+      StencilCoef sc;
+      fill_stencil_coef(c, j.ik, sc);
+      KArgs<RT> a{};
+      for (int p = 0; p <= kMaxR; ++p) {
+        a.kx[p] = (RT)sc.kin[0][p];
+        a.ky[p] = (RT)sc.kin[1][p];
+        a.kz[p] = (RT)sc.kin[2][p];
+      }
+      a.center = (RT)sc.center;
+      a.alpha = (RT)j.alpha; a.cshift = (RT)j.cshift; a.beta = (RT)j.beta;
+      for (int d = 0; d < 3; ++d) { a.ph_re[d] = (RT)sc.phase_re[d]; a.ph_im[d] = (RT)sc.phase_im[d]; }
+      a.n1 = c.p.n[0]; a.n2 = c.p.n[1]; a.n3 = c.p.n[2];
+      a.has_prev = (j.Yprev != nullptr && j.beta != 0.0) ? 1 : 0;
+      a.ld = j.ld; a.ld_prev = j.ld_prev; a.ld_out = j.ld_out;
+      a.tiles_x = (a.n1 + TX - 1) / TX;
+      const int tiles = a.tiles_x * ((a.n2 + TY - 1) / TY);
+      // the job's own z chunk (tuned or built-in); the fallback shape has none
+      a.tz = shp[i].tz > 1 ? std::min(a.n3, shp[i].tz) : std::max(8, std::min(a.n3, 24));
+      const int nzc = (a.n3 + a.tz - 1) / a.tz;
+      SJob<RT>& h = hj[slot++];
+      h.Yin = j.Yin; h.Yprev = j.Yprev; h.Yout = j.Yout;
+      if constexpr (sizeof(RT) == 4) h.V = c.d_Vf; else h.V = c.d_V;
+      h.a = a;
+      h.ntiles = tiles;
+      h.nzc = nzc;
+      h.item_begin = L.total;
+      L.total += (unsigned long long)tiles * nzc * j.ncol;
+      ++L.njob;
+    }
+    out.push_back(L);
   }
-  return hipGetLastError() == hipSuccess ? HCU_OK : HCU_DEVICE;
+  return HCU_OK;
 }
 
-size_t stencil_job_bytes(int njobs, bool single) {
-  return (size_t)njobs * (single ? sizeof(SJob<float>) : sizeof(SJob<double>));
+template <typename T>
+hcu_status run_stencil_batch(const BatchLaunch& L, const void* d_jobs, unsigned long long* d_counters,
+                             hipStream_t st) {
+  using RT = typename real_of<T>::type;
+  if (d_counters && hipMemsetAsync(d_counters, 0, kNumXcd * sizeof(unsigned long long), st) != hipSuccess)
+    return HCU_DEVICE;
+  const int TY = L.TYt * L.RY;
+  const size_t lds = 2 * (size_t)(TY + 2 * L.R) * (L.TX + 2 * L.R) * sizeof(T);
+  dim3 grid(1024), block(L.TX, L.TYt);
+  const SJob<RT>* dj = reinterpret_cast<const SJob<RT>*>(d_jobs) + L.first;
+  switch (L.R) {
+    case 1: launch_batch_r<T, RT, 1>(L.RY, grid, block, lds, dj, L.njob, L.total, d_counters, st); break;
+    case 2: launch_batch_r<T, RT, 2>(L.RY, grid, block, lds, dj, L.njob, L.total, d_counters, st); break;
+    case 3: launch_batch_r<T, RT, 3>(L.RY, grid, block, lds, dj, L.njob, L.total, d_counters, st); break;
+    case 4: launch_batch_r<T, RT, 4>(L.RY, grid, block, lds, dj, L.njob, L.total, d_counters, st); break;
+    case 5: launch_batch_r<T, RT, 5>(L.RY, grid, block, lds, dj, L.njob, L.total, d_counters, st); break;
+    default: launch_batch_r<T, RT, 6>(L.RY, grid, block, lds, dj, L.njob, L.total, d_counters, st); break;
+  }
+  return hipGetLastError() == hipSuccess ? HCU_OK : HCU_DEVICE;
 }
 
 #define INST_STENCIL(T)                                                                                 \
   template void launch_stencil<T>(const Ctx&, int, const T*, int64_t, const T*, int64_t, T*, int64_t, int, \
                                   double, double, double, hipStream_t);                                \
-  template hcu_status launch_stencil_batch<T>(const std::vector<StencilJob>&, void*, size_t,             \
-                                              unsigned long long*, std::vector<unsigned char>&, hipStream_t);
+  template hcu_status plan_stencil_batch<T>(const std::vector<StencilJob>&, std::vector<unsigned char>&,   \
+                                            std::vector<BatchLaunch>&);                                    \
+  template hcu_status run_stencil_batch<T>(const BatchLaunch&, const void*, unsigned long long*, hipStream_t);
 INST_STENCIL(double)
 INST_STENCIL(float)
 INST_STENCIL(cplx<double>)

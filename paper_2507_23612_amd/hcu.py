@@ -55,7 +55,8 @@ class hcu_scf_step_info(C.Structure):
 
 class hcu_sizes(C.Structure):
     _fields_ = [("nd", C.c_int64), ("nproj", C.c_int), ("nblocks", C.c_int), ("support_points", C.c_int64),
-                ("table_nnz", C.c_int64), ("workspace_bytes", C.c_size_t)]
+                ("table_nnz", C.c_int64), ("workspace_bytes", C.c_size_t), ("max_brick_functions", C.c_int),
+                ("brick_slots", C.c_int64)]
 
 
 class hcu_energies(C.Structure):

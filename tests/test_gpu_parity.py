@@ -346,6 +346,34 @@ def test_apply_h_bloch_kpoint(precision):
     assert err < (1e-12 if precision == "fp64" else 3e-6)
 
 
+@pytest.mark.parametrize("kind", ["fp64", "mixed", "c128", "c64"])
+def test_apply_h_odd_grid_unaligned_rows(kind):
+    """A 15x13x11 grid (2145 points: rows of the block not 16-byte aligned,
+    so the brick kernels take their element-wise load path; last brick
+    ragged) with 9 states, real and complex, against the oracle."""
+    torch = _torch()
+    cfg = workloads.make_config("tiny", seed=3)
+    cfg["n"] = np.array([15, 13, 11], np.int32)
+    cfg["ns"] = 9
+    cplx = kind in ("c128", "c64")
+    if cplx:
+        cfg["kpts"] = np.array([KPT])
+    precision = "fp64" if kind in ("fp64", "c128") else "mixed"
+    ctx = _ctx(cfg, precision)
+    D = _rand_D(1, ctx.nhub, 12)
+    ctx.set_hubbard_occupation(D)
+    X = workloads.random_block(ctx.nd, ctx.ns, 19, complex_=cplx)
+    Xd = torch.from_numpy(X).to(ctx.dtype).cuda()
+    Yd = torch.empty_like(Xd)
+    ctx.apply_h(Xd, Yd)
+    torch.cuda.synchronize()
+    Xr = Xd.cpu().numpy().astype(np.complex128 if cplx else np.float64)
+    want = _oracle_H(cfg, D[0], KPT if cplx else (0.0, 0.0, 0.0)).apply(Xr)
+    err = np.max(np.abs(Yd.cpu().numpy() - want)) / np.max(np.abs(want))
+    print(f"[gpu] apply_h odd grid {kind} rel err {err:.2e}", flush=True)
+    assert err < (1e-12 if precision == "fp64" else 3e-6)
+
+
 def test_scf_spin_polarised_kpoints_tiny():
     """Spin-polarised SCF with the shifted 2x2x2 k-point set (16 complex
     problems in one context) against the oracle's SCF."""
