@@ -305,7 +305,7 @@ hcu_status rr_t(Ctx& c, int sk, T* Y, T* HY) {
   HCU_HIP(hipGetLastError());
   const bool cp = sizeof(T) > sizeof(typename real_of<T>::type);
   {
-    ProfScope ps(c, PK_EIG);
+    ProfScope ps(c, PK_EIG, true);
     hcu_status es = generalized_eig(c, ns, cp, c.d_lam + (size_t)sk * ns);
     if (es != HCU_OK) return es;
   }
@@ -821,6 +821,8 @@ hcu_status scf_post(Ctx& c, hcu_scf_step_info* info) {
 
 namespace hcu {
 hcu_status compute_density(Ctx& c) { return DISPATCH(c, density_t, c, (double*)nullptr); }
+
+thread_local KTimer* g_ktimer = nullptr;
 
 void prof_resolve(Ctx& c) {
   for (auto& pe : c.ev_pending) {

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -215,19 +216,59 @@ struct Ctx {
 enum ProfKind { PK_STENCIL = 0, PK_PROJECT = 1, PK_GRAM = 2, PK_EIG = 3, PK_ROTATE = 4, PK_SCATTER = 5 };
 
 // Scoped timing of the launches queued inside it (no-op unless profiling).
+// Per-phase GPU time.  A marker event recorded between two kernels on a
+// stream can be timestamped before the earlier kernel has drained, so phases
+// made of our own kernels take the begin and end timestamps of the kernels'
+// own dispatches instead (launch_k below: the first kernel of the phase
+// stamps its start, every kernel re-stamps the stop).  Phases made of
+// library calls (the eigensolve) fall back to marker events.
+struct KTimer {
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool started = false;
+};
+extern thread_local KTimer* g_ktimer;
+
+template <typename K, typename... A>
+inline void launch_k(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st, A... args) {
+  KTimer* t = g_ktimer;
+  if (!t) {
+    kernel<<<grid, block, lds, st>>>(args...);
+    return;
+  }
+  hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, st, t->started ? nullptr : t->start, t->stop, 0u,
+                        args...);
+  t->started = true;
+}
+
 struct ProfScope {
   Ctx& c;
   int kind;
-  hipEvent_t e1 = nullptr, e2 = nullptr;
-  ProfScope(Ctx& c_, int k) : c(c_), kind(k) {
+  bool markers;
+  KTimer t, *saved = nullptr;
+  ProfScope(Ctx& c_, int k, bool library_calls = false) : c(c_), kind(k), markers(library_calls) {
     if (!c.prof) return;
-    e1 = take(); e2 = take();
-    hipEventRecord(e1, c.stream);
+    t.start = take();
+    t.stop = take();
+    if (markers) {
+      hipEventRecord(t.start, c.stream);
+    } else {
+      saved = g_ktimer;
+      g_ktimer = &t;
+    }
   }
   ~ProfScope() {
     if (!c.prof) return;
-    hipEventRecord(e2, c.stream);
-    c.ev_pending.push_back({kind, {e1, e2}});
+    if (markers) {
+      hipEventRecord(t.stop, c.stream);
+    } else {
+      g_ktimer = saved;
+      if (!t.started) {   // nothing launched in this phase
+        c.ev_pool.push_back(t.start);
+        c.ev_pool.push_back(t.stop);
+        return;
+      }
+    }
+    c.ev_pending.push_back({kind, {t.start, t.stop}});
   }
   hipEvent_t take() {
     hipEvent_t e;

@@ -35,7 +35,7 @@ constexpr int GP = GK + 1; // padded LDS row
 
 // part layout: [chunk][tile][2][GT][GT] doubles
 template <typename T>
-__global__ __launch_bounds__(256) void k_gram2(const T* __restrict__ Y, const T* __restrict__ HY, int64_t ld,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gram2(const T* __restrict__ Y, const T* __restrict__ HY, int64_t ld,
                                                int n, int64_t nd, int64_t kchunk, const int2* __restrict__ tiles,
                                                int ntiles, double* __restrict__ part) {
   using V = typename Acc<T>::V;
@@ -50,16 +50,32 @@ __global__ __launch_bounds__(256) void k_gram2(const T* __restrict__ Y, const T*
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       for (int r = 0; r < 4; ++r) { accS[a][b][r] = 0; accH[a][b][r] = 0; }
-  for (int64_t k = kb; k < ke; k += GK) {
-    for (int e = threadIdx.x; e < GT * GK; e += 256) {
+  // the next stage's values are loaded into registers while the current
+  // stage is multiplied out of LDS
+  constexpr int PER = GT * GK / 256;
+  T ra[PER], rb[PER], rh[PER];
+  auto fetch = [&](int64_t k) {
+    for (int t = 0; t < PER; ++t) {
+      const int e = threadIdx.x + 256 * t;
       const int col = e / GK, kk = e % GK;
       const int64_t g = k + kk;
       const bool okk = g < ke;
-      sA[col][kk] = (okk && i0 + col < n) ? Y[(int64_t)(i0 + col) * ld + g] : T(0);
-      sB[col][kk] = (okk && j0 + col < n) ? Y[(int64_t)(j0 + col) * ld + g] : T(0);
-      sH[col][kk] = (okk && j0 + col < n) ? HY[(int64_t)(j0 + col) * ld + g] : T(0);
+      ra[t] = (okk && i0 + col < n) ? Y[(int64_t)(i0 + col) * ld + g] : T(0);
+      rb[t] = (okk && j0 + col < n) ? Y[(int64_t)(j0 + col) * ld + g] : T(0);
+      rh[t] = (okk && j0 + col < n) ? HY[(int64_t)(j0 + col) * ld + g] : T(0);
+    }
+  };
+  if (kb < ke) fetch(kb);
+  for (int64_t k = kb; k < ke; k += GK) {
+    for (int t = 0; t < PER; ++t) {
+      const int e = threadIdx.x + 256 * t;
+      const int col = e / GK, kk = e % GK;
+      sA[col][kk] = ra[t];
+      sB[col][kk] = rb[t];
+      sH[col][kk] = rh[t];
     }
     __syncthreads();
+    if (k + GK < ke) fetch(k + GK);
     for (int kk = 0; kk < GK; kk += 4) {
       T af[2], bf[2], hf[2];
       for (int a = 0; a < 2; ++a) af[a] = sA[32 * wi + 16 * a + (lane & 15)][kk + (lane >> 4)];
@@ -150,8 +166,8 @@ void launch_gram2(const Ctx& c, const T* Y, const T* HY, int ncol, int64_t ld, d
   int64_t kc;
   gram_plan(ncol, c.nd, t1, nt, kc, nc);
   const int2* d_tiles = c.d_tiles;
-  k_gram2<T><<<dim3(nt, nc), 256, 0, st>>>(Y, HY, ld, ncol, c.nd, kc, d_tiles, nt, c.d_part);
-  k_gram_reduce<<<dim3(nt, GT * GT / 256, 2), 256, 0, st>>>(c.d_part, nc, nt, d_tiles, ncol, c.dv, S, Hs);
+  launch_k(k_gram2<T>, dim3(nt, nc), 256, 0, st, Y, HY, ld, ncol, c.nd, kc, d_tiles, nt, c.d_part);
+  launch_k(k_gram_reduce, dim3(nt, GT * GT / 256, 2), 256, 0, st, c.d_part, nc, nt, d_tiles, ncol, c.dv, S, Hs);
 }
 
 // X = Y C, computed as X^T = C^T Y^T so that each lane's outputs run along the
@@ -170,15 +186,28 @@ __global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ Y, int64_t
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       for (int r = 0; r < 4; ++r) acc[a][b][r] = 0;
-  for (int i0 = 0; i0 < n; i0 += RK) {
-    for (int e = threadIdx.x; e < RK * GT; e += 256) {
+  // next stage prefetched into registers during the current stage's products
+  constexpr int PER = RK * GT / 256;
+  T ry[PER], rc[PER];
+  auto fetch = [&](int i0) {
+    for (int t = 0; t < PER; ++t) {
+      const int e = threadIdx.x + 256 * t;
       const int ii = e / GT, pp = e % GT;
       const int64_t g = p0 + pp;
-      sY[ii][pp] = (i0 + ii < n && g < nd) ? Y[(int64_t)(i0 + ii) * ld + g] : T(0);
+      ry[t] = (i0 + ii < n && g < nd) ? Y[(int64_t)(i0 + ii) * ld + g] : T(0);
       const int jj = e / RK, i2 = e % RK;
-      sC[i2][jj] = (i0 + i2 < n && j0 + jj < n) ? C[(int64_t)(j0 + jj) * n + i0 + i2] : T(0);
+      rc[t] = (i0 + i2 < n && j0 + jj < n) ? C[(int64_t)(j0 + jj) * n + i0 + i2] : T(0);
+    }
+  };
+  fetch(0);
+  for (int i0 = 0; i0 < n; i0 += RK) {
+    for (int t = 0; t < PER; ++t) {
+      const int e = threadIdx.x + 256 * t;
+      sY[e / GT][e % GT] = ry[t];
+      sC[e % RK][e / RK] = rc[t];
     }
     __syncthreads();
+    if (i0 + RK < n) fetch(i0 + RK);
     for (int kk = 0; kk < RK; kk += 4) {
       T af[2], bf[2];
       for (int a = 0; a < 2; ++a) af[a] = sC[kk + (lane >> 4)][32 * wj + 16 * a + (lane & 15)];
@@ -200,7 +229,7 @@ __global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ Y, int64_t
 template <typename T>
 void launch_rotate(const Ctx& c, const T* Y, int64_t ld, const T* Cb, T* X, int ncol, hipStream_t st) {
   dim3 grid((ncol + GT - 1) / GT, (unsigned)((c.nd + GT - 1) / GT));
-  k_rotate<T><<<grid, 256, 0, st>>>(Y, ld, Cb, X, ncol, c.nd);
+  launch_k(k_rotate<T>, grid, 256, 0, st, Y, ld, Cb, X, ncol, c.nd);
 }
 
 // PX[s][j] = sum_i C[i][s] PY[i][j]  (projections follow the rotation)
@@ -219,7 +248,7 @@ template <typename T>
 void launch_rotate_proj(const Ctx& c, const T* PY, const T* Cb, T* PX, int ncol, hipStream_t st) {
   if (c.nproj == 0) return;
   dim3 grid((c.nproj + 127) / 128, ncol);
-  k_rotate_proj<T><<<grid, 128, 0, st>>>(PY, Cb, PX, ncol, c.nproj);
+  launch_k(k_rotate_proj<T>, grid, 128, 0, st, PY, Cb, PX, ncol, c.nproj);
 }
 
 template void launch_gram2<double>(const Ctx&, const double*, const double*, int, int64_t, double*, double*, hipStream_t);
@@ -330,8 +359,8 @@ void launch_gram2_c(const Ctx& c, const T* Y, const T* HY, int ncol, int64_t ld,
   int64_t kc;
   gram_plan_c(ncol, c.nd, t1, nt, kc, nc);
   const int2* d_tiles = c.d_tiles;
-  k_gram2_c<T><<<dim3(nt, nc), 256, 0, st>>>(Y, HY, ld, ncol, c.nd, kc, d_tiles, nt, c.d_part);
-  k_gram_reduce_c<<<nt, 256, 0, st>>>(c.d_part, nc, nt, d_tiles, ncol, c.dv, S, Hs);
+  launch_k(k_gram2_c<T>, dim3(nt, nc), 256, 0, st, Y, HY, ld, ncol, c.nd, kc, d_tiles, nt, c.d_part);
+  launch_k(k_gram_reduce_c, nt, 256, 0, st, c.d_part, nc, nt, d_tiles, ncol, c.dv, S, Hs);
 }
 
 // X = Y C for complex blocks: workgroup = 64 grid points x 32 states.
@@ -371,7 +400,7 @@ __global__ __launch_bounds__(256) void k_rotate_c(const T* __restrict__ Y, int64
 template <typename T>
 void launch_rotate_c(const Ctx& c, const T* Y, int64_t ld, const T* Cb, T* X, int ncol, hipStream_t st) {
   dim3 grid((ncol + CT - 1) / CT, (unsigned)((c.nd + 63) / 64));
-  k_rotate_c<T><<<grid, 256, 0, st>>>(Y, ld, Cb, X, ncol, c.nd);
+  launch_k(k_rotate_c<T>, grid, 256, 0, st, Y, ld, Cb, X, ncol, c.nd);
 }
 
 template <>

@@ -128,16 +128,16 @@ void launch_nl_scatter(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T
   if constexpr (sizeof(T) == sizeof(typename real_of<T>::type)) {
     const int nbrick = (int)c.boff.size() - 1;
     const int nst = (ncol + 63) / 64;
-    k_nl_brick<T><<<(unsigned)nbrick * nst, 256, 0, st>>>(Y, ld, ncol, c.d_boff, c.d_bnj, c.d_bj,
-                                                           (const T*)c.d_bval[ik], Qt, c.p.ns, (T)alpha, c.nd, nst);
+    launch_k(k_nl_brick<T>, (unsigned)nbrick * nst, 256, 0, st, Y, ld, ncol, c.d_boff, c.d_bnj, c.d_bj,
+             (const T*)c.d_bval[ik], Qt, c.p.ns, (T)alpha, c.nd, nst);
     return;
   }
   else {
     using R = typename real_of<T>::type;
     const int nbrick = (int)c.boff.size() - 1;
     const int nst = (ncol + 63) / 64;
-    k_nl_brick_c<R><<<(unsigned)nbrick * nst, 256, 0, st>>>(Y, ld, ncol, c.d_boff, c.d_bnj, c.d_bj,
-                                                            (const T*)c.d_bval[ik], Qt, c.p.ns, (R)alpha, c.nd, nst);
+    launch_k(k_nl_brick_c<R>, (unsigned)nbrick * nst, 256, 0, st, Y, ld, ncol, c.d_boff, c.d_bnj, c.d_bj,
+             (const T*)c.d_bval[ik], Qt, c.p.ns, (R)alpha, c.nd, nst);
     return;
   }
 }

@@ -285,15 +285,15 @@ void launch_project_brick(const Ctx& c, int ik, const T* Y, int ncol, int64_t ld
   // wide loads of the state rows need 16-byte aligned rows
   const int vec = ((uintptr_t)Y % 16 == 0 && (ld * (int64_t)sizeof(T)) % 16 == 0) ? 1 : 0;
   if constexpr (sizeof(T) == sizeof(typename real_of<T>::type))
-    k_proj_brick<T><<<(unsigned)npb * nst, 256, 0, st>>>(Y, ld, ncol, c.d_pboff, c.d_pbnj, (const T*)c.d_pbval[ik],
-                                                         c.d_pdest, part, c.p.ns, c.nd, nst, vec);
+    launch_k(k_proj_brick<T>, (unsigned)npb * nst, 256, 0, st, Y, ld, ncol, c.d_pboff, c.d_pbnj,
+             (const T*)c.d_pbval[ik], c.d_pdest, part, c.p.ns, c.nd, nst, vec);
   else
-    k_proj_brick_c<typename real_of<T>::type><<<(unsigned)npb * nst, 256, 0, st>>>(
-        Y, ld, ncol, c.d_pboff, c.d_pbnj, (const T*)c.d_pbval[ik], c.d_pdest, part, c.p.ns, c.nd, nst, vec);
+    launch_k(k_proj_brick_c<typename real_of<T>::type>, (unsigned)npb * nst, 256, 0, st, Y, ld, ncol, c.d_pboff,
+             c.d_pbnj, (const T*)c.d_pbval[ik], c.d_pdest, part, c.p.ns, c.nd, nst, vec);
   dim3 g2((ncol + 63) / 64, c.nproj);
-  k_slot_sum<T><<<g2, 1024, 0, st>>>(part, c.p.ns, ncol, c.d_jrow, P, c.nproj, c.dv);
+  launch_k(k_slot_sum<T>, g2, 1024, 0, st, part, c.p.ns, ncol, c.d_jrow, P, c.nproj, c.dv);
   dim3 g3((ncol + 63) / 64, (unsigned)c.blocks.size());
-  k_couple<T><<<g3, 64, 0, st>>>(P, c.d_blocks, ncol, coup, Q, c.nproj, c.p.ns);
+  launch_k(k_couple<T>, g3, 64, 0, st, P, c.d_blocks, ncol, coup, Q, c.nproj, c.p.ns);
 }
 
 template void launch_project_brick<double>(const Ctx&, int, const double*, int, int64_t, const double*, double*,

@@ -379,18 +379,18 @@ static void launch_r(int RY, const KArgs<RT>& a, dim3 grid, dim3 block, size_t l
   if constexpr (sizeof(T) == sizeof(RT)) {
     if (block.x * block.y > 512) {
       if (RY == 2)
-        k_stencil_big<T, RT, R, 2><<<grid, block, lds, st>>>(Yin, Yprev, Yout, V, a);
+        launch_k(k_stencil_big<T, RT, R, 2>, grid, block, lds, st, Yin, Yprev, Yout, V, a);
       else
-        k_stencil_big<T, RT, R, 1><<<grid, block, lds, st>>>(Yin, Yprev, Yout, V, a);
+        launch_k(k_stencil_big<T, RT, R, 1>, grid, block, lds, st, Yin, Yprev, Yout, V, a);
       return;
     }
   }
   if (RY == 4)
-    k_stencil<T, RT, R, 4><<<grid, block, lds, st>>>(Yin, Yprev, Yout, V, a);
+    launch_k(k_stencil<T, RT, R, 4>, grid, block, lds, st, Yin, Yprev, Yout, V, a);
   else if (RY == 2)
-    k_stencil<T, RT, R, 2><<<grid, block, lds, st>>>(Yin, Yprev, Yout, V, a);
+    launch_k(k_stencil<T, RT, R, 2>, grid, block, lds, st, Yin, Yprev, Yout, V, a);
   else
-    k_stencil<T, RT, R, 1><<<grid, block, lds, st>>>(Yin, Yprev, Yout, V, a);
+    launch_k(k_stencil<T, RT, R, 1>, grid, block, lds, st, Yin, Yprev, Yout, V, a);
 }
 
 template <typename T>
@@ -440,19 +440,19 @@ static void launch_batch_r(int RY, dim3 grid, dim3 block, size_t lds, const SJob
   if (!counters) {   // one workgroup per item
     dim3 g((unsigned)total);
     if (RY == 4)
-      k_stencil_multi<T, RT, R, 4><<<g, block, lds, st>>>(jobs, njobs);
+      launch_k(k_stencil_multi<T, RT, R, 4>, g, block, lds, st, jobs, njobs);
     else if (RY == 2)
-      k_stencil_multi<T, RT, R, 2><<<g, block, lds, st>>>(jobs, njobs);
+      launch_k(k_stencil_multi<T, RT, R, 2>, g, block, lds, st, jobs, njobs);
     else
-      k_stencil_multi<T, RT, R, 1><<<g, block, lds, st>>>(jobs, njobs);
+      launch_k(k_stencil_multi<T, RT, R, 1>, g, block, lds, st, jobs, njobs);
     return;
   }
   if (RY == 4)
-    k_stencil_batch<T, RT, R, 4><<<grid, block, lds, st>>>(jobs, njobs, total, counters);
+    launch_k(k_stencil_batch<T, RT, R, 4>, grid, block, lds, st, jobs, njobs, total, counters);
   else if (RY == 2)
-    k_stencil_batch<T, RT, R, 2><<<grid, block, lds, st>>>(jobs, njobs, total, counters);
+    launch_k(k_stencil_batch<T, RT, R, 2>, grid, block, lds, st, jobs, njobs, total, counters);
   else
-    k_stencil_batch<T, RT, R, 1><<<grid, block, lds, st>>>(jobs, njobs, total, counters);
+    launch_k(k_stencil_batch<T, RT, R, 1>, grid, block, lds, st, jobs, njobs, total, counters);
 }
 
 // Common tile shape for a set of grids: the autotuned shape of the first
