@@ -49,13 +49,30 @@ __global__ __launch_bounds__(256) void k_nl_brick(T* __restrict__ Y, int64_t ld,
       const int64_t p = p0 + pt * 16 + (lane & 15);
       acc[pt][q] = (s < ncol && p < nd) ? Y[(int64_t)s * ld + p] : T(0);
     }
-  for (int jj = 0; jj < nj4; jj += 4) {
-    const int jl = jj + (lane >> 4);
-    const int jg = bj[jo + jl];
-    const T a = (sa_ok && jg >= 0) ? alpha * Qt[(int64_t)jg * ldq + sa] : T(0);
-    for (int pt = 0; pt < 4; ++pt) {
-      const T bb = vb[(int64_t)jl * kBrick + pt * 16 + (lane & 15)];
-      acc[pt] = Mf<T>::mfma(a, bb, acc[pt]);
+  // The brick's function indices are read 64 at a time (one per lane) and
+  // handed to the lanes that need them by cross-lane reads, so the loop has
+  // no index -> coefficient load chain; 16 functions per step keep 20
+  // independent loads in flight per lane before the matrix-core ops.
+  int bjl = -1;
+  for (int jj = 0; jj < nj4; jj += 16) {
+    if ((jj & 63) == 0) {
+      const int e = jj + lane;
+      bjl = e < nj4 ? bj[jo + e] : -1;
+    }
+    T a[4], bb[4][4];
+    for (int u = 0; u < 4; ++u) {
+      const int jl = jj + 4 * u + (lane >> 4);
+      a[u] = T(0);
+      for (int pt = 0; pt < 4; ++pt) bb[u][pt] = T(0);
+      if (jj + 4 * u < nj4) {   // wave-uniform
+        const int jg = __shfl(bjl, jl & 63);
+        if (sa_ok && jg >= 0) a[u] = alpha * Qt[(int64_t)jg * ldq + sa];
+        for (int pt = 0; pt < 4; ++pt) bb[u][pt] = vb[(int64_t)jl * kBrick + pt * 16 + (lane & 15)];
+      }
+    }
+    for (int u = 0; u < 4; ++u) {
+      if (jj + 4 * u >= nj4) break;
+      for (int pt = 0; pt < 4; ++pt) acc[pt] = Mf<T>::mfma(a[u], bb[u][pt], acc[pt]);
     }
   }
   for (int pt = 0; pt < 4; ++pt)
