@@ -15,6 +15,7 @@
 #include "common.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace hcu {
 
@@ -23,45 +24,65 @@ namespace hcu {
 // wave w owning 16 states:
 //   part[pdest[slot]][s] = sum_{p in brick} Phi_b[slot][p] y_s(p)
 // as D(16 slots x 16 s) += A(16 slots x 4) B(4 x 16 s) on the matrix cores.
-// The contraction runs over the brick's points in the order
-// p = piece*64 + 16 q + kk, with q = l/16 the depth index of lane l and kk
-// the step: lane l then needs 16 consecutive points of its state row (one
-// 128-byte run for FP64) and 16 consecutive table values (the table is stored
-// in that order), so both operands are read with wide contiguous loads.
+// Operand order, for a group size G (points per lane and load group, a
+// property of the context): at step t (0..15) of a 64-point piece, lane l
+// (depth index q = l/16, column l%16) supplies the point
+//   piece*64 + 4G*(t/G) + G*q + t%G,
+// so each load instruction of a wave covers 4G consecutive points of each of
+// its 16 state rows (4 lanes x G points), and the table, stored in the same
+// order [tile][piece][t/G][lane][t%G], is read as one contiguous run per
+// instruction.  G = 16 (a lane reads 16 consecutive points of its own row)
+// touches 64 cache lines per instruction, and the vector-cache tag rate
+// rather than HBM then limits FP64; G = 2 (16 bytes per lane in FP64) and
+// G = 4 (FP32) cover each line with a quarter of the instructions.
 // Every point-state value is read once per launch.
-template <typename T>
-__device__ __forceinline__ void load16(const T* __restrict__ p, bool vec, int64_t n_ok, T* out) {
-  if (vec && n_ok >= 16) {
-    if constexpr (sizeof(T) == 8) {
-      using D2 = double __attribute__((ext_vector_type(2)));
-      const D2* v = reinterpret_cast<const D2*>(p);
-      for (int i = 0; i < 8; ++i) {
-        const D2 x = v[i];
-        out[2 * i] = x[0];
-        out[2 * i + 1] = x[1];
-      }
-    } else {
+
+// G consecutive values at p (wide loads when vec: state rows and the table
+// start 16-byte aligned and groups start at multiples of G)
+template <typename T, int G>
+__device__ __forceinline__ void ld_group(const T* __restrict__ p, bool vec, T* out) {
+  constexpr int bytes = G * (int)sizeof(T);
+  if (vec) {
+    if constexpr (bytes % 16 == 0) {
       using F4 = float __attribute__((ext_vector_type(4)));
-      const F4* v = reinterpret_cast<const F4*>(p);
-      for (int i = 0; i < 4; ++i) {
-        const F4 x = v[i];
-        out[4 * i] = x[0];
-        out[4 * i + 1] = x[1];
-        out[4 * i + 2] = x[2];
-        out[4 * i + 3] = x[3];
-      }
+      F4 v[bytes / 16];
+      for (int c = 0; c < bytes / 16; ++c) v[c] = reinterpret_cast<const F4*>(p)[c];
+      __builtin_memcpy(out, v, bytes);
+      return;
+    } else if constexpr (bytes == 8) {
+      using F2 = float __attribute__((ext_vector_type(2)));
+      const F2 v = *reinterpret_cast<const F2*>(p);
+      __builtin_memcpy(out, &v, bytes);
+      return;
     }
+  }
+  for (int g = 0; g < G; ++g) out[g] = p[g];
+}
+
+// the 16 step operands of one piece: groups at row + i*stride + off; for
+// state rows (stride 4G, off G q) n_here = points of the piece inside the
+// grid, for the table (stride 64 G, off 0) n_here = 64
+template <typename T, int G>
+__device__ __forceinline__ void load_piece(const T* __restrict__ row, int stride, int off, int64_t n_here, bool vec,
+                                           T* out) {
+  if (n_here >= 64) {
+    for (int i = 0; i < 16 / G; ++i) ld_group<T, G>(row + i * stride + off, vec, out + G * i);
   } else {
-    for (int i = 0; i < 16; ++i) out[i] = i < n_ok ? p[i] : T(0);
+    for (int i = 0; i < 16 / G; ++i)
+      for (int g = 0; g < G; ++g) {
+        const int o = i * stride + off + g;
+        out[G * i + g] = o < n_here ? row[o] : T();
+      }
   }
 }
 
-template <typename T>
+template <typename T, int G>
 __global__ __launch_bounds__(256) void k_proj_brick(const T* __restrict__ Y, int64_t ld, int ncol,
                                                     const int64_t* __restrict__ pboff, const int* __restrict__ pbnj,
                                                     const T* __restrict__ pbval, const int64_t* __restrict__ pdest,
                                                     T* __restrict__ part, int ldp, int64_t nd, int nst, int vec) {
   using V = typename Mf<T>::V;
+  constexpr int P = kPBrick / 64;
   const unsigned lw = xcd_linear();   // 1-D grid: state tile fastest, then brick
   const int b = lw / nst;
   const int st_ = lw % nst;
@@ -75,8 +96,13 @@ __global__ __launch_bounds__(256) void k_proj_brick(const T* __restrict__ Y, int
   const int sb = s0 + (lane & 15);
   const int q = lane >> 4;
   const int64_t p0 = (int64_t)b * kPBrick;
+  // rows of padding states repeat the last state (results never stored)
   const T* __restrict__ Ys = Y + (int64_t)min(sb, ncol - 1) * ld;
   const bool vec_ok = vec != 0;
+  // table run of (tile, piece) for this lane
+  auto trow = [&](int tile, int piece) {
+    return pbval + (((jo / 16 + tile) * P + piece) * (16 / G)) * (64 * G) + lane * G;
+  };
   if constexpr (sizeof(T) == 8) {
     // FP64: up to four slot tiles per sweep, one accumulator each (the
     // register budget keeps three waves per SIMD)
@@ -84,15 +110,14 @@ __global__ __launch_bounds__(256) void k_proj_brick(const T* __restrict__ Y, int
       V acc[4];
       for (int t = 0; t < 4; ++t)
         for (int r = 0; r < 4; ++r) acc[t][r] = T(0);
-      for (int piece = 0; piece < kPBrick / 64; ++piece) {
-        const int64_t pb = p0 + piece * 64 + 16 * q;
+      for (int piece = 0; piece < P; ++piece) {
+        const int64_t pb = p0 + piece * 64;
         T bk[16];
-        const int64_t n_ok = sb < ncol ? max((int64_t)0, min((int64_t)16, nd - pb)) : 0;
-        load16<T>(Ys + pb, vec_ok, n_ok, bk);
+        load_piece<T, G>(Ys + pb, 4 * G, G * q, nd - pb, vec_ok, bk);
         for (int t = 0; t < 4; ++t) {
           if (jg + t >= ntile) break;   // wave-uniform
           T a[16];
-          load16<T>(pbval + ((((jo / 16 + jg + t) * (kPBrick / 64) + piece) * 64 + lane) * 16), true, 16, a);
+          load_piece<T, G>(trow(jg + t, piece), 64 * G, 0, 64, true, a);
           for (int kk = 0; kk < 16; ++kk) acc[t] = Mf<T>::mfma(a[kk], bk[kk], acc[t]);
         }
       }
@@ -113,14 +138,13 @@ __global__ __launch_bounds__(256) void k_proj_brick(const T* __restrict__ Y, int
       for (int t = 0; t < 2; ++t)
         for (int h = 0; h < 2; ++h)
           for (int r = 0; r < 4; ++r) acc[t][h][r] = T(0);
-      for (int piece = 0; piece < kPBrick / 64; ++piece) {
-        const int64_t pb = p0 + piece * 64 + 16 * q;
+      for (int piece = 0; piece < P; ++piece) {
+        const int64_t pb = p0 + piece * 64;
         T bk[16], a0[16], a1[16];
-        const int64_t n_ok = sb < ncol ? max((int64_t)0, min((int64_t)16, nd - pb)) : 0;
-        load16<T>(Ys + pb, vec_ok, n_ok, bk);
-        load16<T>(pbval + ((((jo / 16 + jg) * (kPBrick / 64) + piece) * 64 + lane) * 16), true, 16, a0);
+        load_piece<T, G>(Ys + pb, 4 * G, G * q, nd - pb, vec_ok, bk);
+        load_piece<T, G>(trow(jg, piece), 64 * G, 0, 64, true, a0);
         if (two) {
-          load16<T>(pbval + ((((jo / 16 + jg + 1) * (kPBrick / 64) + piece) * 64 + lane) * 16), true, 16, a1);
+          load_piece<T, G>(trow(jg + 1, piece), 64 * G, 0, 64, true, a1);
           for (int kk = 0; kk < 16; ++kk) {
             acc[0][kk & 1] = Mf<T>::mfma(a0[kk], bk[kk], acc[0][kk & 1]);
             acc[1][kk & 1] = Mf<T>::mfma(a1[kk], bk[kk], acc[1][kk & 1]);
@@ -141,38 +165,7 @@ __global__ __launch_bounds__(256) void k_proj_brick(const T* __restrict__ Y, int
 // Complex (Bloch) blocks: the same brick GEMM with P = Phi^H y, as four
 // real matrix-core products per step,
 //   Re P += Re Phi Re y + Im Phi Im y,   Im P += Re Phi Im y - Im Phi Re y.
-template <typename R>
-__device__ __forceinline__ void load16c(const cplx<R>* __restrict__ p, bool vec, int64_t n_ok, R* re, R* im) {
-  if (vec && n_ok >= 16) {
-    if constexpr (sizeof(R) == 8) {
-      using D2 = double __attribute__((ext_vector_type(2)));
-      const D2* v = reinterpret_cast<const D2*>(p);
-      for (int i = 0; i < 16; ++i) {
-        const D2 x = v[i];
-        re[i] = x[0];
-        im[i] = x[1];
-      }
-    } else {
-      using F4 = float __attribute__((ext_vector_type(4)));
-      const F4* v = reinterpret_cast<const F4*>(p);
-      for (int i = 0; i < 8; ++i) {
-        const F4 x = v[i];
-        re[2 * i] = x[0];
-        im[2 * i] = x[1];
-        re[2 * i + 1] = x[2];
-        im[2 * i + 1] = x[3];
-      }
-    }
-  } else {
-    for (int i = 0; i < 16; ++i) {
-      const cplx<R> x = i < n_ok ? p[i] : cplx<R>();
-      re[i] = x.re;
-      im[i] = x.im;
-    }
-  }
-}
-
-template <typename R>
+template <typename R, int G>
 __global__ __launch_bounds__(256) void k_proj_brick_c(const cplx<R>* __restrict__ Y, int64_t ld, int ncol,
                                                       const int64_t* __restrict__ pboff,
                                                       const int* __restrict__ pbnj,
@@ -180,6 +173,7 @@ __global__ __launch_bounds__(256) void k_proj_brick_c(const cplx<R>* __restrict_
                                                       const int64_t* __restrict__ pdest, cplx<R>* __restrict__ part,
                                                       int ldp, int64_t nd, int nst, int vec) {
   using V = typename Mf<R>::V;
+  constexpr int P = kPBrick / 64;
   const unsigned lw = xcd_linear();
   const int b = lw / nst;
   const int st_ = lw % nst;
@@ -200,17 +194,17 @@ __global__ __launch_bounds__(256) void k_proj_brick_c(const cplx<R>* __restrict_
   for (int jt = 0; jt < ntile; ++jt) {
     V c0, c1, c2, c3;
     for (int r = 0; r < 4; ++r) c0[r] = c1[r] = c2[r] = c3[r] = R(0);
-    for (int piece = 0; piece < kPBrick / 64; ++piece) {
-      const int64_t pb = p0 + piece * 64 + 16 * q;
-      R yr[16], yi[16], fr[16], fi[16];
-      const int64_t n_ok = sb < ncol ? max((int64_t)0, min((int64_t)16, nd - pb)) : 0;
-      load16c<R>(Ys + pb, vec_ok, n_ok, yr, yi);
-      load16c<R>(pbval + ((((jo / 16 + jt) * (kPBrick / 64) + piece) * 64 + lane) * 16), true, 16, fr, fi);
+    for (int piece = 0; piece < P; ++piece) {
+      const int64_t pb = p0 + piece * 64;
+      cplx<R> y[16], f[16];
+      load_piece<cplx<R>, G>(Ys + pb, 4 * G, G * q, nd - pb, vec_ok, y);
+      load_piece<cplx<R>, G>(pbval + (((jo / 16 + jt) * P + piece) * (16 / G)) * (64 * G) + lane * G, 64 * G, 0, 64,
+                             true, f);
       for (int kk = 0; kk < 16; ++kk) {
-        c0 = Mf<R>::mfma(fr[kk], yr[kk], c0);
-        c1 = Mf<R>::mfma(fi[kk], yi[kk], c1);
-        c2 = Mf<R>::mfma(fr[kk], yi[kk], c2);
-        c3 = Mf<R>::mfma(fi[kk], yr[kk], c3);
+        c0 = Mf<R>::mfma(f[kk].re, y[kk].re, c0);
+        c1 = Mf<R>::mfma(f[kk].im, y[kk].im, c1);
+        c2 = Mf<R>::mfma(f[kk].re, y[kk].im, c2);
+        c3 = Mf<R>::mfma(f[kk].im, y[kk].re, c3);
       }
     }
     for (int r = 0; r < 4; ++r) {
@@ -284,12 +278,20 @@ void launch_project_brick(const Ctx& c, int ik, const T* Y, int ncol, int64_t ld
   const int nst = (ncol + 63) / 64;
   // wide loads of the state rows need 16-byte aligned rows
   const int vec = ((uintptr_t)Y % 16 == 0 && (ld * (int64_t)sizeof(T)) % 16 == 0) ? 1 : 0;
-  if constexpr (sizeof(T) == sizeof(typename real_of<T>::type))
-    launch_k(k_proj_brick<T>, (unsigned)npb * nst, 256, 0, st, Y, ld, ncol, c.d_pboff, c.d_pbnj,
-             (const T*)c.d_pbval[ik], c.d_pdest, part, c.p.ns, c.nd, nst, vec);
-  else
-    launch_k(k_proj_brick_c<typename real_of<T>::type>, (unsigned)npb * nst, 256, 0, st, Y, ld, ncol, c.d_pboff,
-             c.d_pbnj, (const T*)c.d_pbval[ik], c.d_pdest, part, c.p.ns, c.nd, nst, vec);
+  auto run = [&](auto g) {
+    constexpr int G = decltype(g)::value;
+    if constexpr (sizeof(T) == sizeof(typename real_of<T>::type))
+      launch_k(k_proj_brick<T, G>, (unsigned)npb * nst, 256, 0, st, Y, ld, ncol, c.d_pboff, c.d_pbnj,
+               (const T*)c.d_pbval[ik], c.d_pdest, part, c.p.ns, c.nd, nst, vec);
+    else
+      launch_k(k_proj_brick_c<typename real_of<T>::type, G>, (unsigned)npb * nst, 256, 0, st, Y, ld, ncol,
+               c.d_pboff, c.d_pbnj, (const T*)c.d_pbval[ik], c.d_pdest, part, c.p.ns, c.nd, nst, vec);
+  };
+  switch (c.pgroup) {
+    case 2: run(std::integral_constant<int, 2>()); break;
+    case 4: run(std::integral_constant<int, 4>()); break;
+    default: run(std::integral_constant<int, 16>()); break;
+  }
   dim3 g2((ncol + 63) / 64, c.nproj);
   launch_k(k_slot_sum<T>, g2, 1024, 0, st, part, c.p.ns, ncol, c.d_jrow, P, c.nproj, c.dv);
   dim3 g3((ncol + 63) / 64, (unsigned)c.blocks.size());

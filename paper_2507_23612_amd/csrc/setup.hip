@@ -232,9 +232,13 @@ hcu_status build_structure(Ctx& c) {
   }
   // projection bricks: the function list of each brick
   // is padded to a multiple of 16 (one matrix-core tile), and the value tile
-  // is stored in operand order [tile][64-point piece][lane][16]: lane l of a
-  // wave holds row 16 tile + l%16 at the 16 consecutive points
-  // piece*64 + 16*(l/16) .. +15, so that each lane's operands are contiguous.
+  // is stored in operand order [tile][64-point piece][step group i][lane][G]:
+  // at steps G i .. G i + G-1 lane l of a wave holds row 16 tile + l%16 at
+  // the G consecutive points from piece*64 + 4G i + G (l/16), which is also
+  // the order in which the lane reads its state row.  G = 2 (16-byte groups
+  // in FP64 and complex FP32) unless every block is real FP32 (G = 4).
+  c.pgroup = (c.mixed && !c.any_complex) ? 4 : 2;
+  const int G = c.pgroup;
   c.pboff.assign(1, 0);
   c.pbnj.clear();
   c.pbsrc.clear();
@@ -270,11 +274,12 @@ hcu_status build_structure(Ctx& c) {
       const int p0 = b * kPBrick, p1 = std::min(c.nd, p0 + kPBrick);
       const int64_t tile0 = c.pboff[b] / 16;
       for (int p = p0; p < p1; ++p) {
-        const int pl = p - p0, piece = pl / 64, q = (pl % 64) / 16, kk = pl % 16;
+        const int pl = p - p0, piece = pl / 64, r = pl % 64;
+        const int i = r / (4 * G), q = (r % (4 * G)) / G, h = r % G;
         for (int t = c.csr_ptr[p]; t < c.csr_ptr[p + 1]; ++t) {
           const int jl = (int)(std::lower_bound(jb, jb + nj, c.csr_col[t]) - jb);
           const int64_t lane = q * 16 + jl % 16;
-          const int64_t flat = (((tile0 + jl / 16) * (kPBrick / 64) + piece) * 64 + lane) * 16 + kk;
+          const int64_t flat = ((((tile0 + jl / 16) * (kPBrick / 64) + piece) * (16 / G) + i) * 64 + lane) * G + h;
           c.pbsrc[flat] = c.csr_src[t];
         }
       }
