@@ -306,7 +306,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(args.config, prec, tile),
-                "kernel": ("k_stencil_batch (persistent, all (spin, k) blocks)" if nsk > 1 else "k_stencil")
+                "kernel": ("k_stencil_batch (persistent, all (spin, k) blocks)" if nsk > 1 else
+                           "k_stencil_big" if tuning["tile_x"] * tuning["tile_yt"] > 512 else "k_stencil")
                           + " (12th-order FD stencil + V_loc + Chebyshev three-term step)",
                 "avg_launch_ms": round(st_ms, 4), "algorithmic_bytes_per_launch": int(bytes_launch),
                 "tile": tile}
