@@ -251,7 +251,7 @@ struct ProfScope {
     t.start = take();
     t.stop = take();
     if (markers) {
-      hipEventRecord(t.start, c.stream);
+      (void)hipEventRecord(t.start, c.stream);
     } else {
       saved = g_ktimer;
       g_ktimer = &t;
@@ -260,7 +260,7 @@ struct ProfScope {
   ~ProfScope() {
     if (!c.prof) return;
     if (markers) {
-      hipEventRecord(t.stop, c.stream);
+      (void)hipEventRecord(t.stop, c.stream);
     } else {
       g_ktimer = saved;
       if (!t.started) {   // nothing launched in this phase
@@ -274,7 +274,7 @@ struct ProfScope {
   hipEvent_t take() {
     hipEvent_t e;
     if (!c.ev_pool.empty()) { e = c.ev_pool.back(); c.ev_pool.pop_back(); }
-    else hipEventCreate(&e);
+    else (void)hipEventCreate(&e);
     return e;
   }
 };
