@@ -22,8 +22,12 @@ namespace hcu {
 // D'(16 s x 16 p) += A'(16 s x 4 j) B'(4 j x 16 p) for the brick's 4 point
 // tiles, with A' = alpha Q^T (lane: s = l%16, j = l/16) and
 // B' = Phi (j = l/16, p = l%16); D' starts from Y and is written back.
+// groups of 4 functions per step; with two groups the kernel fits five
+// waves per SIMD, which hides the load latency better than deeper batches
+constexpr int kScatterU = 2;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_nl_brick(T* __restrict__ Y, int64_t ld, int ncol,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_nl_brick(T* __restrict__ Y, int64_t ld, int ncol,
                                                   const int64_t* __restrict__ boff, const int* __restrict__ bnj,
                                                   const int* __restrict__ bj, const T* __restrict__ bval,
                                                   const T* __restrict__ Qt, int ldq, T alpha, int64_t nd, int nst) {
@@ -51,16 +55,16 @@ __global__ __launch_bounds__(256) void k_nl_brick(T* __restrict__ Y, int64_t ld,
     }
   // The brick's function indices are read 64 at a time (one per lane) and
   // handed to the lanes that need them by cross-lane reads, so the loop has
-  // no index -> coefficient load chain; 16 functions per step keep 20
-  // independent loads in flight per lane before the matrix-core ops.
+  // no index -> coefficient load chain; each step issues all its loads
+  // (4 kScatterU functions) before the matrix-core ops.
   int bjl = -1;
-  for (int jj = 0; jj < nj4; jj += 16) {
+  for (int jj = 0; jj < nj4; jj += 4 * kScatterU) {
     if ((jj & 63) == 0) {
       const int e = jj + lane;
       bjl = e < nj4 ? bj[jo + e] : -1;
     }
-    T a[4], bb[4][4];
-    for (int u = 0; u < 4; ++u) {
+    T a[kScatterU], bb[kScatterU][4];
+    for (int u = 0; u < kScatterU; ++u) {
       const int jl = jj + 4 * u + (lane >> 4);
       a[u] = T(0);
       for (int pt = 0; pt < 4; ++pt) bb[u][pt] = T(0);
@@ -70,7 +74,7 @@ __global__ __launch_bounds__(256) void k_nl_brick(T* __restrict__ Y, int64_t ld,
         for (int pt = 0; pt < 4; ++pt) bb[u][pt] = vb[(int64_t)jl * kBrick + pt * 16 + (lane & 15)];
       }
     }
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kScatterU; ++u) {
       if (jj + 4 * u >= nj4) break;
       for (int pt = 0; pt < 4; ++pt) acc[pt] = Mf<T>::mfma(a[u], bb[u][pt], acc[pt]);
     }
