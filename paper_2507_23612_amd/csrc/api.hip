@@ -101,6 +101,15 @@ size_t layout(Ctx& c, char* base) {
   b.take(c.d_occ, sizeof(double) * (size_t)nsk * ns);
   b.take(c.d_E, sizeof(double) * (size_t)ns * 2);
   b.take(c.d_info, sizeof(int) * 4);
+  c.rr_slots.resize((size_t)std::max(0, std::min(nsk, kRRLanes) - 1));
+  for (Ctx::RRSlot& r : c.rr_slots) {
+    b.take(r.part, sizeof(double) * c.part_elems);
+    b.take(r.S, sizeof(double) * (size_t)ns * ns * cp);
+    b.take(r.Hs, sizeof(double) * (size_t)ns * ns * cp);
+    b.take(r.Cb, es * (size_t)ns * ns);
+    b.take(r.E, sizeof(double) * (size_t)ns * 2);
+    b.take(r.info, sizeof(int) * 4);
+  }
   b.take(c.d_D, sizeof(double) * (size_t)c.p.nspin * nh * 25);
   size_t red = std::max<size_t>(16384 * sizeof(double), sizeof(double) * 8 * (size_t)c.p.natom);
   red = std::max(red, sizeof(int) * c.blocks.size());
@@ -381,6 +390,95 @@ struct BProb {
 // The launches of the whole pass are planned first and their job tables
 // uploaded once, so the host never waits on the device inside the pass.
 // All contexts share the stream and the filter degree.
+// Rayleigh-Ritz of every problem of a pass.  The eigensolves are chains of
+// small library kernels bound by launch latency, so with several problems
+// they run on up to kRRLanes side streams at once: problem i goes to lane
+// i % lanes, the j-th problem of a context uses the context's scratch slot
+// j % lanes (problems that share a slot also share a lane, so they run in
+// order), and the lead stream waits for every lane before it goes on.
+struct RRSwap {   // a context's Rayleigh-Ritz scratch, handle and stream redirected to a slot and lane
+  Ctx& c;
+  hipStream_t st0;
+  rocblas_handle blas0;
+  double *part0, *S0, *Hs0, *E0;
+  void* Cb0;
+  int* info0;
+  RRSwap(Ctx& c_, int slot, hipStream_t lane)
+      : c(c_), st0(c_.stream), blas0(c_.blas), part0(c_.d_part), S0(c_.d_S), Hs0(c_.d_Hs), E0(c_.d_E),
+        Cb0(c_.d_Cb), info0(c_.d_info) {
+    if (slot > 0) {
+      const Ctx::RRSlot& r = c.rr_slots[slot - 1];
+      c.blas = r.blas;
+      c.d_part = r.part;
+      c.d_S = r.S;
+      c.d_Hs = r.Hs;
+      c.d_E = r.E;
+      c.d_Cb = r.Cb;
+      c.d_info = r.info;
+    }
+    c.stream = lane;
+    rocblas_set_stream(c.blas, lane);
+  }
+  ~RRSwap() {
+    if (c.blas == blas0) rocblas_set_stream(c.blas, st0);
+    c.stream = st0;
+    c.blas = blas0;
+    c.d_part = part0;
+    c.d_S = S0;
+    c.d_Hs = Hs0;
+    c.d_E = E0;
+    c.d_Cb = Cb0;
+    c.d_info = info0;
+  }
+};
+
+template <typename T, typename Op>
+hcu_status rr_all_t(std::vector<BProb>& probs, Ctx& lead, const std::vector<Op>& ys, const std::vector<Op>& hys) {
+  const int np = (int)probs.size();
+  const int nl = std::min(np, kRRLanes);
+  if (nl <= 1) {
+    for (int i = 0; i < np; ++i) {
+      hcu_status s = rr_t<T>(*probs[i].c, probs[i].sk, (T*)ys[i].out, (T*)hys[i].out);
+      if (s != HCU_OK) return s;
+    }
+    return HCU_OK;
+  }
+  while ((int)lead.rr_streams.size() < nl) {
+    hipStream_t st;
+    HCU_HIP_CTX(lead, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    lead.rr_streams.push_back(st);
+  }
+  while ((int)lead.rr_events.size() < 1 + nl) {
+    hipEvent_t e;
+    HCU_HIP_CTX(lead, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    lead.rr_events.push_back(e);
+  }
+  HCU_HIP_CTX(lead, hipEventRecord(lead.rr_events[0], lead.stream));
+  for (int l = 0; l < nl; ++l) HCU_HIP_CTX(lead, hipStreamWaitEvent(lead.rr_streams[l], lead.rr_events[0], 0));
+  hcu_status s = HCU_OK;
+  std::vector<std::pair<const Ctx*, int>> seen;
+  for (int i = 0; i < np && s == HCU_OK; ++i) {
+    Ctx& c = *probs[i].c;
+    int j = 0;
+    auto it = std::find_if(seen.begin(), seen.end(), [&](const std::pair<const Ctx*, int>& e) { return e.first == &c; });
+    if (it == seen.end()) seen.push_back({&c, 1});
+    else j = it->second++;
+    const int slot = j % nl;
+    if (slot > (int)c.rr_slots.size()) {
+      s = fail(c, HCU_INVALID_ARG, "no Rayleigh-Ritz scratch slot for this block");
+      break;
+    }
+    RRSwap sw(c, slot, lead.rr_streams[i % nl]);
+    s = rr_t<T>(c, probs[i].sk, (T*)ys[i].out, (T*)hys[i].out);
+  }
+  // the lead stream waits for every lane, also after a failure
+  for (int l = 0; l < nl; ++l) {
+    HCU_HIP_CTX(lead, hipEventRecord(lead.rr_events[1 + l], lead.rr_streams[l]));
+    HCU_HIP_CTX(lead, hipStreamWaitEvent(lead.stream, lead.rr_events[1 + l], 0));
+  }
+  return s;
+}
+
 template <typename T>
 hcu_status batch_pass_t(std::vector<BProb>& probs, Ctx& lead, double* filter_ms) {
   hipStream_t st = lead.stream;
@@ -463,11 +561,8 @@ hcu_status batch_pass_t(std::vector<BProb>& probs, Ctx& lead, double* filter_ms)
     if (step == m - 1 && filter_ms) HCU_HIP_CTX(lead, hipEventRecord(e1, st));
   }
   // ---- Rayleigh-Ritz per problem: Y = the last filter output, H Y = the last output
-  for (int i = 0; i < np; ++i) {
-    BProb& q = probs[i];
-    hcu_status s = rr_t<T>(*q.c, q.sk, (T*)ops[m - 1][i].out, (T*)ops[m][i].out);
-    if (s != HCU_OK) return s;
-  }
+  hcu_status s = rr_all_t<T>(probs, lead, ops[m - 1], ops[m]);
+  if (s != HCU_OK) return s;
   HCU_HIP_CTX(lead, hipStreamSynchronize(st));
   if (filter_ms) {
     float ms = 0;
@@ -933,6 +1028,11 @@ void hcu_destroy(hcu_ctx* ctx) {
   for (auto& pe : ctx->ev_pending) { hipEventDestroy(pe.second.first); hipEventDestroy(pe.second.second); }
   for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
   if (ctx->blas) rocblas_destroy_handle(ctx->blas);
+  for (Ctx::RRSlot& r : ctx->rr_slots)
+    if (r.blas) rocblas_destroy_handle(r.blas);
+  for (hipStream_t st : ctx->rr_streams) (void)hipStreamDestroy(st);
+  for (hipEvent_t e : ctx->rr_events) (void)hipEventDestroy(e);
+  if (ctx->h_info_pinned) (void)hipHostFree(ctx->h_info_pinned);
   delete ctx;
 }
 
@@ -972,6 +1072,14 @@ hcu_status hcu_bind(hcu_ctx* ctx, void* dev_ptr, size_t bytes, void* stream) {
     if (rocblas_create_handle(&c.blas) != rocblas_status_success) return fail(c, HCU_DEVICE, "rocblas handle");
   }
   rocblas_set_stream(c.blas, c.stream);
+  for (Ctx::RRSlot& r : c.rr_slots)
+    if (!r.blas && rocblas_create_handle(&r.blas) != rocblas_status_success)
+      return fail(c, HCU_DEVICE, "rocblas handle");
+  if (!c.h_info_pinned) {
+    HCU_HIP(hipHostMalloc((void**)&c.h_info_pinned, sizeof(int) * c.h_info_store.size(), hipHostMallocDefault));
+    std::copy(c.h_info_store.begin(), c.h_info_store.end(), c.h_info_pinned);
+    c.h_info = c.h_info_pinned;
+  }
   // per-count block lists and Hubbard block indices
   std::vector<int> lists, hb;
   for (int nm = 0; nm <= kMaxNm; ++nm)

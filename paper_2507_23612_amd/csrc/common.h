@@ -179,7 +179,21 @@ struct Ctx {
   double* d_E = nullptr;             // rocsolver work (ns)
   int* d_info = nullptr;
   std::vector<int> h_info_store;     // host copies of the eigensolve status per (spin,k)
-  int* h_info = nullptr;
+  int* h_info = nullptr;             // pinned copy once bound (asynchronous copies from side streams)
+  int* h_info_pinned = nullptr;
+  // Rayleigh-Ritz steps running beside each other (several blocks): scratch
+  // slots 1.. of this context (slot 0 is d_part, d_S, ... above), carved
+  // from the workspace, each with its own library handle; side streams and
+  // events of the batches this context leads
+  struct RRSlot {
+    rocblas_handle blas = nullptr;
+    double *part = nullptr, *S = nullptr, *Hs = nullptr, *E = nullptr;
+    void* Cb = nullptr;
+    int* info = nullptr;
+  };
+  std::vector<RRSlot> rr_slots;
+  std::vector<hipStream_t> rr_streams;
+  std::vector<hipEvent_t> rr_events;   // [0] main stream, [1 + lane] side streams
   double* d_D = nullptr;             // D_out [nspin][nhub][25]
   double* d_red = nullptr;           // scalar reductions scratch
   double* d_scal = nullptr;          // scalars [0..63]: mu, e_band, dc, E_U, kT S, F, dot results;
@@ -334,6 +348,7 @@ hcu_status run_stencil_batch(const BatchLaunch& L, const void* d_jobs, unsigned 
 template <typename T>
 void launch_nl_scatter(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T* Qt, double alpha, hipStream_t st);
 constexpr int kBrick = 64;
+constexpr int kRRLanes = 4;   // Rayleigh-Ritz steps of different blocks in flight at once
 constexpr int kPBrick = 256;
 
 // 16x16x4 matrix-core step D += A B per wave.  Operands: lane l supplies
