@@ -249,9 +249,21 @@ void scatter_t(Ctx& c, int spin, int ik, T* Y, int64_t ldy, int ncol, double alp
   launch_nl_scatter<T>(c, ik, Y, ldy, ncol, (const T*)c.d_Q[sk_index(c, spin, ik)], alpha, c.stream);
 }
 
+// Y += alpha Phi Q and, in the same pass (real blocks), P and Q of the
+// updated Y for the next Chebyshev step.
 template <typename T>
-void apply_h_t(Ctx& c, int spin, int ik, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncol) {
-  if (c.nproj > 0) project_t<T>(c, spin, ik, X, ldx, ncol);
+void scatter_project_t(Ctx& c, int spin, int ik, T* Y, int64_t ldy, int ncol, double alpha) {
+  ProfScope ps(c, PK_SCATTER);
+  const int sk = sk_index(c, spin, ik);
+  launch_scatter_project<T>(c, ik, Y, ldy, ncol, (const T*)c.d_Q[sk], alpha, c.d_coup[spin], (T*)c.d_P[sk],
+                            (T*)c.d_Q[sk], c.stream);
+}
+
+// proj_in = false: P and Q of X are already current (left by the step that
+// produced X).
+template <typename T>
+void apply_h_t(Ctx& c, int spin, int ik, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncol, bool proj_in = true) {
+  if (c.nproj > 0 && proj_in) project_t<T>(c, spin, ik, X, ldx, ncol);
   {
     ProfScope ps(c, PK_STENCIL);
     launch_stencil<T>(c, ik, X, ldx, nullptr, 0, Y, ldy, ncol, 1.0, 0.0, 0.0, c.stream);
@@ -260,26 +272,37 @@ void apply_h_t(Ctx& c, int spin, int ik, const T* X, int64_t ldx, T* Y, int64_t 
 }
 
 // One Chebyshev step: out = alpha (H y - c y) - beta yprev.
+// proj_in: project y first (else its P and Q are current); proj_out: leave P
+// and Q of out behind (fused with the scatter).
 template <typename T>
 void cheb_step_t(Ctx& c, int spin, int ik, const T* y, int64_t ldy, const T* yprev, int64_t ldp, T* out,
-                 int64_t ldo, int ncol, double alpha, double cc, double beta) {
-  if (c.nproj > 0) project_t<T>(c, spin, ik, y, ldy, ncol);
+                 int64_t ldo, int ncol, double alpha, double cc, double beta, bool proj_in, bool proj_out) {
+  if (c.nproj > 0 && proj_in) project_t<T>(c, spin, ik, y, ldy, ncol);
   {
     ProfScope ps(c, PK_STENCIL);
     launch_stencil<T>(c, ik, y, ldy, yprev, ldp, out, ldo, ncol, alpha, cc, beta, c.stream);
   }
-  if (c.nproj > 0) scatter_t<T>(c, spin, ik, out, ldo, ncol, alpha);
+  if (c.nproj > 0) {
+    if (proj_out) scatter_project_t<T>(c, spin, ik, out, ldo, ncol, alpha);
+    else scatter_t<T>(c, spin, ik, out, ldo, ncol, alpha);
+  }
 }
 
 // Returns the index of the work block that holds the filtered block.
+// project_last: leave P and Q of the filtered block behind (for H Y next).
+// Between steps the projections come out of the fused scatter when the
+// block type allows it.
 template <typename T>
-int filter_t(Ctx& c, int spin, int ik, const T* X, int64_t ldx, int ncol, int m, double a, double b, double aL) {
+int filter_t(Ctx& c, int spin, int ik, const T* X, int64_t ldx, int ncol, int m, double a, double b, double aL,
+             bool project_last = false) {
+  const bool fuse = scatter_project_ok<T>(c);
   const double e = (b - a) / 2, cc = (b + a) / 2;
   double sigma = e / (aL - cc);
   const double tau = 2.0 / sigma;
   const int64_t nd = c.nd;
   void** W = &c.d_W[3 * sk_index(c, spin, ik)];
-  cheb_step_t<T>(c, spin, ik, X, ldx, nullptr, 0, (T*)W[0], nd, ncol, sigma / e, cc, 0.0);
+  cheb_step_t<T>(c, spin, ik, X, ldx, nullptr, 0, (T*)W[0], nd, ncol, sigma / e, cc, 0.0, true,
+                 fuse && (m > 1 || project_last));
   const T* prev = X;
   int64_t ldp = ldx;
   int cur = 0;
@@ -287,7 +310,7 @@ int filter_t(Ctx& c, int spin, int ik, const T* X, int64_t ldx, int ncol, int m,
     const double s2 = 1.0 / (tau - sigma);
     const int out = (cur + 1) % 3;
     cheb_step_t<T>(c, spin, ik, (const T*)W[cur], nd, prev, ldp, (T*)W[out], nd, ncol, 2.0 * s2 / e, cc,
-                   sigma * s2);
+                   sigma * s2, !fuse, fuse && (i < m || project_last));
     prev = (const T*)W[cur];
     ldp = nd;
     cur = out;
@@ -360,11 +383,12 @@ hcu_status pass_t(Ctx& c, int spin, int ik, double* filter_ms) {
   HCU_HIP(hipEventCreate(&e0));
   HCU_HIP(hipEventCreate(&e1));
   HCU_HIP(hipEventRecord(e0, c.stream));
-  const int iy = filter_t<T>(c, spin, ik, X, nd, ns, c.p.degree, a, b, aL);
+  const bool fuse = scatter_project_ok<T>(c);
+  const int iy = filter_t<T>(c, spin, ik, X, nd, ns, c.p.degree, a, b, aL, fuse);
   const int ih = (iy + 1) % 3;
   T* Y = (T*)c.d_W[3 * sk + iy];
   T* HY = (T*)c.d_W[3 * sk + ih];
-  apply_h_t<T>(c, spin, ik, Y, nd, HY, nd, ns);
+  apply_h_t<T>(c, spin, ik, Y, nd, HY, nd, ns, !fuse);
   HCU_HIP(hipEventRecord(e1, c.stream));
   hcu_status s = rr_t<T>(c, sk, Y, HY);
   if (s != HCU_OK) return s;
@@ -543,7 +567,8 @@ hcu_status batch_pass_t(std::vector<BProb>& probs, Ctx& lead, double* filter_ms)
   for (int step = 0; step <= m; ++step) {
     for (int i = 0; i < np; ++i) {
       BProb& q = probs[i];
-      if (q.c->nproj > 0) project_t<T>(*q.c, q.spin, q.ik, (const T*)ops[step][i].in, q.c->nd, q.c->p.ns);
+      if (q.c->nproj > 0 && (step == 0 || !scatter_project_ok<T>(*q.c)))
+        project_t<T>(*q.c, q.spin, q.ik, (const T*)ops[step][i].in, q.c->nd, q.c->p.ns);
     }
     for (size_t l = first[step]; l < first[step + 1]; ++l) {
       ProfScope ps(lead, PK_STENCIL);
@@ -555,8 +580,14 @@ hcu_status batch_pass_t(std::vector<BProb>& probs, Ctx& lead, double* filter_ms)
     }
     for (int i = 0; i < np; ++i) {
       BProb& q = probs[i];
-      if (q.c->nproj > 0)
-        scatter_t<T>(*q.c, q.spin, q.ik, (T*)ops[step][i].out, q.c->nd, q.c->p.ns, ops[step][i].alpha);
+      if (q.c->nproj > 0) {
+        // steps before the last leave the projections of their output (the
+        // next step's input) behind
+        if (step < m && scatter_project_ok<T>(*q.c))
+          scatter_project_t<T>(*q.c, q.spin, q.ik, (T*)ops[step][i].out, q.c->nd, q.c->p.ns, ops[step][i].alpha);
+        else
+          scatter_t<T>(*q.c, q.spin, q.ik, (T*)ops[step][i].out, q.c->nd, q.c->p.ns, ops[step][i].alpha);
+      }
     }
     if (step == m - 1 && filter_ms) HCU_HIP_CTX(lead, hipEventRecord(e1, st));
   }

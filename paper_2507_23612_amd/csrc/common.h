@@ -133,6 +133,7 @@ struct Ctx {
   std::vector<int> pbnj;
   std::vector<int64_t> pbsrc, pdest, jrow;
   int pgroup = 2;   // points per lane and load group in the table order (2, 4 or 16)
+  int max_ptiles = 0;   // most 16-function slot tiles of any projection brick
   int64_t* d_pboff = nullptr;
   int* d_pbnj = nullptr;
   int64_t* d_pbsrc = nullptr;
@@ -374,6 +375,13 @@ template <typename T>
 void launch_project_brick(const Ctx& c, int ik, const T* Y, int ncol, int64_t ld, const double* coup, T* P, T* Q,
                           hipStream_t st);
 size_t project_partial_elems(const Ctx& c);
+// Real blocks: Y += alpha Phi Q and, in the same pass, P and Q of the
+// updated Y (the next Chebyshev step's input); usable when scatter_project_ok.
+template <typename T>
+bool scatter_project_ok(const Ctx& c);
+template <typename T>
+void launch_scatter_project(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T* Qt, double alpha,
+                            const double* coup, T* P, T* Q, hipStream_t st);
 
 // gemm.hip
 size_t gram_partial_elems(int n, int64_t nd);

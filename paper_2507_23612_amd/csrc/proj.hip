@@ -264,6 +264,162 @@ __global__ void k_couple(const T* __restrict__ P, const BlockDesc* __restrict__ 
   }
 }
 
+// ------------------------------------------------ fused scatter + projection
+// Real blocks inside a Chebyshev step: the projector scatter of this step's
+// output and the projections of that output (the next step's input) in one
+// pass,
+//   Y_b += alpha Phi_b Q                   (64-point bricks, as k_nl_brick)
+//   part[pdest[slot]][s] = sum_{p in B} Phi[slot][p] Y[s][p]
+//                                           (256-point brick B, as k_proj_brick)
+// One workgroup per (projection brick, 64 states) walks the brick's four
+// scatter bricks: each is updated in registers and written back, and the new
+// values go through a wave-private LDS tile [state][point] (rows padded by
+// 16 bytes) into the projection's operand order, so the block is read and
+// written once for both operations.  NT bounds the brick's slot tiles (all
+// accumulators stay in registers).
+template <typename T> constexpr int kYsRow = kBrick + 16 / (int)sizeof(T);
+
+template <typename T, int G, int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_scatter_project(
+    T* __restrict__ Y, int64_t ld, int ncol, const int64_t* __restrict__ boff, const int* __restrict__ bnj,
+    const int* __restrict__ bj, const T* __restrict__ bval, const T* __restrict__ Qt, int ldq, T alpha, int nbrick,
+    const int64_t* __restrict__ pboff, const int* __restrict__ pbnj, const T* __restrict__ pbval,
+    const int64_t* __restrict__ pdest, T* __restrict__ part, int ldp, int64_t nd, int nst) {
+  using V = typename Mf<T>::V;
+  constexpr int P = kPBrick / kBrick;
+  constexpr int RS = kYsRow<T>;
+  __shared__ __attribute__((aligned(16))) T ys[4][16 * RS];
+  const unsigned lw = xcd_linear();   // 1-D grid: state tile fastest, then brick
+  const int b = lw / nst;
+  const int st_ = lw % nst;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int s0 = st_ * 64 + wave * 16;
+  if (s0 >= ncol) return;   // whole wave; no workgroup barrier below
+  const int sa = s0 + (lane & 15);
+  const bool sa_ok = sa < ncol;
+  const int q = lane >> 4;
+  const int njp = pbnj[b];
+  const int ntile = (njp + 15) / 16;   // <= NT (host-checked)
+  const int64_t jop = pboff[b];
+  T* yw = ys[wave];
+  V pacc[NT];
+  for (int t = 0; t < NT; ++t)
+    for (int r = 0; r < 4; ++r) pacc[t][r] = T(0);
+  for (int k = 0; k < P; ++k) {
+    const int sbk = b * P + k;
+    if (sbk >= nbrick) break;   // uniform: the last brick of a ragged grid
+    const int64_t p0 = (int64_t)sbk * kBrick;
+    // ---- scatter of brick sbk (k_nl_brick's steps)
+    V acc[4];
+    for (int pt = 0; pt < 4; ++pt)
+      for (int r = 0; r < 4; ++r) {
+        const int s = s0 + Mf<T>::row(lane, r);
+        const int64_t p = p0 + pt * 16 + (lane & 15);
+        acc[pt][r] = (s < ncol && p < nd) ? Y[(int64_t)s * ld + p] : T(0);
+      }
+    const int64_t jo = boff[sbk];
+    const int nj4 = (bnj[sbk] + 3) & ~3;
+    const T* __restrict__ vb = bval + jo * kBrick;
+    int bjl = -1;
+    for (int jj = 0; jj < nj4; jj += 8) {
+      if ((jj & 63) == 0) {
+        const int e = jj + lane;
+        bjl = e < nj4 ? bj[jo + e] : -1;
+      }
+      T a[2], bb[2][4];
+      for (int u = 0; u < 2; ++u) {
+        const int jl = jj + 4 * u + (lane >> 4);
+        a[u] = T(0);
+        for (int pt = 0; pt < 4; ++pt) bb[u][pt] = T(0);
+        if (jj + 4 * u < nj4) {   // wave-uniform
+          const int jg = __shfl(bjl, jl & 63);
+          if (sa_ok && jg >= 0) a[u] = alpha * Qt[(int64_t)jg * ldq + sa];
+          for (int pt = 0; pt < 4; ++pt) bb[u][pt] = vb[(int64_t)jl * kBrick + pt * 16 + (lane & 15)];
+        }
+      }
+      for (int u = 0; u < 2; ++u) {
+        if (jj + 4 * u >= nj4) break;
+        for (int pt = 0; pt < 4; ++pt) acc[pt] = Mf<T>::mfma(a[u], bb[u][pt], acc[pt]);
+      }
+    }
+    for (int pt = 0; pt < 4; ++pt)
+      for (int r = 0; r < 4; ++r) {
+        const int sl = Mf<T>::row(lane, r);
+        const int64_t p = p0 + pt * 16 + (lane & 15);
+        if (nj4 > 0 && s0 + sl < ncol && p < nd) Y[(int64_t)(s0 + sl) * ld + p] = acc[pt][r];
+        yw[sl * RS + pt * 16 + (lane & 15)] = acc[pt][r];
+      }
+    if (ntile == 0) continue;
+    // ---- projection of the updated piece k (wave-private LDS, in order)
+    T bk[16];
+    load_piece<T, G>(yw + (lane & 15) * RS, 4 * G, G * q, 64, true, bk);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (t >= ntile) break;   // wave-uniform
+      T a[16];
+      load_piece<T, G>(pbval + (((jop / 16 + t) * P + k) * (16 / G)) * (64 * G) + lane * G, 64 * G, 0, 64, true,
+                       a);
+      for (int kk = 0; kk < 16; ++kk) pacc[t] = Mf<T>::mfma(a[kk], bk[kk], pacc[t]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if (t >= ntile) break;
+    for (int r = 0; r < 4; ++r) {
+      const int j = t * 16 + Mf<T>::row(lane, r);
+      if (j < njp && sa_ok) part[pdest[jop + j] * ldp + sa] = pacc[t][r];
+    }
+  }
+}
+
+template <typename T>
+bool scatter_project_ok(const Ctx& c) {
+  return sizeof(T) == sizeof(typename real_of<T>::type) && c.nproj > 0 && c.max_ptiles <= 8 && !c.pboff.empty();
+}
+
+template <typename T>
+void launch_scatter_project(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T* Qt, double alpha,
+                            const double* coup, T* P, T* Q, hipStream_t st) {
+  if constexpr (sizeof(T) == sizeof(typename real_of<T>::type)) {
+    T* part = reinterpret_cast<T*>(c.d_ppart);
+    const int npb = (int)c.pboff.size() - 1;
+    const int nbrick = (int)c.boff.size() - 1;
+    const int nst = (ncol + 63) / 64;
+    auto run = [&](auto g, auto nt) {
+      constexpr int G = decltype(g)::value, NT = decltype(nt)::value;
+      launch_k(k_scatter_project<T, G, NT>, (unsigned)npb * nst, 256, 0, st, Y, ld, ncol, c.d_boff, c.d_bnj, c.d_bj,
+               (const T*)c.d_bval[ik], Qt, c.p.ns, (T)alpha, nbrick, c.d_pboff, c.d_pbnj, (const T*)c.d_pbval[ik],
+               c.d_pdest, part, c.p.ns, c.nd, nst);
+    };
+    using I2 = std::integral_constant<int, 2>;
+    using I4 = std::integral_constant<int, 4>;
+    using I8 = std::integral_constant<int, 8>;
+    if (c.pgroup == 2) {
+      if (c.max_ptiles <= 4) run(I2(), I4()); else run(I2(), I8());
+    } else {
+      if (c.max_ptiles <= 4) run(I4(), I4()); else run(I4(), I8());
+    }
+    dim3 g2((ncol + 63) / 64, c.nproj);
+    launch_k(k_slot_sum<T>, g2, 1024, 0, st, part, c.p.ns, ncol, c.d_jrow, P, c.nproj, c.dv);
+    dim3 g3((ncol + 63) / 64, (unsigned)c.blocks.size());
+    launch_k(k_couple<T>, g3, 64, 0, st, P, c.d_blocks, ncol, coup, Q, c.nproj, c.p.ns);
+  }
+}
+
+template bool scatter_project_ok<double>(const Ctx&);
+template bool scatter_project_ok<float>(const Ctx&);
+template bool scatter_project_ok<cplx<double>>(const Ctx&);
+template bool scatter_project_ok<cplx<float>>(const Ctx&);
+template void launch_scatter_project<double>(const Ctx&, int, double*, int64_t, int, const double*, double,
+                                             const double*, double*, double*, hipStream_t);
+template void launch_scatter_project<float>(const Ctx&, int, float*, int64_t, int, const float*, double,
+                                            const double*, float*, float*, hipStream_t);
+template void launch_scatter_project<cplx<double>>(const Ctx&, int, cplx<double>*, int64_t, int,
+                                                   const cplx<double>*, double, const double*, cplx<double>*,
+                                                   cplx<double>*, hipStream_t);
+template void launch_scatter_project<cplx<float>>(const Ctx&, int, cplx<float>*, int64_t, int, const cplx<float>*,
+                                                  double, const double*, cplx<float>*, cplx<float>*, hipStream_t);
+
 size_t project_partial_elems(const Ctx& c) {
   if (c.pboff.empty()) return 0;
   return (size_t)c.pboff.back() * c.p.ns;

@@ -240,6 +240,7 @@ hcu_status build_structure(Ctx& c) {
   c.pgroup = (c.mixed && !c.any_complex) ? 4 : 2;
   const int G = c.pgroup;
   c.pboff.assign(1, 0);
+  c.max_ptiles = 0;
   c.pbnj.clear();
   c.pbsrc.clear();
   c.pdest.clear();
@@ -256,6 +257,7 @@ hcu_status build_structure(Ctx& c) {
       const int nj = (int)js.size();
       const int njp = (nj + 15) / 16 * 16;
       c.pbnj.push_back(nj);
+      c.max_ptiles = std::max(c.max_ptiles, njp / 16);
       c.pboff.push_back(c.pboff.back() + njp);
       for (int t = 0; t < njp; ++t) {
         pbj.push_back(t < nj ? js[t] : -1);
