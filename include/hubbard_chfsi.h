@@ -145,8 +145,13 @@ typedef struct hcu_energies {
   double mu;                    /* Fermi level                               */
 } hcu_energies;
 
-/* Accumulated device time per kernel family (HIP events on the bound
- * stream, recorded only while profiling is on). */
+/* Accumulated device time per kernel family, recorded only while profiling
+ * is on: from the begin/end timestamps of the family's own kernel dispatches
+ * (the eigensolve, made of library calls, from events around it).  Rayleigh-
+ * Ritz steps of several blocks run side by side, so their times can add up
+ * to more than the wall time.  For real blocks the projections of a
+ * Chebyshev step's output are computed in the scatter pass of that step and
+ * counted under scatter; project then holds the first step's projections. */
 typedef struct hcu_kernel_times {
   double stencil_ms;  long long stencil_launches;  /* stencil + V + Chebyshev step       */
   double project_ms;  long long project_launches;  /* projections onto atom functions    */
@@ -176,8 +181,13 @@ hcu_status hcu_workspace_size(const hcu_ctx* ctx, size_t* bytes);
 
 /* Bind `bytes` of device memory at `dev_ptr` (256-byte aligned) and the HIP
  * stream `stream` (NULL = default stream); evaluates V_loc and every atom-
- * centred function on the grid (Sec. II.B) on the device.  Errors:
- * HCU_OOM if bytes < hcu_workspace_size(), HCU_DEVICE on a HIP error. */
+ * centred function on the grid (Sec. II.B) on the device.  The context also
+ * takes a few bytes of pinned host memory (eigensolve status copies) and,
+ * when Rayleigh-Ritz steps of several blocks run side by side, up to four
+ * side streams of its own; their work is ordered after and before the
+ * bound stream's by events, so to the caller everything stays ordered on
+ * `stream`.  Errors: HCU_OOM if bytes < hcu_workspace_size(), HCU_DEVICE on
+ * a HIP error. */
 hcu_status hcu_bind(hcu_ctx* ctx, void* dev_ptr, size_t bytes, void* stream);
 
 /* Hubbard occupation matrices D_in (host, [nspin][nhub][5][5] row-major;
