@@ -149,9 +149,10 @@ typedef struct hcu_energies {
  * is on: from the begin/end timestamps of the family's own kernel dispatches
  * (the eigensolve, made of library calls, from events around it).  Rayleigh-
  * Ritz steps of several blocks run side by side, so their times can add up
- * to more than the wall time.  For real blocks the projections of a
- * Chebyshev step's output are computed in the scatter pass of that step and
- * counted under scatter; project then holds the first step's projections. */
+ * to more than the wall time.  For real and complex FP32 blocks the
+ * projections of a Chebyshev step's output are computed in the scatter pass
+ * of that step and counted under scatter; project then holds the first
+ * step's projections. */
 typedef struct hcu_kernel_times {
   double stencil_ms;  long long stencil_launches;  /* stencil + V + Chebyshev step       */
   double project_ms;  long long project_launches;  /* projections onto atom functions    */

@@ -372,9 +372,114 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   }
 }
 
+// Complex (Bloch) blocks in FP32: the same fused pass with the scatter's
+// four real products per step (k_nl_brick_c) and the projection's four
+// accumulators per slot tile (k_proj_brick_c); at most four slot tiles.
+template <typename R, int G, int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_scatter_project_c(
+    cplx<R>* __restrict__ Y, int64_t ld, int ncol, const int64_t* __restrict__ boff, const int* __restrict__ bnj,
+    const int* __restrict__ bj, const cplx<R>* __restrict__ bval, const cplx<R>* __restrict__ Qt, int ldq, R alpha,
+    int nbrick, const int64_t* __restrict__ pboff, const int* __restrict__ pbnj, const cplx<R>* __restrict__ pbval,
+    const int64_t* __restrict__ pdest, cplx<R>* __restrict__ part, int ldp, int64_t nd, int nst) {
+  using V = typename Mf<R>::V;
+  using C = cplx<R>;
+  constexpr int P = kPBrick / kBrick;
+  constexpr int RS = kYsRow<C>;
+  __shared__ __attribute__((aligned(16))) unsigned char ys_raw[4 * 16 * RS * sizeof(C)];
+  const unsigned lw = xcd_linear();
+  const int b = lw / nst;
+  const int st_ = lw % nst;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int s0 = st_ * 64 + wave * 16;
+  if (s0 >= ncol) return;   // whole wave; no workgroup barrier below
+  const int sa = s0 + (lane & 15);
+  const bool sa_ok = sa < ncol;
+  const int q = lane >> 4;
+  const int njp = pbnj[b];
+  const int ntile = (njp + 15) / 16;   // <= NT (host-checked)
+  const int64_t jop = pboff[b];
+  C* yw = reinterpret_cast<C*>(ys_raw) + wave * 16 * RS;
+  // per slot tile: Re Phi Re y, Im Phi Im y, Re Phi Im y, Im Phi Re y
+  V pc[NT][4];
+  for (int t = 0; t < NT; ++t)
+    for (int h = 0; h < 4; ++h)
+      for (int r = 0; r < 4; ++r) pc[t][h][r] = R(0);
+  for (int k = 0; k < P; ++k) {
+    const int sbk = b * P + k;
+    if (sbk >= nbrick) break;   // uniform: the last brick of a ragged grid
+    const int64_t p0 = (int64_t)sbk * kBrick;
+    // ---- scatter of brick sbk (k_nl_brick_c's steps)
+    V ar[4], ai[4];
+    for (int pt = 0; pt < 4; ++pt)
+      for (int r = 0; r < 4; ++r) {
+        const int s = s0 + Mf<R>::row(lane, r);
+        const int64_t p = p0 + pt * 16 + (lane & 15);
+        const C y = (s < ncol && p < nd) ? Y[(int64_t)s * ld + p] : C();
+        ar[pt][r] = y.re;
+        ai[pt][r] = y.im;
+      }
+    const int64_t jo = boff[sbk];
+    const int nj4 = (bnj[sbk] + 3) & ~3;
+    const C* __restrict__ vb = bval + jo * kBrick;
+    for (int jj = 0; jj < nj4; jj += 4) {
+      const int jl = jj + (lane >> 4);
+      const int jg = bj[jo + jl];
+      const C qv = (sa_ok && jg >= 0) ? Qt[(int64_t)jg * ldq + sa] : C();
+      const R qr = alpha * qv.re, qi = alpha * qv.im;
+      C f[4];
+      for (int pt = 0; pt < 4; ++pt) f[pt] = vb[(int64_t)jl * kBrick + pt * 16 + (lane & 15)];
+      for (int pt = 0; pt < 4; ++pt) {
+        ar[pt] = Mf<R>::mfma(qr, f[pt].re, ar[pt]);
+        ai[pt] = Mf<R>::mfma(qr, f[pt].im, ai[pt]);
+      }
+      for (int pt = 0; pt < 4; ++pt) {
+        ar[pt] = Mf<R>::mfma(-qi, f[pt].im, ar[pt]);
+        ai[pt] = Mf<R>::mfma(qi, f[pt].re, ai[pt]);
+      }
+    }
+    for (int pt = 0; pt < 4; ++pt)
+      for (int r = 0; r < 4; ++r) {
+        const int sl = Mf<R>::row(lane, r);
+        const int64_t p = p0 + pt * 16 + (lane & 15);
+        const C v(ar[pt][r], ai[pt][r]);
+        if (nj4 > 0 && s0 + sl < ncol && p < nd) Y[(int64_t)(s0 + sl) * ld + p] = v;
+        yw[sl * RS + pt * 16 + (lane & 15)] = v;
+      }
+    if (ntile == 0) continue;
+    // ---- projection of the updated piece k (wave-private LDS, in order)
+    C y[16];
+    load_piece<C, G>(yw + (lane & 15) * RS, 4 * G, G * q, 64, true, y);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (t >= ntile) break;   // wave-uniform
+      C f[16];
+      load_piece<C, G>(pbval + (((jop / 16 + t) * P + k) * (16 / G)) * (64 * G) + lane * G, 64 * G, 0, 64, true,
+                       f);
+      for (int kk = 0; kk < 16; ++kk) {
+        pc[t][0] = Mf<R>::mfma(f[kk].re, y[kk].re, pc[t][0]);
+        pc[t][1] = Mf<R>::mfma(f[kk].im, y[kk].im, pc[t][1]);
+        pc[t][2] = Mf<R>::mfma(f[kk].re, y[kk].im, pc[t][2]);
+        pc[t][3] = Mf<R>::mfma(f[kk].im, y[kk].re, pc[t][3]);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if (t >= ntile) break;
+    for (int r = 0; r < 4; ++r) {
+      const int j = t * 16 + Mf<R>::row(lane, r);
+      if (j < njp && sa_ok)
+        part[pdest[jop + j] * ldp + sa] = C(pc[t][0][r] + pc[t][1][r], pc[t][2][r] - pc[t][3][r]);
+    }
+  }
+}
+
 template <typename T>
 bool scatter_project_ok(const Ctx& c) {
-  return sizeof(T) == sizeof(typename real_of<T>::type) && c.nproj > 0 && c.max_ptiles <= 8 && !c.pboff.empty();
+  if (c.nproj == 0 || c.pboff.empty()) return false;
+  if constexpr (sizeof(T) == sizeof(typename real_of<T>::type)) return c.max_ptiles <= 8;
+  else if constexpr (std::is_same<T, cplx<float>>::value) return c.max_ptiles <= 4 && c.pgroup == 2;
+  else return false;   // complex FP64: the accumulators do not fit the register budget
 }
 
 template <typename T>
@@ -399,6 +504,18 @@ void launch_scatter_project(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, co
     } else {
       if (c.max_ptiles <= 4) run(I4(), I4()); else run(I4(), I8());
     }
+    dim3 g2((ncol + 63) / 64, c.nproj);
+    launch_k(k_slot_sum<T>, g2, 1024, 0, st, part, c.p.ns, ncol, c.d_jrow, P, c.nproj, c.dv);
+    dim3 g3((ncol + 63) / 64, (unsigned)c.blocks.size());
+    launch_k(k_couple<T>, g3, 64, 0, st, P, c.d_blocks, ncol, coup, Q, c.nproj, c.p.ns);
+  } else if constexpr (std::is_same<T, cplx<float>>::value) {
+    T* part = reinterpret_cast<T*>(c.d_ppart);
+    const int npb = (int)c.pboff.size() - 1;
+    const int nbrick = (int)c.boff.size() - 1;
+    const int nst = (ncol + 63) / 64;
+    launch_k(k_scatter_project_c<float, 2, 4>, (unsigned)npb * nst, 256, 0, st, Y, ld, ncol, c.d_boff, c.d_bnj,
+             c.d_bj, (const T*)c.d_bval[ik], Qt, c.p.ns, (float)alpha, nbrick, c.d_pboff, c.d_pbnj,
+             (const T*)c.d_pbval[ik], c.d_pdest, part, c.p.ns, c.nd, nst);
     dim3 g2((ncol + 63) / 64, c.nproj);
     launch_k(k_slot_sum<T>, g2, 1024, 0, st, part, c.p.ns, ncol, c.d_jrow, P, c.nproj, c.dv);
     dim3 g3((ncol + 63) / 64, (unsigned)c.blocks.size());

@@ -190,30 +190,36 @@ def test_cheb_filter_matches_oracle():
     assert err < 1e-11
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_cheb_filter_odd_grid(precision):
+@pytest.mark.parametrize("kind", ["fp64", "mixed", "c128", "c64"])
+def test_cheb_filter_odd_grid(kind):
     """Chebyshev filter on a 15x13x11 grid (2145 points: the last scatter
-    brick and the last projection brick are ragged, rows unaligned), where
+    brick and the last projection brick are ragged, rows unaligned), real
+    and Bloch blocks; where the block type allows it (real, complex FP32)
     each step after the first takes its projections from the previous
-    step's fused scatter pass, against the oracle's filter."""
+    step's fused scatter pass.  Against the oracle's filter."""
     torch = _torch()
     from oracle import chfsi
     cfg = workloads.make_config("tiny", seed=3)
     cfg["n"] = np.array([15, 13, 11], np.int32)
     cfg["ns"] = 9
+    cplx = kind in ("c128", "c64")
+    if cplx:
+        cfg["kpts"] = np.array([KPT])
+    precision = "fp64" if kind in ("fp64", "c128") else "mixed"
     ctx = _ctx(cfg, precision)
     D = _rand_D(1, ctx.nhub, 21)
     ctx.set_hubbard_occupation(D)
-    X = workloads.random_block(ctx.nd, ctx.ns, 22)
+    X = workloads.random_block(ctx.nd, ctx.ns, 22, complex_=cplx)
     Xd = torch.from_numpy(X).to(ctx.dtype).cuda()
     Yd = torch.empty_like(Xd)
     a, b, aL, m = 1.0, 120.0, -0.5, 6
     ctx.cheb_filter(Xd, Yd, m, a, b, aL)
     torch.cuda.synchronize()
-    Xr = Xd.cpu().numpy().astype(np.float64)
-    want = chfsi.cheb_filter(_oracle_H(cfg, D[0]).apply, Xr, m, a, b, aL)
+    Xr = Xd.cpu().numpy().astype(np.complex128 if cplx else np.float64)
+    H = _oracle_H(cfg, D[0], KPT if cplx else (0.0, 0.0, 0.0))
+    want = chfsi.cheb_filter(H.apply, Xr, m, a, b, aL)
     err = np.max(np.abs(Yd.cpu().numpy() - want)) / np.max(np.abs(want))
-    print(f"[gpu] filter odd grid {precision} rel err {err:.2e}", flush=True)
+    print(f"[gpu] filter odd grid {kind} rel err {err:.2e}", flush=True)
     assert err < (1e-11 if precision == "fp64" else 3e-5)
 
 
