@@ -11,6 +11,7 @@
 #include "common.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace hcu {
 
@@ -259,8 +260,9 @@ template void launch_rotate_proj<double>(const Ctx&, const double*, const double
 template void launch_rotate_proj<float>(const Ctx&, const float*, const float*, float*, int, hipStream_t);
 
 // ---------------------------------------------------------------- complex blocks
-// Complex (Bloch) blocks use VALU tiles: S = Y^H Y dV, Hs = Y^H HY dV
-// (Hermitian), X = Y C.  Partials hold interleaved complex doubles.
+// Complex (Bloch) blocks: S = Y^H Y dV, Hs = Y^H HY dV (Hermitian), X = Y C;
+// complex FP32 on the matrix cores (k_gram2_cm, k_rotate_cm), complex FP64
+// on VALU tiles.  Partials hold interleaved complex doubles.
 constexpr int CT = 32;     // output tile
 constexpr int CK = 32;     // grid points per stage
 template <typename T>
@@ -303,6 +305,84 @@ __global__ __launch_bounds__(256) void k_gram2_c(const T* __restrict__ Y, const 
     const int e = ti * CT + tj + q;
     outS[2 * e] = (double)aS[q].re; outS[2 * e + 1] = (double)aS[q].im;
     outH[2 * e] = (double)aH[q].re; outH[2 * e + 1] = (double)aH[q].im;
+  }
+}
+
+// Complex FP32 blocks on the matrix cores: the same 32 x 32 output tiles and
+// partial layout as k_gram2_c, each wave one 16 x 16 sub-tile of S and of Hs,
+// with the four real products of a complex one kept in separate
+// accumulators (Re: rr + ii, Im: ri - ir for A^H B); staged through LDS as
+// separate real and imaginary planes, next stage prefetched into registers.
+template <typename R>
+__global__ __launch_bounds__(256) void k_gram2_cm(const cplx<R>* __restrict__ Y, const cplx<R>* __restrict__ HY,
+                                                  int64_t ld, int n, int64_t nd, int64_t kchunk,
+                                                  const int2* __restrict__ tiles, int ntiles,
+                                                  double* __restrict__ part) {
+  using V = typename Acc<R>::V;
+  using C = cplx<R>;
+  __shared__ R sAr[CT][CK + 1], sAi[CT][CK + 1], sBr[CT][CK + 1], sBi[CT][CK + 1], sHr[CT][CK + 1],
+      sHi[CT][CK + 1];
+  const int2 tl = tiles[blockIdx.x];
+  const int i0 = tl.x * CT, j0 = tl.y * CT;
+  const int64_t kb = (int64_t)blockIdx.y * kchunk;
+  const int64_t ke = min(nd, kb + kchunk);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  V acc[8];   // S: rr ii ri ir, Hs: rr ii ri ir
+  for (int t = 0; t < 8; ++t)
+    for (int r = 0; r < 4; ++r) acc[t][r] = 0;
+  constexpr int PER = CT * CK / 256;
+  C ra[PER], rb[PER], rh[PER];
+  auto fetch = [&](int64_t k) {
+    for (int t = 0; t < PER; ++t) {
+      const int e = threadIdx.x + 256 * t;
+      const int col = e / CK, kk = e % CK;
+      const int64_t g = k + kk;
+      const bool okk = g < ke;
+      ra[t] = (okk && i0 + col < n) ? Y[(int64_t)(i0 + col) * ld + g] : C();
+      rb[t] = (okk && j0 + col < n) ? Y[(int64_t)(j0 + col) * ld + g] : C();
+      rh[t] = (okk && j0 + col < n) ? HY[(int64_t)(j0 + col) * ld + g] : C();
+    }
+  };
+  if (kb < ke) fetch(kb);
+  for (int64_t k = kb; k < ke; k += CK) {
+    for (int t = 0; t < PER; ++t) {
+      const int e = threadIdx.x + 256 * t;
+      const int col = e / CK, kk = e % CK;
+      sAr[col][kk] = ra[t].re;
+      sAi[col][kk] = ra[t].im;
+      sBr[col][kk] = rb[t].re;
+      sBi[col][kk] = rb[t].im;
+      sHr[col][kk] = rh[t].re;
+      sHi[col][kk] = rh[t].im;
+    }
+    __syncthreads();
+    if (k + CK < ke) fetch(k + CK);
+    for (int kk = 0; kk < CK; kk += 4) {
+      const int ia = 16 * wi + (lane & 15), jb = 16 * wj + (lane & 15), kq = kk + (lane >> 4);
+      const R ar = sAr[ia][kq], ai = sAi[ia][kq];
+      const R br = sBr[jb][kq], bi = sBi[jb][kq], hr = sHr[jb][kq], hi = sHi[jb][kq];
+      acc[0] = Acc<R>::mfma(ar, br, acc[0]);
+      acc[1] = Acc<R>::mfma(ai, bi, acc[1]);
+      acc[2] = Acc<R>::mfma(ar, bi, acc[2]);
+      acc[3] = Acc<R>::mfma(ai, br, acc[3]);
+      acc[4] = Acc<R>::mfma(ar, hr, acc[4]);
+      acc[5] = Acc<R>::mfma(ai, hi, acc[5]);
+      acc[6] = Acc<R>::mfma(ar, hi, acc[6]);
+      acc[7] = Acc<R>::mfma(ai, hr, acc[7]);
+    }
+    __syncthreads();
+  }
+  double* outS = part + ((int64_t)blockIdx.y * ntiles + blockIdx.x) * 2 * CT * CT * 2;
+  double* outH = outS + CT * CT * 2;
+  for (int r = 0; r < 4; ++r) {
+    const int i = 16 * wi + Acc<R>::row(lane, r);
+    const int j = 16 * wj + (lane & 15);
+    const int e = i * CT + j;
+    outS[2 * e] = (double)acc[0][r] + (double)acc[1][r];
+    outS[2 * e + 1] = (double)acc[2][r] - (double)acc[3][r];
+    outH[2 * e] = (double)acc[4][r] + (double)acc[5][r];
+    outH[2 * e + 1] = (double)acc[6][r] - (double)acc[7][r];
   }
 }
 
@@ -359,7 +439,10 @@ void launch_gram2_c(const Ctx& c, const T* Y, const T* HY, int ncol, int64_t ld,
   int64_t kc;
   gram_plan_c(ncol, c.nd, t1, nt, kc, nc);
   const int2* d_tiles = c.d_tiles;
-  launch_k(k_gram2_c<T>, dim3(nt, nc), 256, 0, st, Y, HY, ld, ncol, c.nd, kc, d_tiles, nt, c.d_part);
+  if constexpr (std::is_same<T, cplx<float>>::value)
+    launch_k(k_gram2_cm<float>, dim3(nt, nc), 256, 0, st, Y, HY, ld, ncol, c.nd, kc, d_tiles, nt, c.d_part);
+  else
+    launch_k(k_gram2_c<T>, dim3(nt, nc), 256, 0, st, Y, HY, ld, ncol, c.nd, kc, d_tiles, nt, c.d_part);
   launch_k(k_gram_reduce_c, nt, 256, 0, st, c.d_part, nc, nt, d_tiles, ncol, c.dv, S, Hs);
 }
 
@@ -397,10 +480,88 @@ __global__ __launch_bounds__(256) void k_rotate_c(const T* __restrict__ Y, int64
   }
 }
 
+// Complex FP32 rotation on the matrix cores: X^T = C^T Y^T as in k_rotate
+// (64 states x 64 grid points per workgroup, each wave 2 x 2 sub-tiles), the
+// complex product as four real ones: Re X = rr - ii, Im X = ir + ri
+// (first letter C, second Y).
+template <typename R>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rotate_cm(
+    const cplx<R>* __restrict__ Y, int64_t ld, const cplx<R>* __restrict__ Cm, cplx<R>* __restrict__ X, int n,
+    int64_t nd) {
+  using V = typename Acc<R>::V;
+  using C = cplx<R>;
+  __shared__ R sYr[RK][GT + 1], sYi[RK][GT + 1], sCr[RK][GT + 1], sCi[RK][GT + 1];
+  const int j0 = blockIdx.x * GT;
+  const int64_t p0 = (int64_t)blockIdx.y * GT;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wp = wave >> 1, wj = wave & 1;
+  V acc[2][2][4];   // rr ii ir ri
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int h = 0; h < 4; ++h)
+        for (int r = 0; r < 4; ++r) acc[a][b][h][r] = 0;
+  constexpr int PER = RK * GT / 256;
+  C ry[PER], rc[PER];
+  auto fetch = [&](int i0) {
+    for (int t = 0; t < PER; ++t) {
+      const int e = threadIdx.x + 256 * t;
+      const int ii = e / GT, pp = e % GT;
+      const int64_t g = p0 + pp;
+      ry[t] = (i0 + ii < n && g < nd) ? Y[(int64_t)(i0 + ii) * ld + g] : C();
+      const int jj = e / RK, i2 = e % RK;
+      rc[t] = (i0 + i2 < n && j0 + jj < n) ? Cm[(int64_t)(j0 + jj) * n + i0 + i2] : C();
+    }
+  };
+  fetch(0);
+  for (int i0 = 0; i0 < n; i0 += RK) {
+    for (int t = 0; t < PER; ++t) {
+      const int e = threadIdx.x + 256 * t;
+      sYr[e / GT][e % GT] = ry[t].re;
+      sYi[e / GT][e % GT] = ry[t].im;
+      sCr[e % RK][e / RK] = rc[t].re;
+      sCi[e % RK][e / RK] = rc[t].im;
+    }
+    __syncthreads();
+    if (i0 + RK < n) fetch(i0 + RK);
+    for (int kk = 0; kk < RK; kk += 4) {
+      R cr[2], ci[2], yr[2], yi[2];
+      for (int a = 0; a < 2; ++a) {
+        cr[a] = sCr[kk + (lane >> 4)][32 * wj + 16 * a + (lane & 15)];
+        ci[a] = sCi[kk + (lane >> 4)][32 * wj + 16 * a + (lane & 15)];
+      }
+      for (int b = 0; b < 2; ++b) {
+        yr[b] = sYr[kk + (lane >> 4)][32 * wp + 16 * b + (lane & 15)];
+        yi[b] = sYi[kk + (lane >> 4)][32 * wp + 16 * b + (lane & 15)];
+      }
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+          acc[a][b][0] = Acc<R>::mfma(cr[a], yr[b], acc[a][b][0]);
+          acc[a][b][1] = Acc<R>::mfma(ci[a], yi[b], acc[a][b][1]);
+          acc[a][b][2] = Acc<R>::mfma(ci[a], yr[b], acc[a][b][2]);
+          acc[a][b][3] = Acc<R>::mfma(cr[a], yi[b], acc[a][b][3]);
+        }
+    }
+    __syncthreads();
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int r = 0; r < 4; ++r) {
+        const int j = j0 + 32 * wj + 16 * a + Acc<R>::row(lane, r);
+        const int64_t p = p0 + 32 * wp + 16 * b + (lane & 15);
+        if (j < n && p < nd)
+          X[(int64_t)j * ld + p] = C(acc[a][b][0][r] - acc[a][b][1][r], acc[a][b][2][r] + acc[a][b][3][r]);
+      }
+}
+
 template <typename T>
 void launch_rotate_c(const Ctx& c, const T* Y, int64_t ld, const T* Cb, T* X, int ncol, hipStream_t st) {
-  dim3 grid((ncol + CT - 1) / CT, (unsigned)((c.nd + 63) / 64));
-  launch_k(k_rotate_c<T>, grid, 256, 0, st, Y, ld, Cb, X, ncol, c.nd);
+  if constexpr (std::is_same<T, cplx<float>>::value) {
+    dim3 grid((ncol + GT - 1) / GT, (unsigned)((c.nd + GT - 1) / GT));
+    launch_k(k_rotate_cm<float>, grid, 256, 0, st, Y, ld, Cb, X, ncol, c.nd);
+  } else {
+    dim3 grid((ncol + CT - 1) / CT, (unsigned)((c.nd + 63) / 64));
+    launch_k(k_rotate_c<T>, grid, 256, 0, st, Y, ld, Cb, X, ncol, c.nd);
+  }
 }
 
 template <>

@@ -434,3 +434,33 @@ def test_scf_spin_polarised_kpoints_tiny():
     for s in range(2):
         for h in range(ctx.nhub):
             np.testing.assert_allclose(Dg[s, h], np.real(ref["D"][s][h]), atol=1e-6)
+
+
+def test_scf_spin_polarised_kpoints_tiny_mixed():
+    """The same spin-polarised 8-k-point SCF with complex FP32 blocks
+    (projections, scatters, Gram matrices and rotations of complex FP32 on
+    the matrix cores; Cholesky, eigensolve and D in FP64) against the
+    oracle's FP64 SCF: free energy within 1e-5 Ha/atom."""
+    torch = _torch()
+    from oracle import scf as oscf
+    from paper_2507_23612_amd import hcu
+    cfg = workloads.with_kpoints(workloads.make_config("tiny"))
+    ctx = _ctx(cfg, "mixed")
+    ctx.set_hubbard_occupation(hcu.initial_occupation(ctx, cfg))
+    for s in range(2):
+        for ik in range(8):
+            X0, v0 = hcu.start_inputs(ctx, cfg, s, ik)
+            ctx.set_start(s, ik, X0, v0)
+    rep = ctx.scf(tol_d=1e-5)
+    ref = oscf.scf(cfg)
+    e = ctx.get_energies()
+    natom = len(cfg["atom_species"])
+    dF = abs(e["F"] - ref["F"]) / natom
+    lam = ctx.get_eigenvalues()
+    dl = np.max(np.abs(lam[:, :, :8] - ref["eigs"][:, :, :8]))
+    print(f"[gpu] spin+k tiny mixed: |dF|/atom {dF:.2e}, max |d eig| {dl:.2e}, iters {rep['iterations']}",
+          flush=True)
+    assert rep["converged"]
+    assert dF < 1e-5
+    assert dl < 1e-4
+
