@@ -337,6 +337,7 @@ struct BatchLaunch {
   int njob;
   unsigned long long total;     // work items
   int TX, TYt, RY, R;
+  int halo_slots;               // most halo values per thread and plane over the jobs
 };
 template <typename T>
 hcu_status plan_stencil_batch(const std::vector<StencilJob>& jobs, std::vector<unsigned char>& host,

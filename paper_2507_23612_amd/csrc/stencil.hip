@@ -17,6 +17,7 @@
 #include "common.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace hcu {
 
@@ -91,10 +92,14 @@ __device__ inline int wrap(int g, int n, int& w) {
   return g - w * n;
 }
 
-constexpr int kHaloSlots = 8;     // halo values a thread stages per plane (host checks the bound)
+// Halo values a thread stages per plane (host checks the bound).  Kernels
+// come with 8 slots and, for the single-block and persistent forms, with 4:
+// the slot bookkeeping lives in registers, and most tiles need at most 4.
+constexpr int kHaloSlots = 8;
+constexpr int kHaloSlotsSmall = 4;
 
 // One work item: tile `tile` of the x-y plane, z chunk `zc`, state `s`.
-template <typename T, typename RT, int R, int RY>
+template <typename T, typename RT, int R, int RY, int NHS>
 __device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T* __restrict__ Yprev,
                                              T* __restrict__ Yout, const RT* __restrict__ V, const KArgs<RT>& a,
                                              int tile, int zc, int64_t s, unsigned char* smem_raw) {
@@ -125,8 +130,8 @@ __device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T*
   // halo slots owned by this thread: y halo (2R rows x TX) then, unless
   // xfull, x halo (TY rows x 2R)
   const int nyh = 2 * R * TX, nh = nyh + (xfull ? 0 : TY * 2 * R);
-  int h_xy[kHaloSlots], h_lds[kHaloSlots], h_w[kHaloSlots];
-  for (int k = 0; k < kHaloSlots; ++k) {
+  int h_xy[NHS], h_lds[NHS], h_w[NHS];
+  for (int k = 0; k < NHS; ++k) {
     const int e = tid + k * nthr;
     h_lds[k] = -1; h_xy[k] = 0; h_w[k] = 0;
     if (e >= nh) continue;
@@ -168,14 +173,14 @@ __device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T*
         if (tx >= n1 - R) buf[row * SW + tx - n1 + R] = Ld<T>::get(&v, 0, -1, 0, 0, a);
       }
     }
-    for (int k = 0; k < kHaloSlots; ++k)
+    for (int k = 0; k < NHS; ++k)
       if (h_lds[k] >= 0) buf[h_lds[k]] = hreg[k];
   };
-  T hreg[kHaloSlots];
+  T hreg[NHS];
   {
     int wz;
     const int gz = wrap(zbeg, n3, wz);
-    for (int k = 0; k < kHaloSlots; ++k)
+    for (int k = 0; k < NHS; ++k)
       if (h_lds[k] >= 0)
         hreg[k] = Ld<T>::get(Ys, h_xy[k] + plane * gz, h_w[k] / 16 - 4, h_w[k] % 16 - 4, wz, a);
   }
@@ -192,7 +197,7 @@ __device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T*
       const int gz = wrap(z + 1 + R, n3, wz);
       for (int r = 0; r < RY; ++r)
         qn[r] = Ld<T>::get(Ys, gx + (int64_t)n1 * gy[r] + plane * gz, wxo, wyo[r], wz, a);
-      for (int k = 0; k < kHaloSlots; ++k)
+      for (int k = 0; k < NHS; ++k)
         if (h_lds[k] >= 0)
           hreg[k] = Ld<T>::get(Ys, h_xy[k] + plane * (z + 1), h_w[k] / 16 - 4, h_w[k] % 16 - 4, 0, a);
     }
@@ -234,7 +239,7 @@ __device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T*
   }
 }
 
-template <typename T, typename RT, int R, int RY>
+template <typename T, typename RT, int R, int RY, int NHS>
 __global__ __launch_bounds__(512) void k_stencil(const T* __restrict__ Yin, const T* __restrict__ Yprev,
                                                  T* __restrict__ Yout, const RT* __restrict__ V,
                                                  const KArgs<RT> a) {
@@ -244,7 +249,7 @@ __global__ __launch_bounds__(512) void k_stencil(const T* __restrict__ Yin, cons
   const int tile = lw % gridDim.x;
   const int zc = (lw / gridDim.x) % gridDim.y;
   const int64_t s = lw / (gridDim.x * gridDim.y);
-  stencil_item<T, RT, R, RY>(Yin, Yprev, Yout, V, a, tile, zc, s, smem_raw);
+  stencil_item<T, RT, R, RY, NHS>(Yin, Yprev, Yout, V, a, tile, zc, s, smem_raw);
 }
 
 // Large-workgroup form (up to 1024 threads, e.g. a 72 x 12 tile with one
@@ -260,7 +265,7 @@ __global__ __launch_bounds__(1024) void k_stencil_big(const T* __restrict__ Yin,
   const int tile = lw % gridDim.x;
   const int zc = (lw / gridDim.x) % gridDim.y;
   const int64_t s = lw / (gridDim.x * gridDim.y);
-  stencil_item<T, RT, R, RY>(Yin, Yprev, Yout, V, a, tile, zc, s, smem_raw);
+  stencil_item<T, RT, R, RY, kHaloSlots>(Yin, Yprev, Yout, V, a, tile, zc, s, smem_raw);
 }
 
 // Persistent form over a list of jobs (blocks of possibly different grids):
@@ -268,7 +273,7 @@ __global__ __launch_bounds__(1024) void k_stencil_big(const T* __restrict__ Yin,
 // counter each; workgroup w starts on range w % kNumXcd (the XCD it runs on)
 // and moves to the next range when its own is exhausted.  Every workgroup
 // leaves after visiting all ranges, so the grid always drains.
-template <typename T, typename RT, int R, int RY>
+template <typename T, typename RT, int R, int RY, int NHS>
 __global__ __launch_bounds__(512) void k_stencil_batch(const SJob<RT>* __restrict__ jobs, int njobs,
                                                        unsigned long long total,
                                                        unsigned long long* __restrict__ counters) {
@@ -300,7 +305,7 @@ __global__ __launch_bounds__(512) void k_stencil_batch(const SJob<RT>* __restric
       const int tile = (int)(loc % jb.ntiles);
       const int zc = (int)((loc / jb.ntiles) % jb.nzc);
       const int64_t s = (int64_t)(loc / ((unsigned long long)jb.ntiles * jb.nzc));
-      stencil_item<T, RT, R, RY>((const T*)jb.Yin, (const T*)jb.Yprev, (T*)jb.Yout, jb.V, jb.a, tile, zc, s,
+      stencil_item<T, RT, R, RY, NHS>((const T*)jb.Yin, (const T*)jb.Yprev, (T*)jb.Yout, jb.V, jb.a, tile, zc, s,
                                  smem_raw);
     }
   }
@@ -324,7 +329,7 @@ __global__ __launch_bounds__(512) void k_stencil_multi(const SJob<RT>* __restric
   const int tile = (int)(loc % jb.ntiles);
   const int zc = (int)((loc / jb.ntiles) % jb.nzc);
   const int64_t s = (int64_t)(loc / ((unsigned long long)jb.ntiles * jb.nzc));
-  stencil_item<T, RT, R, RY>((const T*)jb.Yin, (const T*)jb.Yprev, (T*)jb.Yout, jb.V, jb.a, tile, zc, s, smem_raw);
+  stencil_item<T, RT, R, RY, kHaloSlots>((const T*)jb.Yin, (const T*)jb.Yprev, (T*)jb.Yout, jb.V, jb.a, tile, zc, s, smem_raw);
 }
 
 // Tile shape for a grid: TX threads along x, TYt thread rows, RY points per
@@ -337,6 +342,13 @@ static bool big_ok(const Ctx& c, int RY) {
   return c.mixed ? RY <= 2 : RY == 1;
 }
 
+// halo values per thread and plane for a tile on a grid with n1 points in x
+static int halo_slots(int n1, int TX, int TYt, int TY, int R) {
+  const int nthr = TX * TYt;
+  const int nh = 2 * R * TX + ((TX == n1 && n1 >= R) ? 0 : TY * 2 * R);
+  return (nh + nthr - 1) / nthr;
+}
+
 static bool shape_ok(const Ctx& c, const StencilShape& sh, int R) {
   const int n1 = c.p.n[0], n2 = c.p.n[1];
   if (sh.TX < 1 || sh.TX > n1 || sh.TYt < 1 || sh.TX * sh.TYt > 1024) return false;
@@ -344,9 +356,7 @@ static bool shape_ok(const Ctx& c, const StencilShape& sh, int R) {
   if (sh.RY != 1 && sh.RY != 2 && sh.RY != 4) return false;
   const int TY = sh.TYt * sh.RY;
   if (TY > n2) return false;
-  const int nthr = sh.TX * sh.TYt;
-  const int nh = 2 * R * sh.TX + ((sh.TX == n1 && n1 >= R) ? 0 : TY * 2 * R);
-  if ((nh + nthr - 1) / nthr > kHaloSlots) return false;
+  if (halo_slots(n1, sh.TX, sh.TYt, TY, R) > kHaloSlots) return false;
   return sh.tz >= 1;
 }
 
@@ -374,8 +384,8 @@ static StencilShape pick_tiles(const Ctx& c, int ncol, int elem) {
 }
 
 template <typename T, typename RT, int R>
-static void launch_r(int RY, const KArgs<RT>& a, dim3 grid, dim3 block, size_t lds, const T* Yin, const T* Yprev,
-                     T* Yout, const RT* V, hipStream_t st) {
+static void launch_r(int RY, bool small_halo, const KArgs<RT>& a, dim3 grid, dim3 block, size_t lds, const T* Yin,
+                     const T* Yprev, T* Yout, const RT* V, hipStream_t st) {
   if constexpr (sizeof(T) == sizeof(RT)) {
     if (block.x * block.y > 512) {
       if (RY == 2)
@@ -385,12 +395,17 @@ static void launch_r(int RY, const KArgs<RT>& a, dim3 grid, dim3 block, size_t l
       return;
     }
   }
-  if (RY == 4)
-    launch_k(k_stencil<T, RT, R, 4>, grid, block, lds, st, Yin, Yprev, Yout, V, a);
-  else if (RY == 2)
-    launch_k(k_stencil<T, RT, R, 2>, grid, block, lds, st, Yin, Yprev, Yout, V, a);
-  else
-    launch_k(k_stencil<T, RT, R, 1>, grid, block, lds, st, Yin, Yprev, Yout, V, a);
+  auto go = [&](auto nhs) {
+    constexpr int NHS = decltype(nhs)::value;
+    if (RY == 4)
+      launch_k(k_stencil<T, RT, R, 4, NHS>, grid, block, lds, st, Yin, Yprev, Yout, V, a);
+    else if (RY == 2)
+      launch_k(k_stencil<T, RT, R, 2, NHS>, grid, block, lds, st, Yin, Yprev, Yout, V, a);
+    else
+      launch_k(k_stencil<T, RT, R, 1, NHS>, grid, block, lds, st, Yin, Yprev, Yout, V, a);
+  };
+  if (small_halo) go(std::integral_constant<int, kHaloSlotsSmall>());
+  else go(std::integral_constant<int, kHaloSlots>());
 }
 
 template <typename T>
@@ -422,21 +437,22 @@ void launch_stencil(const Ctx& c, int ik, const T* Yin, int64_t ld, const T* Ypr
   dim3 block(TX, TYt);
   const int R = sc.R;
   size_t lds = 2 * (size_t)(TY + 2 * R) * (TX + 2 * R) * sizeof(T);
+  const bool small = halo_slots(a.n1, TX, TYt, TY, R) <= kHaloSlotsSmall;
   const RT* V;
   if constexpr (sizeof(RT) == 4) V = c.d_Vf; else V = c.d_V;
   switch (R) {
-    case 1: launch_r<T, RT, 1>(sh.RY, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
-    case 2: launch_r<T, RT, 2>(sh.RY, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
-    case 3: launch_r<T, RT, 3>(sh.RY, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
-    case 4: launch_r<T, RT, 4>(sh.RY, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
-    case 5: launch_r<T, RT, 5>(sh.RY, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
-    default: launch_r<T, RT, 6>(sh.RY, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    case 1: launch_r<T, RT, 1>(sh.RY, small, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    case 2: launch_r<T, RT, 2>(sh.RY, small, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    case 3: launch_r<T, RT, 3>(sh.RY, small, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    case 4: launch_r<T, RT, 4>(sh.RY, small, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    case 5: launch_r<T, RT, 5>(sh.RY, small, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    default: launch_r<T, RT, 6>(sh.RY, small, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
   }
 }
 
 template <typename T, typename RT, int R>
-static void launch_batch_r(int RY, dim3 grid, dim3 block, size_t lds, const SJob<RT>* jobs, int njobs,
-                           unsigned long long total, unsigned long long* counters, hipStream_t st) {
+static void launch_batch_r(int RY, bool small_halo, dim3 grid, dim3 block, size_t lds, const SJob<RT>* jobs,
+                           int njobs, unsigned long long total, unsigned long long* counters, hipStream_t st) {
   if (!counters) {   // one workgroup per item
     dim3 g((unsigned)total);
     if (RY == 4)
@@ -447,12 +463,17 @@ static void launch_batch_r(int RY, dim3 grid, dim3 block, size_t lds, const SJob
       launch_k(k_stencil_multi<T, RT, R, 1>, g, block, lds, st, jobs, njobs);
     return;
   }
-  if (RY == 4)
-    launch_k(k_stencil_batch<T, RT, R, 4>, grid, block, lds, st, jobs, njobs, total, counters);
-  else if (RY == 2)
-    launch_k(k_stencil_batch<T, RT, R, 2>, grid, block, lds, st, jobs, njobs, total, counters);
-  else
-    launch_k(k_stencil_batch<T, RT, R, 1>, grid, block, lds, st, jobs, njobs, total, counters);
+  auto go = [&](auto nhs) {
+    constexpr int NHS = decltype(nhs)::value;
+    if (RY == 4)
+      launch_k(k_stencil_batch<T, RT, R, 4, NHS>, grid, block, lds, st, jobs, njobs, total, counters);
+    else if (RY == 2)
+      launch_k(k_stencil_batch<T, RT, R, 2, NHS>, grid, block, lds, st, jobs, njobs, total, counters);
+    else
+      launch_k(k_stencil_batch<T, RT, R, 1, NHS>, grid, block, lds, st, jobs, njobs, total, counters);
+  };
+  if (small_halo) go(std::integral_constant<int, kHaloSlotsSmall>());
+  else go(std::integral_constant<int, kHaloSlots>());
 }
 
 // Common tile shape for a set of grids: the autotuned shape of the first
@@ -522,11 +543,12 @@ hcu_status plan_stencil_batch(const std::vector<StencilJob>& jobs, std::vector<u
   for (size_t g = 0; g < groups.size(); ++g) {
     const int TX = groups[g].TX, TYt = groups[g].TYt, RY = groups[g].RY;
     const int TY = TYt * RY;
-    BatchLaunch L{slot, 0, 0, TX, TYt, RY, R};
+    BatchLaunch L{slot, 0, 0, TX, TYt, RY, R, 0};
     for (size_t i = 0; i < jobs.size(); ++i) {
       if (gid[i] != (int)g) continue;
       const StencilJob& j = jobs[i];
       const Ctx& c = *j.c;
+      L.halo_slots = std::max(L.halo_slots, halo_slots(c.p.n[0], TX, TYt, TY, R));
       StencilCoef sc;
       fill_stencil_coef(c, j.ik, sc);
       KArgs<RT> a{};
@@ -569,15 +591,28 @@ hcu_status run_stencil_batch(const BatchLaunch& L, const void* d_jobs, unsigned 
     return HCU_DEVICE;
   const int TY = L.TYt * L.RY;
   const size_t lds = 2 * (size_t)(TY + 2 * L.R) * (L.TX + 2 * L.R) * sizeof(T);
+  const bool small = L.halo_slots <= kHaloSlotsSmall;
   dim3 grid(1024), block(L.TX, L.TYt);
   const SJob<RT>* dj = reinterpret_cast<const SJob<RT>*>(d_jobs) + L.first;
   switch (L.R) {
-    case 1: launch_batch_r<T, RT, 1>(L.RY, grid, block, lds, dj, L.njob, L.total, d_counters, st); break;
-    case 2: launch_batch_r<T, RT, 2>(L.RY, grid, block, lds, dj, L.njob, L.total, d_counters, st); break;
-    case 3: launch_batch_r<T, RT, 3>(L.RY, grid, block, lds, dj, L.njob, L.total, d_counters, st); break;
-    case 4: launch_batch_r<T, RT, 4>(L.RY, grid, block, lds, dj, L.njob, L.total, d_counters, st); break;
-    case 5: launch_batch_r<T, RT, 5>(L.RY, grid, block, lds, dj, L.njob, L.total, d_counters, st); break;
-    default: launch_batch_r<T, RT, 6>(L.RY, grid, block, lds, dj, L.njob, L.total, d_counters, st); break;
+    case 1:
+      launch_batch_r<T, RT, 1>(L.RY, small, grid, block, lds, dj, L.njob, L.total, d_counters, st);
+      break;
+    case 2:
+      launch_batch_r<T, RT, 2>(L.RY, small, grid, block, lds, dj, L.njob, L.total, d_counters, st);
+      break;
+    case 3:
+      launch_batch_r<T, RT, 3>(L.RY, small, grid, block, lds, dj, L.njob, L.total, d_counters, st);
+      break;
+    case 4:
+      launch_batch_r<T, RT, 4>(L.RY, small, grid, block, lds, dj, L.njob, L.total, d_counters, st);
+      break;
+    case 5:
+      launch_batch_r<T, RT, 5>(L.RY, small, grid, block, lds, dj, L.njob, L.total, d_counters, st);
+      break;
+    default:
+      launch_batch_r<T, RT, 6>(L.RY, small, grid, block, lds, dj, L.njob, L.total, d_counters, st);
+      break;
   }
   return hipGetLastError() == hipSuccess ? HCU_OK : HCU_DEVICE;
 }
