@@ -62,26 +62,27 @@ def stencil_bytes(cfg, elem):
 
 
 def measured_traffic(config, prec, tile):
-    """HBM bytes per stencil launch from the committed counter summary
-    profiles/k_stencil_<config>_<prec>.md (FETCH_SIZE and WRITE_SIZE runs,
-    calibrated on a plain copy), or None if there is none for this tile shape
-    or the kernel sources changed since it was taken."""
+    """HBM bytes per stencil launch from the committed counter summaries
+    profiles/k_stencil_<config>_<prec>*.md (FETCH_SIZE and WRITE_SIZE runs,
+    calibrated on a plain copy; one file per tile shape), or None if there is
+    none for this tile shape or the kernel sources changed since it was
+    taken."""
+    import glob
     from paper_2507_23612_amd.tracesum import kernel_source_digest
-    path = os.path.join(ROOT, "profiles", f"k_stencil_{config}_{prec}.md")
-    if not os.path.exists(path):
-        return None
-    rec = {}
-    with open(path) as fh:
-        for line in fh:
-            if line.startswith("- record "):
-                k, _, v = line[len("- record "):].partition(":")
-                rec[k.strip()] = v.strip()
-    try:
-        if rec.get("source_sha256") != kernel_source_digest() or rec.get("tile") != tile:
-            return None
-        return int(float(rec["traffic_bytes_per_launch"]))
-    except (KeyError, ValueError):
-        return None
+    digest = kernel_source_digest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"k_stencil_{config}_{prec}*.md"))):
+        rec = {}
+        with open(path) as fh:
+            for line in fh:
+                if line.startswith("- record "):
+                    k, _, v = line[len("- record "):].partition(":")
+                    rec[k.strip()] = v.strip()
+        try:
+            if rec.get("source_sha256") == digest and rec.get("tile") == tile:
+                return int(float(rec["traffic_bytes_per_launch"]))
+        except (KeyError, ValueError):
+            continue
+    return None
 
 
 def cpu_baseline(cfg, nstates=24, degree=16):
