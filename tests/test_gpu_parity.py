@@ -148,6 +148,31 @@ def test_apply_h_ld_and_partial_columns():
     assert np.all(got[:, ctx.nd:] == 7.0)     # padding untouched
 
 
+def test_cheb_filter_ld_and_partial_columns():
+    """Filter on 5 of the context's columns with a padded leading dimension
+    (the fused scatter + projection steps run on a partial block)."""
+    torch = _torch()
+    from oracle import chfsi
+    cfg = workloads.make_config("tiny")
+    ctx = _ctx(cfg)
+    D = _rand_D(1, ctx.nhub, 5)
+    ctx.set_hubbard_occupation(D)
+    ld = ctx.nd + 37
+    X = np.zeros((5, ld))
+    X[:, :ctx.nd] = workloads.random_block(ctx.nd, 5, 13)
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.full_like(Xd, 7.0)
+    a, b, aL, m = 1.0, 120.0, -0.5, 5
+    ctx.cheb_filter(Xd, Yd, m, a, b, aL, ncol=5, ld=ld)
+    torch.cuda.synchronize()
+    got = Yd.cpu().numpy()
+    want = chfsi.cheb_filter(_oracle_H(cfg, D[0]).apply, X[:, :ctx.nd], m, a, b, aL)
+    err = np.max(np.abs(got[:, :ctx.nd] - want)) / np.max(np.abs(want))
+    print(f"[gpu] filter partial columns rel err {err:.2e}", flush=True)
+    assert err < 1e-11
+    assert np.all(got[:, ctx.nd:] == 7.0)     # padding untouched
+
+
 def test_apply_h_c2_sampled_columns():
     """Full-size c2 operator (72x72x96, 256 states) in the benchmark's launch
     configuration; the oracle recomputes 3 sampled columns."""
