@@ -117,9 +117,11 @@ __global__ __launch_bounds__(256) void k_nl_brick_c(cplx<R>* __restrict__ Y, int
       ar[pt][q] = y.re;
       ai[pt][q] = y.im;
     }
+  int bjl = -1;   // function indices 64 at a time, passed between lanes
   for (int jj = 0; jj < nj4; jj += 4) {
+    if ((jj & 63) == 0) bjl = jj + lane < nj4 ? bj[jo + jj + lane] : -1;
     const int jl = jj + (lane >> 4);
-    const int jg = bj[jo + jl];
+    const int jg = __shfl(bjl, jl & 63);
     const cplx<R> qv = (sa_ok && jg >= 0) ? Qt[(int64_t)jg * ldq + sa] : cplx<R>();
     const R qr = alpha * qv.re, qi = alpha * qv.im;
     cplx<R> f[4];

@@ -421,9 +421,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int64_t jo = boff[sbk];
     const int nj4 = (bnj[sbk] + 3) & ~3;
     const C* __restrict__ vb = bval + jo * kBrick;
+    int bjl = -1;   // function indices 64 at a time, passed between lanes
     for (int jj = 0; jj < nj4; jj += 4) {
+      if ((jj & 63) == 0) bjl = jj + lane < nj4 ? bj[jo + jj + lane] : -1;
       const int jl = jj + (lane >> 4);
-      const int jg = bj[jo + jl];
+      const int jg = __shfl(bjl, jl & 63);
       const C qv = (sa_ok && jg >= 0) ? Qt[(int64_t)jg * ldq + sa] : C();
       const R qr = alpha * qv.re, qi = alpha * qv.im;
       C f[4];
