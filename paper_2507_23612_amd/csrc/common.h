@@ -132,7 +132,7 @@ struct Ctx {
   std::vector<int64_t> pboff;
   std::vector<int> pbnj;
   std::vector<int64_t> pbsrc, pdest, jrow;
-  int pgroup = 2;   // points per lane and load group in the table order (2, 4 or 16)
+  int pgroup = 2;   // points per lane and load group in the table order (2 or 4)
   int max_ptiles = 0;   // most 16-function slot tiles of any projection brick
   int64_t* d_pboff = nullptr;
   int* d_pbnj = nullptr;

@@ -562,11 +562,8 @@ void launch_project_brick(const Ctx& c, int ik, const T* Y, int ncol, int64_t ld
       launch_k(k_proj_brick_c<typename real_of<T>::type, G>, (unsigned)npb * nst, 256, 0, st, Y, ld, ncol,
                c.d_pboff, c.d_pbnj, (const T*)c.d_pbval[ik], c.d_pdest, part, c.p.ns, c.nd, nst, vec);
   };
-  switch (c.pgroup) {
-    case 2: run(std::integral_constant<int, 2>()); break;
-    case 4: run(std::integral_constant<int, 4>()); break;
-    default: run(std::integral_constant<int, 16>()); break;
-  }
+  if (c.pgroup == 4) run(std::integral_constant<int, 4>());
+  else run(std::integral_constant<int, 2>());
   dim3 g2((ncol + 63) / 64, c.nproj);
   launch_k(k_slot_sum<T>, g2, 1024, 0, st, part, c.p.ns, ncol, c.d_jrow, P, c.nproj, c.dv);
   dim3 g3((ncol + 63) / 64, (unsigned)c.blocks.size());
