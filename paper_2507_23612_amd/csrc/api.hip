@@ -456,6 +456,45 @@ struct RRSwap {   // a context's Rayleigh-Ritz scratch, handle and stream redire
   }
 };
 
+// Side streams of a batch (created on first use, owned by the lead context)
+// and the event pairs that order them against the lead stream.
+hcu_status side_lanes(Ctx& lead, int nl) {
+  while ((int)lead.rr_streams.size() < nl) {
+    hipStream_t st;
+    HCU_HIP_CTX(lead, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    lead.rr_streams.push_back(st);
+  }
+  while ((int)lead.rr_events.size() < 1 + nl) {
+    hipEvent_t e;
+    HCU_HIP_CTX(lead, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    lead.rr_events.push_back(e);
+  }
+  return HCU_OK;
+}
+// the lanes wait for everything queued on the lead stream so far
+hcu_status fan_out(Ctx& lead, int nl) {
+  HCU_HIP_CTX(lead, hipEventRecord(lead.rr_events[0], lead.stream));
+  for (int l = 0; l < nl; ++l) HCU_HIP_CTX(lead, hipStreamWaitEvent(lead.rr_streams[l], lead.rr_events[0], 0));
+  return HCU_OK;
+}
+// the lead stream waits for everything queued on the lanes so far
+hcu_status fan_in(Ctx& lead, int nl) {
+  for (int l = 0; l < nl; ++l) {
+    HCU_HIP_CTX(lead, hipEventRecord(lead.rr_events[1 + l], lead.rr_streams[l]));
+    HCU_HIP_CTX(lead, hipStreamWaitEvent(lead.stream, lead.rr_events[1 + l], 0));
+  }
+  return HCU_OK;
+}
+
+struct StreamSwap {   // a context's kernels queued on another stream for a while
+  Ctx& c;
+  hipStream_t st0;
+  StreamSwap(Ctx& c_, hipStream_t st) : c(c_), st0(c_.stream) {
+    if (st) c.stream = st;
+  }
+  ~StreamSwap() { c.stream = st0; }
+};
+
 template <typename T, typename Op>
 hcu_status rr_all_t(std::vector<BProb>& probs, Ctx& lead, const std::vector<Op>& ys, const std::vector<Op>& hys) {
   const int np = (int)probs.size();
@@ -467,19 +506,10 @@ hcu_status rr_all_t(std::vector<BProb>& probs, Ctx& lead, const std::vector<Op>&
     }
     return HCU_OK;
   }
-  while ((int)lead.rr_streams.size() < nl) {
-    hipStream_t st;
-    HCU_HIP_CTX(lead, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    lead.rr_streams.push_back(st);
-  }
-  while ((int)lead.rr_events.size() < 1 + nl) {
-    hipEvent_t e;
-    HCU_HIP_CTX(lead, hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    lead.rr_events.push_back(e);
-  }
-  HCU_HIP_CTX(lead, hipEventRecord(lead.rr_events[0], lead.stream));
-  for (int l = 0; l < nl; ++l) HCU_HIP_CTX(lead, hipStreamWaitEvent(lead.rr_streams[l], lead.rr_events[0], 0));
-  hcu_status s = HCU_OK;
+  hcu_status s = side_lanes(lead, nl);
+  if (s != HCU_OK) return s;
+  s = fan_out(lead, nl);
+  if (s != HCU_OK) return s;
   std::vector<std::pair<const Ctx*, int>> seen;
   for (int i = 0; i < np && s == HCU_OK; ++i) {
     Ctx& c = *probs[i].c;
@@ -496,11 +526,8 @@ hcu_status rr_all_t(std::vector<BProb>& probs, Ctx& lead, const std::vector<Op>&
     s = rr_t<T>(c, probs[i].sk, (T*)ys[i].out, (T*)hys[i].out);
   }
   // the lead stream waits for every lane, also after a failure
-  for (int l = 0; l < nl; ++l) {
-    HCU_HIP_CTX(lead, hipEventRecord(lead.rr_events[1 + l], lead.rr_streams[l]));
-    HCU_HIP_CTX(lead, hipStreamWaitEvent(lead.stream, lead.rr_events[1 + l], 0));
-  }
-  return s;
+  const hcu_status s2 = fan_in(lead, nl);
+  return s != HCU_OK ? s : s2;
 }
 
 template <typename T>
@@ -564,11 +591,46 @@ hcu_status batch_pass_t(std::vector<BProb>& probs, Ctx& lead, double* filter_ms)
     HCU_HIP_CTX(lead, hipEventRecord(e0, st));
   }
   // ---- execute
-  for (int step = 0; step <= m; ++step) {
+  // With several member contexts, each context's projections and scatters
+  // go to one side stream (context index mod the lane count; the blocks of
+  // one context share its scratch and stay in order on one lane), so that
+  // the small members' kernels overlap; the stencil launches stay on the
+  // lead stream, ordered against the lanes by events.
+  std::vector<int> lane_of(np, 0);
+  int nctx = 0;
+  {
+    std::vector<const Ctx*> seen;
     for (int i = 0; i < np; ++i) {
-      BProb& q = probs[i];
-      if (q.c->nproj > 0 && (step == 0 || !scatter_project_ok<T>(*q.c)))
-        project_t<T>(*q.c, q.spin, q.ik, (const T*)ops[step][i].in, q.c->nd, q.c->p.ns);
+      auto it = std::find(seen.begin(), seen.end(), probs[i].c);
+      if (it == seen.end()) {
+        lane_of[i] = (int)seen.size();
+        seen.push_back(probs[i].c);
+      } else {
+        lane_of[i] = (int)(it - seen.begin());
+      }
+    }
+    nctx = (int)seen.size();
+  }
+  const int nl = std::min(nctx, kRRLanes);
+  if (nl > 1) {
+    hcu_status s = side_lanes(lead, nl);
+    if (s != HCU_OK) return s;
+  }
+  auto lane_stream = [&](int i) -> hipStream_t { return nl > 1 ? lead.rr_streams[lane_of[i] % nl] : nullptr; };
+  for (int step = 0; step <= m; ++step) {
+    bool any_proj = false;
+    for (int i = 0; i < np; ++i)
+      any_proj |= probs[i].c->nproj > 0 && (step == 0 || !scatter_project_ok<T>(*probs[i].c));
+    if (any_proj) {
+      if (nl > 1 && fan_out(lead, nl) != HCU_OK) return HCU_DEVICE;
+      for (int i = 0; i < np; ++i) {
+        BProb& q = probs[i];
+        if (q.c->nproj > 0 && (step == 0 || !scatter_project_ok<T>(*q.c))) {
+          StreamSwap sw(*q.c, lane_stream(i));
+          project_t<T>(*q.c, q.spin, q.ik, (const T*)ops[step][i].in, q.c->nd, q.c->p.ns);
+        }
+      }
+      if (nl > 1 && fan_in(lead, nl) != HCU_OK) return HCU_DEVICE;
     }
     for (size_t l = first[step]; l < first[step + 1]; ++l) {
       ProfScope ps(lead, PK_STENCIL);
@@ -578,9 +640,11 @@ hcu_status batch_pass_t(std::vector<BProb>& probs, Ctx& lead, double* filter_ms)
       hcu_status s = run_stencil_batch<T>(launches[l], lead.d_jobs, persistent ? lead.d_counters : nullptr, st);
       if (s != HCU_OK) return fail(lead, s, "batched stencil launch failed");
     }
+    if (nl > 1 && fan_out(lead, nl) != HCU_OK) return HCU_DEVICE;
     for (int i = 0; i < np; ++i) {
       BProb& q = probs[i];
       if (q.c->nproj > 0) {
+        StreamSwap sw(*q.c, lane_stream(i));
         // steps before the last leave the projections of their output (the
         // next step's input) behind
         if (step < m && scatter_project_ok<T>(*q.c))
@@ -589,6 +653,7 @@ hcu_status batch_pass_t(std::vector<BProb>& probs, Ctx& lead, double* filter_ms)
           scatter_t<T>(*q.c, q.spin, q.ik, (T*)ops[step][i].out, q.c->nd, q.c->p.ns, ops[step][i].alpha);
       }
     }
+    if (nl > 1 && fan_in(lead, nl) != HCU_OK) return HCU_DEVICE;
     if (step == m - 1 && filter_ms) HCU_HIP_CTX(lead, hipEventRecord(e1, st));
   }
   // ---- Rayleigh-Ritz per problem: Y = the last filter output, H Y = the last output
