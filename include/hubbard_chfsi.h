@@ -184,10 +184,11 @@ hcu_status hcu_workspace_size(const hcu_ctx* ctx, size_t* bytes);
  * stream `stream` (NULL = default stream); evaluates V_loc and every atom-
  * centred function on the grid (Sec. II.B) on the device.  The context also
  * takes a few bytes of pinned host memory (eigensolve status copies) and,
- * when Rayleigh-Ritz steps of several blocks run side by side, up to four
- * side streams of its own; their work is ordered after and before the
- * bound stream's by events, so to the caller everything stays ordered on
- * `stream`.  Errors: HCU_OOM if bytes < hcu_workspace_size(), HCU_DEVICE on
+ * when it leads a pass over several blocks (several (spin, k) blocks, or a
+ * batch), up to four side streams of its own for the blocks' Rayleigh-Ritz
+ * steps and the members' projections and scatters; their work is ordered
+ * after and before the bound stream's by events, so to the caller
+ * everything stays ordered on `stream`.  Errors: HCU_OOM if bytes < hcu_workspace_size(), HCU_DEVICE on
  * a HIP error. */
 hcu_status hcu_bind(hcu_ctx* ctx, void* dev_ptr, size_t bytes, void* stream);
 
