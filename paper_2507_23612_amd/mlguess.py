@@ -13,7 +13,7 @@ Everything numeric runs in the library; this module moves arrays and
 collects reports.  Command line (writes one JSON summary):
 
     python -m paper_2507_23612_amd.mlguess --train 2000 --heldout 200 \\
-        --out gpurun_out/mlguess.json
+        --out mlguess.json
 """
 from __future__ import annotations
 
