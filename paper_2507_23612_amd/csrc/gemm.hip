@@ -41,9 +41,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                int ntiles, double* __restrict__ part) {
   using V = typename Acc<T>::V;
   __shared__ T sA[GT][GP], sB[GT][GP], sH[GT][GP];
-  const int2 tl = tiles[blockIdx.x];
+  // XCD-contiguous order, tile fastest: the tiles of one grid chunk read the
+  // same rows of Y and HY and share them in one L2
+  const unsigned lw = xcd_linear();
+  const int bx = (int)(lw % gridDim.x), by = (int)(lw / gridDim.x);
+  const int2 tl = tiles[bx];
   const int i0 = tl.x * GT, j0 = tl.y * GT;
-  const int64_t kb = (int64_t)blockIdx.y * kchunk;
+  const int64_t kb = (int64_t)by * kchunk;
   const int64_t ke = min(nd, kb + kchunk);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wi = wave >> 1, wj = wave & 1;
@@ -92,7 +96,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
     __syncthreads();
   }
-  double* outS = part + ((int64_t)blockIdx.y * ntiles + blockIdx.x) * 2 * GT * GT;
+  double* outS = part + ((int64_t)by * ntiles + bx) * 2 * GT * GT;
   double* outH = outS + GT * GT;
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
@@ -179,8 +183,11 @@ __global__ __launch_bounds__(256) void k_rotate(const T* __restrict__ Y, int64_t
                                                 T* __restrict__ X, int n, int64_t nd) {
   using V = typename Acc<T>::V;
   __shared__ T sY[RK][GT + 1], sC[RK][GT + 1];
-  const int j0 = blockIdx.x * GT;
-  const int64_t p0 = (int64_t)blockIdx.y * GT;
+  // XCD-contiguous order, state tile fastest: the state tiles of one grid
+  // tile read the same rows of Y and share them in one L2
+  const unsigned lw = xcd_linear();
+  const int j0 = (int)(lw % gridDim.x) * GT;
+  const int64_t p0 = (int64_t)(lw / gridDim.x) * GT;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wp = wave >> 1, wj = wave & 1;
   V acc[2][2];
@@ -273,9 +280,13 @@ __global__ __launch_bounds__(256) void k_gram2_c(const T* __restrict__ Y, const 
   T(*sA)[CK + 1] = reinterpret_cast<T(*)[CK + 1]>(raw);
   T(*sB)[CK + 1] = sA + CT;
   T(*sH)[CK + 1] = sB + CT;
-  const int2 tl = tiles[blockIdx.x];
+  // XCD-contiguous order, tile fastest: the tiles of one grid chunk read the
+  // same rows of Y and HY and share them in one L2
+  const unsigned lw = xcd_linear();
+  const int bx = (int)(lw % gridDim.x), by = (int)(lw / gridDim.x);
+  const int2 tl = tiles[bx];
   const int i0 = tl.x * CT, j0 = tl.y * CT;
-  const int64_t kb = (int64_t)blockIdx.y * kchunk;
+  const int64_t kb = (int64_t)by * kchunk;
   const int64_t ke = min(nd, kb + kchunk);
   const int ti = threadIdx.x / 8, tj = (threadIdx.x % 8) * 4;
   T aS[4], aH[4];
@@ -299,7 +310,7 @@ __global__ __launch_bounds__(256) void k_gram2_c(const T* __restrict__ Y, const 
     }
     __syncthreads();
   }
-  double* outS = part + ((int64_t)blockIdx.y * ntiles + blockIdx.x) * 2 * CT * CT * 2;
+  double* outS = part + ((int64_t)by * ntiles + bx) * 2 * CT * CT * 2;
   double* outH = outS + CT * CT * 2;
   for (int q = 0; q < 4; ++q) {
     const int e = ti * CT + tj + q;
@@ -322,9 +333,13 @@ __global__ __launch_bounds__(256) void k_gram2_cm(const cplx<R>* __restrict__ Y,
   using C = cplx<R>;
   __shared__ R sAr[CT][CK + 1], sAi[CT][CK + 1], sBr[CT][CK + 1], sBi[CT][CK + 1], sHr[CT][CK + 1],
       sHi[CT][CK + 1];
-  const int2 tl = tiles[blockIdx.x];
+  // XCD-contiguous order, tile fastest: the tiles of one grid chunk read the
+  // same rows of Y and HY and share them in one L2
+  const unsigned lw = xcd_linear();
+  const int bx = (int)(lw % gridDim.x), by = (int)(lw / gridDim.x);
+  const int2 tl = tiles[bx];
   const int i0 = tl.x * CT, j0 = tl.y * CT;
-  const int64_t kb = (int64_t)blockIdx.y * kchunk;
+  const int64_t kb = (int64_t)by * kchunk;
   const int64_t ke = min(nd, kb + kchunk);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wi = wave >> 1, wj = wave & 1;
@@ -373,7 +388,7 @@ __global__ __launch_bounds__(256) void k_gram2_cm(const cplx<R>* __restrict__ Y,
     }
     __syncthreads();
   }
-  double* outS = part + ((int64_t)blockIdx.y * ntiles + blockIdx.x) * 2 * CT * CT * 2;
+  double* outS = part + ((int64_t)by * ntiles + bx) * 2 * CT * CT * 2;
   double* outH = outS + CT * CT * 2;
   for (int r = 0; r < 4; ++r) {
     const int i = 16 * wi + Acc<R>::row(lane, r);
@@ -453,8 +468,11 @@ __global__ __launch_bounds__(256) void k_rotate_c(const T* __restrict__ Y, int64
   __shared__ __attribute__((aligned(16))) unsigned char raw[(16 * 64 + 16 * CT) * sizeof(T)];
   T(*sY)[64] = reinterpret_cast<T(*)[64]>(raw);
   T(*sC)[CT] = reinterpret_cast<T(*)[CT]>(raw + 16 * 64 * sizeof(T));
-  const int j0 = blockIdx.x * CT;
-  const int64_t p0 = (int64_t)blockIdx.y * 64;
+  // XCD-contiguous order, state tile fastest: the state tiles of one grid
+  // tile read the same rows of Y and share them in one L2
+  const unsigned lw = xcd_linear();
+  const int j0 = (int)(lw % gridDim.x) * CT;
+  const int64_t p0 = (int64_t)(lw / gridDim.x) * 64;
   const int tp = threadIdx.x % 64, tj = (threadIdx.x / 64) * 8;
   T acc[8];
   for (int q = 0; q < 8; ++q) acc[q] = T(0);
@@ -491,8 +509,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   using V = typename Acc<R>::V;
   using C = cplx<R>;
   __shared__ R sYr[RK][GT + 1], sYi[RK][GT + 1], sCr[RK][GT + 1], sCi[RK][GT + 1];
-  const int j0 = blockIdx.x * GT;
-  const int64_t p0 = (int64_t)blockIdx.y * GT;
+  // XCD-contiguous order, state tile fastest: the state tiles of one grid
+  // tile read the same rows of Y and share them in one L2
+  const unsigned lw = xcd_linear();
+  const int j0 = (int)(lw % gridDim.x) * GT;
+  const int64_t p0 = (int64_t)(lw / gridDim.x) * GT;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wp = wave >> 1, wj = wave & 1;
   V acc[2][2][4];   // rr ii ir ri
