@@ -217,7 +217,11 @@ __device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T*
       T acc = T(0);
       for (int p = 1; p <= R; ++p) {
         acc += a.kx[p] * (L[p] + L[-p]);
-        acc += a.ky[p] * (L[p * SW] + L[-p * SW]);
+        // y neighbours inside the thread's own RY rows come from the queue
+        // centres (the same values the plane buffer holds)
+        const T up = (r + p < RY) ? q[(r + p) % RY][R] : L[p * SW];
+        const T dn = (r - p >= 0) ? q[(r - p + RY) % RY][R] : L[-p * SW];
+        acc += a.ky[p] * (up + dn);
         acc += a.kz[p] * (q[r][R + p] + q[r][R - p]);
       }
       const bool active = (x0 + tx < n1) && (y0 + ty * RY + r < n2);
