@@ -34,6 +34,7 @@ struct Bump {
 
 size_t esize(const Ctx& c) { return (c.mixed ? 4 : 8) * (c.any_complex ? 2 : 1); }
 
+constexpr int kInfoPerBlock = 4;   // eigensolve status words per (spin, k): Cholesky, eigensolver, guard
 constexpr size_t kBatchJobBytes = 1 << 20;   // stencil job records of one batched pass (~2900 jobs)
 constexpr unsigned long long kPersistentMinItems = 4096;   // smaller batched launches use one workgroup per item
 
@@ -196,11 +197,13 @@ void small_sym_eigvals(std::vector<double> A, int n, std::vector<double>& ev) {
 // tridiagonal eigensolver did not converge).
 hcu_status generalized_eig(Ctx& c, int n, bool cp, double* lam) {
   rocblas_status r;
+  launch_rr_guard_in(c.d_S, c.d_Hs, n, cp ? 2 : 1, c.d_info, c.stream);
   if (cp) {
     auto* S = (rocblas_double_complex*)c.d_S;
     auto* A = (rocblas_double_complex*)c.d_Hs;
     const rocblas_double_complex one{1.0, 0.0};
     r = rocsolver_zpotrf(c.blas, rocblas_fill_upper, n, S, n, c.d_info);
+    if (r == rocblas_status_success) launch_rr_guard_chol(c.d_S, c.d_Hs, n, 2, c.d_info, c.stream);
     if (r == rocblas_status_success)
       r = rocblas_ztrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_conjugate_transpose,
                         rocblas_diagonal_non_unit, n, n, &one, S, n, A, n);
@@ -215,6 +218,7 @@ hcu_status generalized_eig(Ctx& c, int n, bool cp, double* lam) {
   } else {
     const double one = 1.0;
     r = rocsolver_dpotrf(c.blas, rocblas_fill_upper, n, c.d_S, n, c.d_info);
+    if (r == rocblas_status_success) launch_rr_guard_chol(c.d_S, c.d_Hs, n, 1, c.d_info, c.stream);
     if (r == rocblas_status_success)
       r = rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
                         rocblas_diagonal_non_unit, n, n, &one, c.d_S, n, c.d_Hs, n);
@@ -348,14 +352,15 @@ hcu_status rr_t(Ctx& c, int sk, T* Y, T* HY) {
   }
   if (c.nproj > 0) launch_rotate_proj<T>(c, (const T*)c.d_PY[sk], (const T*)c.d_Cb, (T*)c.d_PX[sk], ns, c.stream);
   HCU_HIP(hipGetLastError());
-  HCU_HIP(hipMemcpyAsync(c.h_info + 2 * sk, c.d_info, 2 * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+  HCU_HIP(hipMemcpyAsync(c.h_info + kInfoPerBlock * sk, c.d_info, 3 * sizeof(int), hipMemcpyDeviceToHost, c.stream));
   return HCU_OK;
 }
 
 // After the stream has synchronised: check the eigensolve, update bounds.
 hcu_status rr_finish(Ctx& c, int sk) {
   const int ns = c.p.ns;
-  const int* info2 = c.h_info + 2 * sk;
+  const int* info2 = c.h_info + kInfoPerBlock * sk;
+  if (info2[2] != 0) return fail(c, HCU_NAN, "non-finite entries in the Rayleigh-Ritz matrices");
   if (info2[0] != 0)
     return fail(c, HCU_NOT_SPD, "Gram matrix of the filtered block not positive definite (potrf info=" +
                                     std::to_string(info2[0]) + ")");
@@ -727,8 +732,16 @@ hcu_status lanczos_t(Ctx& c, int spin, int ik, int steps, double* th_min, double
   return HCU_OK;
 }
 
+hcu_status check_kset(Ctx& c) {
+  if (c.kset_closed) return HCU_OK;
+  return fail(c, HCU_INVALID_ARG,
+              "occupation matrices need a k-point set closed under k -> -k with equal weights (D is real only "
+              "then); the operator and filter calls accept any k");
+}
+
 template <typename T>
 hcu_status occupations_t(Ctx& c) {
+  if (check_kset(c) != HCU_OK) return HCU_INVALID_ARG;
   const int nsk = c.p.nspin * c.p.nk;
   const int nh = (int)c.hub_atoms.size();
   std::vector<double> aux(nsk + nh + c.p.nspin);
@@ -1083,6 +1096,21 @@ hcu_status hcu_create(const hcu_problem* p, hcu_ctx** out) {
   c->any_complex = false;
   for (int k = 0; k < p->nk; ++k)
     if (k_complex(*c, k)) c->any_complex = true;
+  // D is stored real; that is exact when every k-point has a partner -k
+  // (modulo the reciprocal lattice 2 pi / L_a) of equal weight
+  for (int k = 0; k < p->nk && c->kset_closed; ++k) {
+    bool found = false;
+    for (int q = 0; q < p->nk && !found; ++q) {
+      bool same = std::fabs(c->kw[k] - c->kw[q]) <= 1e-12;
+      for (int a = 0; a < 3 && same; ++a) {
+        const double g = 2.0 * M_PI / p->L[a];
+        const double t = (c->kpts[3 * k + a] + c->kpts[3 * q + a]) / g;
+        same = std::fabs(t - std::round(t)) <= 1e-9;
+      }
+      found = same;
+    }
+    c->kset_closed = found;
+  }
   c->p.kpts = nullptr; c->p.kw = nullptr; c->p.pos = nullptr; c->p.atom_species = nullptr; c->p.species = nullptr;
   hcu_status s = build_structure(*c);
   if (s != HCU_OK) { *out = c; return s; }
@@ -1091,7 +1119,7 @@ hcu_status hcu_create(const hcu_problem* p, hcu_ctx** out) {
   int off = 0;
   for (int nm = 0; nm <= kMaxNm; ++nm) { c->nm_offset[nm] = off; off += c->nm_count[nm]; }
   c->D_in.assign((size_t)p->nspin * c->hub_atoms.size() * 25, 0.0);
-  c->h_info_store.assign((size_t)2 * p->nspin * p->nk, 0);
+  c->h_info_store.assign((size_t)kInfoPerBlock * p->nspin * p->nk, 0);
   c->h_info = c->h_info_store.data();
   c->bounds.assign((size_t)3 * p->nspin * p->nk, 0.0);
   c->ws_bytes = layout(*c, nullptr);
@@ -1199,14 +1227,25 @@ hcu_status hcu_bind(hcu_ctx* ctx, void* dev_ptr, size_t bytes, void* stream) {
 }
 
 hcu_status hcu_set_hubbard_occupation(hcu_ctx* ctx, const double* D) {
+  if (!ctx) return HCU_INVALID_ARG;
+  Ctx& c = *ctx;
+  // host validation first: finite, symmetric in the used (2l+1) block
+  if (!D && !c.hub_atoms.empty()) return fail(c, HCU_INVALID_ARG, "null D");
+  const int nh = (int)c.hub_atoms.size();
+  for (size_t i = 0; i < c.D_in.size(); ++i)
+    if (!std::isfinite(D[i])) return fail(c, HCU_NAN, "non-finite entry in D");
+  for (int sp = 0; sp < c.p.nspin; ++sp)
+    for (int h = 0; h < nh; ++h) {
+      const int nm = 2 * c.hub_l[h] + 1;
+      const double* d = D + ((size_t)sp * nh + h) * 25;
+      for (int i = 0; i < nm; ++i)
+        for (int j = i + 1; j < nm; ++j)
+          if (std::fabs(d[i * 5 + j] - d[j * 5 + i]) > 1e-12 * (1.0 + std::fabs(d[i * 5 + j])))
+            return fail(c, HCU_INVALID_ARG, "D must be symmetric");
+    }
   hcu_status s = check_ctx(ctx);
   if (s != HCU_OK) return s;
-  Ctx& c = *ctx;
-  if (!D && !c.hub_atoms.empty()) return fail(c, HCU_INVALID_ARG, "null D");
-  for (size_t i = 0; i < c.D_in.size(); ++i) {
-    if (!std::isfinite(D[i])) return fail(c, HCU_NAN, "non-finite D");
-    c.D_in[i] = D[i];
-  }
+  for (size_t i = 0; i < c.D_in.size(); ++i) c.D_in[i] = D[i];
   s = upload_coupling(c);
   if (s != HCU_OK) return s;
   HCU_HIP(hipStreamSynchronize(c.stream));
@@ -1303,6 +1342,8 @@ hcu_status hcu_scf_begin(hcu_ctx* ctx, const hcu_scf_opts* o) {
   if (!o) return fail(c, HCU_INVALID_ARG, "null options");
   if (o->max_iter < 1 || o->first_passes < 1 || o->lanczos_steps < 1 || o->pulay_history < 1)
     return fail(c, HCU_INVALID_ARG, "bad SCF options");
+  s = check_kset(c);
+  if (s != HCU_OK) return s;
   c.scf_opts = *o;
   c.scf_iter = 0;
   c.scf_have_old = false;

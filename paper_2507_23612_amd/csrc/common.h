@@ -46,6 +46,17 @@ template <typename T> __host__ __device__ inline T make_scalar(double re, double
 template <> __host__ __device__ inline cplx<double> make_scalar<cplx<double>>(double re, double im) { return {re, im}; }
 template <> __host__ __device__ inline cplx<float> make_scalar<cplx<float>>(double re, double im) { return {float(re), float(im)}; }
 
+// ---------------------------------------------------------------- wave-private LDS hand-off
+// Lanes of one wave exchange values through LDS (one lane writes what another
+// reads).  The wavefront-scope release/acquire pair orders the LDS write
+// before the read (and a read before the next overwrite), and the wave
+// barrier keeps the compiler from moving LDS accesses across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------- XCD-aware order
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  xcd_linear() maps the hardware order to a logical order in which
@@ -102,6 +113,7 @@ struct Ctx {
   double h[3];
   bool mixed = false;
   bool any_complex = false;
+  bool kset_closed = true;           // k-point set closed under k -> -k (equal weights): D is real
   std::vector<int> hub_atoms;        // atom index of each Hubbard atom
   std::vector<int> hub_l;
   std::vector<double> hub_U;
@@ -409,6 +421,10 @@ void launch_fermi(const Ctx& c, hipStream_t st);
 template <typename T>
 void launch_occupation_matrix(const Ctx& c, int spin, int ik, const T* PX, hipStream_t st);
 void launch_energies(const Ctx& c, const double* d_coup_all, hipStream_t st);
+// guards of the projected eigenproblem (info[2]: non-finite S or Hs;
+// info[0] != 0: failed Cholesky); both replace the matrices by the identity
+void launch_rr_guard_in(double* S, double* Hs, int n, int cp, int* info, hipStream_t st);
+void launch_rr_guard_chol(double* U, double* Hs, int n, int cp, const int* info, hipStream_t st);
 template <typename T>
 void launch_density(const Ctx& c, const T* X, int64_t ld, const double* occ, double w, double* rho,
                     hipStream_t st);

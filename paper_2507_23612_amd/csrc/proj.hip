@@ -342,6 +342,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         for (int pt = 0; pt < 4; ++pt) acc[pt] = Mf<T>::mfma(a[u], bb[u][pt], acc[pt]);
       }
     }
+    wave_lds_sync();   // the previous piece's reads of yw are done
     for (int pt = 0; pt < 4; ++pt)
       for (int r = 0; r < 4; ++r) {
         const int sl = Mf<T>::row(lane, r);
@@ -351,6 +352,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
     if (ntile == 0) continue;
     // ---- projection of the updated piece k (wave-private LDS, in order)
+    wave_lds_sync();   // every lane's writes of yw are visible
     T bk[16];
     load_piece<T, G>(yw + (lane & 15) * RS, 4 * G, G * q, 64, true, bk);
 #pragma unroll
@@ -439,6 +441,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         ai[pt] = Mf<R>::mfma(qi, f[pt].re, ai[pt]);
       }
     }
+    wave_lds_sync();   // the previous piece's reads of yw are done
     for (int pt = 0; pt < 4; ++pt)
       for (int r = 0; r < 4; ++r) {
         const int sl = Mf<R>::row(lane, r);
@@ -449,6 +452,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
     if (ntile == 0) continue;
     // ---- projection of the updated piece k (wave-private LDS, in order)
+    wave_lds_sync();   // every lane's writes of yw are visible
     C y[16];
     load_piece<C, G>(yw + (lane & 15) * RS, 4 * G, G * q, 64, true, y);
 #pragma unroll

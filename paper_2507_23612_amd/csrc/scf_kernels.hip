@@ -258,3 +258,56 @@ INST(cplx<double>)
 INST(cplx<float>)
 
 }  // namespace hcu
+
+namespace hcu {
+
+// ---------------------------------------------------------------- Rayleigh-Ritz guards
+// The projected problem Hs C = S C diag(lam) is handed to library routines
+// (Cholesky, triangular solves, symmetric eigensolver) that must not see
+// non-finite or half-factorised data.  Before the Cholesky factorisation:
+// any non-finite entry of the upper triangles of S or Hs sets info[2] and
+// replaces both matrices by the identity.  After it: a failed factorisation
+// (info[0] != 0, S not positive definite) replaces the factor and Hs by the
+// identity.  The library steps then run on harmless data and the host
+// reports the recorded status.  One workgroup; n x n column-major, complex
+// interleaved when cp = 2.
+__device__ void set_identity(double* A, int n, int cp) {
+  const int64_t nn = (int64_t)n * n;
+  for (int64_t e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int64_t i = e % n, j = e / n;
+    A[cp * e] = i == j ? 1.0 : 0.0;
+    if (cp == 2) A[cp * e + 1] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_rr_guard_in(double* S, double* Hs, int n, int cp, int* info) {
+  int bad = 0;
+  const int64_t nn = (int64_t)n * n;
+  for (int64_t e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int64_t i = e % n, j = e / n;
+    if (i > j) continue;   // upper triangle only (what the factorisation reads)
+    for (int h = 0; h < cp; ++h)
+      if (!isfinite(S[cp * e + h]) || !isfinite(Hs[cp * e + h])) bad = 1;
+  }
+  bad = __syncthreads_or(bad);
+  if (bad) {
+    set_identity(S, n, cp);
+    set_identity(Hs, n, cp);
+  }
+  if (threadIdx.x == 0) info[2] = bad;
+}
+
+__global__ __launch_bounds__(1024) void k_rr_guard_chol(double* U, double* Hs, int n, int cp, const int* info) {
+  if (info[0] == 0) return;
+  set_identity(U, n, cp);
+  set_identity(Hs, n, cp);
+}
+
+void launch_rr_guard_in(double* S, double* Hs, int n, int cp, int* info, hipStream_t st) {
+  launch_k(k_rr_guard_in, 1, 1024, 0, st, S, Hs, n, cp, info);
+}
+void launch_rr_guard_chol(double* U, double* Hs, int n, int cp, const int* info, hipStream_t st) {
+  launch_k(k_rr_guard_chol, 1, 1024, 0, st, U, Hs, n, cp, info);
+}
+
+}  // namespace hcu

@@ -260,6 +260,24 @@ class HcuContext:
         if st != HCU_OK:
             raise HcuError(st, self.lib.hcu_last_error(self.h).decode())
 
+    def _block(self, X, ncol, ld, name):
+        """Device pointer of a block argument after checking that the kernels
+        will stay inside it: a contiguous tensor on the context's device, of
+        the context's element type, holding ncol states of ld >= nd values."""
+        t = self.torch
+        if not isinstance(X, t.Tensor):
+            raise HcuError(HCU_INVALID_ARG, f"{name}: expected a torch tensor")
+        if X.device.type != "cuda" or (X.device.index or 0) != (self.device.index or 0):
+            raise HcuError(HCU_INVALID_ARG, f"{name}: tensor on {X.device}, context on {self.device}")
+        if X.dtype != self.dtype:
+            raise HcuError(HCU_INVALID_ARG, f"{name}: dtype {X.dtype}, context uses {self.dtype}")
+        if not X.is_contiguous():
+            raise HcuError(HCU_INVALID_ARG, f"{name}: tensor must be contiguous")
+        if ncol < 1 or ld < self.nd or (ncol - 1) * ld + self.nd > X.numel():
+            raise HcuError(HCU_INVALID_ARG, f"{name}: {ncol} states of leading dimension {ld} do not fit "
+                                            f"a tensor of shape {tuple(X.shape)} (nd = {self.nd})")
+        return C.c_void_p(X.data_ptr())
+
     def close(self):
         if self.h:
             self.lib.hcu_destroy(self.h)
@@ -277,34 +295,33 @@ class HcuContext:
         self._check(self.lib.hcu_set_hubbard_occupation(self.h, _dptr(D)))
 
     def set_start(self, spin, ik, X0, v0):
-        assert X0.is_cuda and v0.is_cuda and X0.dtype == self.dtype and v0.dtype == self.dtype
-        X0 = X0.contiguous()
-        v0 = v0.contiguous()
-        self._check(self.lib.hcu_set_start(self.h, spin, ik, C.c_void_p(X0.data_ptr()), C.c_void_p(v0.data_ptr())))
+        x = self._block(X0, self.ns, self.nd, "X0")
+        v = self._block(v0, 1, self.nd, "v0")
+        self._check(self.lib.hcu_set_start(self.h, spin, ik, x, v))
         self.stream.synchronize()
 
     def apply_h(self, X, Y, ncol=None, ld=None, spin=0, ik=0):
         """Y = H X; X, Y torch tensors of shape (ncol, ld) (state-major rows)."""
         ncol = ncol or X.shape[0]
         ld = ld or X.shape[1]
-        self._check(self.lib.hcu_apply_h(self.h, spin, ik, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),
-                                         ncol, ld))
+        x, y = self._block(X, ncol, ld, "X"), self._block(Y, ncol, ld, "Y")
+        self._check(self.lib.hcu_apply_h(self.h, spin, ik, x, y, ncol, ld))
 
     def cheb_filter(self, X, Y, m, a, b, aL, ncol=None, ld=None, spin=0, ik=0):
         ncol = ncol or X.shape[0]
         ld = ld or X.shape[1]
-        self._check(self.lib.hcu_cheb_filter(self.h, spin, ik, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),
-                                             ncol, ld, m, a, b, aL))
+        x, y = self._block(X, ncol, ld, "X"), self._block(Y, ncol, ld, "Y")
+        self._check(self.lib.hcu_cheb_filter(self.h, spin, ik, x, y, ncol, ld, m, a, b, aL))
 
     def gram(self, Y, HY, ncol=None, ld=None):
         """(S, Hs) = (Y^H Y dV, Y^H HY dV) as numpy arrays."""
         ncol = ncol or Y.shape[0]
         ld = ld or Y.shape[1]
+        y, hy = self._block(Y, ncol, ld, "Y"), self._block(HY, ncol, ld, "HY")
         dt = np.complex128 if self.complex else np.float64
         S = np.zeros((ncol, ncol), dt)
         Hs = np.zeros((ncol, ncol), dt)
-        self._check(self.lib.hcu_gram(self.h, C.c_void_p(Y.data_ptr()), C.c_void_p(HY.data_ptr()), ncol, ld,
-                                      S.ctypes.data_as(C.POINTER(C.c_double)),
+        self._check(self.lib.hcu_gram(self.h, y, hy, ncol, ld, S.ctypes.data_as(C.POINTER(C.c_double)),
                                       Hs.ctypes.data_as(C.POINTER(C.c_double))))
         # column-major on the device side: transpose
         return S.T.copy(), Hs.T.copy()
@@ -313,10 +330,12 @@ class HcuContext:
         """X = Y C (C numpy ncol x ncol)."""
         ncol = ncol or Y.shape[0]
         ld = ld or Y.shape[1]
+        y, x = self._block(Y, ncol, ld, "Y"), self._block(X, ncol, ld, "X")
         dt = np.complex128 if self.complex else np.float64
         Cf = np.asfortranarray(np.asarray(Cm, dt))
-        self._check(self.lib.hcu_rotate(self.h, C.c_void_p(Y.data_ptr()), Cf.ctypes.data_as(C.POINTER(C.c_double)),
-                                        C.c_void_p(X.data_ptr()), ncol, ld))
+        if Cf.shape != (ncol, ncol):
+            raise HcuError(HCU_INVALID_ARG, f"C has shape {Cf.shape}, expected ({ncol}, {ncol})")
+        self._check(self.lib.hcu_rotate(self.h, y, Cf.ctypes.data_as(C.POINTER(C.c_double)), x, ncol, ld))
 
     def lanczos_bounds(self, spin=0, ik=0, steps=10):
         tmin, up = C.c_double(), C.c_double()
@@ -337,7 +356,9 @@ class HcuContext:
         st = self.lib.hcu_scf(self.h, C.byref(o), C.byref(r))
         if st != HCU_OK and not (st == HCU_NOT_CONVERGED and not raise_on_nonconv):
             self._check(st)
-        return {k: getattr(r, k) for k, _ in hcu_scf_report._fields_}
+        out = {k: getattr(r, k) for k, _ in hcu_scf_report._fields_}
+        out["status"] = st
+        return out
 
     def get_sizes(self):
         z = hcu_sizes()
@@ -549,35 +570,63 @@ class HcuMlp:
         self._check(self.lib.hcu_mlp_get_scaling(self.h, *[_fptr(v) for v in a]))
         return a
 
+    def _mat(self, A, rows, width, name):
+        """Device pointer of a row-major FP32 matrix argument holding at least
+        `rows` rows of `width` values on the object's device."""
+        t = self.torch
+        if not isinstance(A, t.Tensor) or A.device.type != "cuda" or \
+                (A.device.index or 0) != (self.device.index or 0):
+            raise HcuError(HCU_INVALID_ARG, f"{name}: expected a tensor on {self.device}")
+        if A.dtype != t.float32 or not A.is_contiguous() or A.dim() != 2:
+            raise HcuError(HCU_INVALID_ARG, f"{name}: expected a contiguous 2-D float32 tensor")
+        if A.shape[1] != width or A.shape[0] < rows:
+            raise HcuError(HCU_INVALID_ARG, f"{name}: shape {tuple(A.shape)}, need >= {rows} rows of {width}")
+        return C.c_void_p(A.data_ptr())
+
+    def _rows(self, X, T, idx, batch):
+        """Pointers of a training batch: X, T and the optional row index
+        (int32, every entry a row of X and T)."""
+        nrow = int(X.shape[0]) if hasattr(X, "shape") else 0
+        x = self._mat(X, 1 if idx is not None else batch, self.dims[0], "X")
+        tt = self._mat(T, nrow, self.dims[-1], "T")
+        if idx is None:
+            return x, tt, C.c_void_p(0)
+        t = self.torch
+        if not isinstance(idx, t.Tensor) or idx.dtype != t.int32 or idx.dim() != 1 or not idx.is_contiguous() \
+                or idx.device != X.device or idx.shape[0] < batch:
+            raise HcuError(HCU_INVALID_ARG, "idx: expected a contiguous 1-D int32 tensor on the device")
+        if batch > 0:
+            lo, hi = int(idx[:batch].min()), int(idx[:batch].max())
+            if lo < 0 or hi >= nrow:
+                raise HcuError(HCU_INVALID_ARG, f"idx: rows {lo}..{hi} outside 0..{nrow - 1}")
+        return x, tt, C.c_void_p(idx.data_ptr())
+
     def fit_scaling(self, X, T):
-        assert X.is_cuda and T.is_cuda and X.dtype == self.torch.float32 and T.dtype == self.torch.float32
-        self._check(self.lib.hcu_mlp_fit_scaling(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
-                                                 int(X.shape[0])))
+        rows = int(X.shape[0])
+        x, tt = self._mat(X, rows, self.dims[0], "X"), self._mat(T, rows, self.dims[-1], "T")
+        self._check(self.lib.hcu_mlp_fit_scaling(self.h, x, tt, rows))
 
     def forward(self, X, bf16=False):
         X = X.contiguous()
+        x = self._mat(X, int(X.shape[0]), self.dims[0], "X")
         Y = self.torch.empty((X.shape[0], self.dims[-1]), dtype=self.torch.float32, device=self.device)
-        self._check(self.lib.hcu_mlp_forward(self.h, C.c_void_p(X.data_ptr()), int(X.shape[0]),
-                                             C.c_void_p(Y.data_ptr()), 1 if bf16 else 0))
+        self._check(self.lib.hcu_mlp_forward(self.h, x, int(X.shape[0]), C.c_void_p(Y.data_ptr()),
+                                             1 if bf16 else 0))
         return Y
-
-    @staticmethod
-    def _idx_ptr(idx):
-        return C.c_void_p(idx.data_ptr()) if idx is not None else C.c_void_p(0)
 
     def gradient(self, X, T, idx=None, batch=None):
         batch = int(idx.shape[0]) if idx is not None else int(X.shape[0]) if batch is None else batch
+        x, tt, ip = self._rows(X, T, idx, batch)
         g = np.zeros(self.nparam, np.float32)
         loss = C.c_double()
-        self._check(self.lib.hcu_mlp_gradient(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
-                                              self._idx_ptr(idx), batch, _fptr(g), C.byref(loss)))
+        self._check(self.lib.hcu_mlp_gradient(self.h, x, tt, ip, batch, _fptr(g), C.byref(loss)))
         return loss.value, g
 
     def train_step(self, X, T, idx=None, lr=1e-3, want_loss=True):
         batch = int(idx.shape[0]) if idx is not None else int(X.shape[0])
+        x, tt, ip = self._rows(X, T, idx, batch)
         loss = C.c_double()
-        self._check(self.lib.hcu_mlp_train_step(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
-                                                self._idx_ptr(idx), batch, C.c_float(lr),
+        self._check(self.lib.hcu_mlp_train_step(self.h, x, tt, ip, batch, C.c_float(lr),
                                                 C.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
 

@@ -86,3 +86,30 @@ def test_batch_and_mlp_validate_on_host():
     assert lib.hcu_mlp_create(bad, 3, 16, ctypes.byref(m)) == hcu.HCU_INVALID_ARG
     assert lib.hcu_mlp_last_error(m)
     lib.hcu_mlp_destroy(m)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_occupation_input_validated_on_host():
+    """A non-finite or non-symmetric occupation matrix is refused before the
+    context is even asked for device memory."""
+    import numpy as np
+    import workloads
+    from paper_2507_23612_amd import hcu
+    lib = hcu.load_library()
+    cfg = workloads.make_config("tiny")
+    prob = hcu.Problem(cfg)
+    h = ctypes.c_void_p()
+    assert lib.hcu_create(ctypes.byref(prob.p), ctypes.byref(h)) == hcu.HCU_OK
+    nh = lib.hcu_num_hubbard_atoms(h)
+    D = np.zeros((1, nh, 5, 5))
+    D[0, :] = 0.2 * np.eye(5)
+    ptr = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    bad = D.copy()
+    bad[0, 0, 1, 3] = np.nan
+    assert lib.hcu_set_hubbard_occupation(h, ptr(bad)) == hcu.HCU_NAN
+    bad = D.copy()
+    bad[0, 1, 0, 4] = 0.05                     # D[0][4] != D[4][0]
+    assert lib.hcu_set_hubbard_occupation(h, ptr(bad)) == hcu.HCU_INVALID_ARG
+    # a valid D passes validation and stops at the missing binding
+    assert lib.hcu_set_hubbard_occupation(h, ptr(D)) == hcu.HCU_NOT_BOUND
+    lib.hcu_destroy(h)

@@ -1,0 +1,148 @@
+"""Parity of the Chebyshev filter at the production shapes, where every step
+after the first takes its projections from the fused scatter + projection
+kernel (several 64-state tiles, the kernel variants the benchmark runs),
+against the oracle's filter on sampled columns (the filter acts column by
+column, so a few oracle columns are an exact check of those columns).
+
+Bars:
+  * FP64: 1e-11 relative to the largest output value (summation order is the
+    only difference; 16 steps).
+  * FP32 blocks (mixed precision) against the FP64 oracle on the same
+    FP32-rounded input: each H application rounds at about 2^-24 of
+    |H||y| <= b |y|, the scaled step divides by e = (b - a)/2, and the
+    rounding of every one of the m steps is carried to the output by the
+    remaining recurrence at most with the signal's own growth, so the error
+    relative to the largest output stays below m * 2^-24 * (2 b / e) * 100
+    (the factor 100 covers the element-wise spread of the output against
+    its largest value): 16 * 6e-8 * 4 * 100 ~ 4e-4.  The bar is 4e-4.
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+A, B, AL, M = 1.5, 190.0, -0.3, 16
+FP32_BAR = 4e-4
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rand_D(nhub, seed):
+    rng = np.random.default_rng(seed)
+    D = np.zeros((1, nhub, 5, 5))
+    for h in range(nhub):
+        A_ = rng.normal(size=(5, 5)) * 0.05
+        D[0, h] = 0.2 * np.eye(5) + A_ + A_.T
+    return D
+
+
+def _oracle_filter(cfg, D, X_cols, k=(0.0, 0.0, 0.0)):
+    from oracle import chfsi
+    from oracle.hamiltonian import Hamiltonian
+    H = Hamiltonian(cfg, k, D=list(D))
+    return chfsi.cheb_filter(H.apply, X_cols, M, A, B, AL)
+
+
+def _run(cfg, precision, X_host, cols, seed_d, k=None):
+    """Filter the full block on the GPU through the C ABI; returns the sampled
+    output columns, the oracle's columns and the context sizes."""
+    torch = _torch()
+    from paper_2507_23612_amd import hcu
+    ctx = hcu.HcuContext(cfg, precision)
+    sizes = ctx.get_sizes()
+    D = _rand_D(ctx.nhub, seed_d)
+    ctx.set_hubbard_occupation(D)
+    Xd = torch.from_numpy(X_host).to(ctx.device).to(ctx.dtype)
+    Yd = torch.empty_like(Xd)
+    ctx.cheb_filter(Xd, Yd, M, A, B, AL)
+    torch.cuda.synchronize()
+    got = Yd[cols].cpu().numpy()
+    X_in = Xd[cols].cpu().numpy().astype(np.complex128 if ctx.complex else np.float64)
+    del Xd, Yd
+    ctx.close()
+    torch.cuda.empty_cache()
+    want = _oracle_filter(cfg, D[0], X_in, k if k is not None else (0.0, 0.0, 0.0))
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    return err, sizes
+
+
+def test_cheb_filter_c2_fp64_fused_sampled_columns():
+    """48-atom cell, 72x72x96, 256 states (four 64-state tiles), FP64,
+    degree 16: the fused kernel with up to four 16-function slot tiles."""
+    cfg = workloads.make_config("c2")
+    print("[gpu] filter c2 fp64 full block (256 states), oracle on 4 columns", flush=True)
+    X = workloads.random_block(int(np.prod(cfg["n"])), cfg["ns"], 31)
+    cols = [5, 70, 141, 250]                      # one column in each 64-state tile
+    err, sizes = _run(cfg, "fp64", X, cols, 41)
+    print(f"[gpu] filter c2 fp64: rel err {err:.2e}, most functions per 256-point brick "
+          f"{sizes['max_brick_functions']}", flush=True)
+    assert err < 1e-11
+
+
+def test_cheb_filter_c3_mixed_fused_sampled_columns():
+    """108-atom cell, 108x108x96, 640 states (ten 64-state tiles), FP32
+    blocks: the fused kernel's eight-slot-tile variant (more than 64
+    functions touch some 256-point brick)."""
+    cfg = workloads.make_config("c3")
+    nd = int(np.prod(cfg["n"]))
+    print("[gpu] filter c3 mixed full block (640 states), oracle on 4 columns", flush=True)
+    X = np.random.default_rng(32).random((cfg["ns"], nd), dtype=np.float32) - np.float32(0.5)
+    cols = [3, 200, 411, 637]
+    err, sizes = _run(cfg, "mixed", X, cols, 42)
+    print(f"[gpu] filter c3 mixed: rel err {err:.2e}, most functions per 256-point brick "
+          f"{sizes['max_brick_functions']}", flush=True)
+    assert sizes["max_brick_functions"] > 64      # the NT = 8 instantiation ran
+    assert err < FP32_BAR
+
+
+def test_cheb_filter_c2_complex_fp32_block_sampled_columns():
+    """One Bloch block of the c2 cell at a k-point of the shifted 2x2x2 set,
+    complex FP32 (the block type of the batched spin/k workload): the fused
+    complex kernel over four 64-state tiles."""
+    cfg = workloads.make_config("c2")
+    kpts, _ = workloads.tio2.mp_shifted_222(cfg["L"])
+    cfg["kpts"] = kpts[5:6]
+    cfg["kw"] = np.ones(1)
+    nd = int(np.prod(cfg["n"]))
+    print("[gpu] filter c2 complex fp32 block (256 states), oracle on 3 columns", flush=True)
+    X = workloads.random_block(nd, cfg["ns"], 33, complex_=True).astype(np.complex64)
+    cols = [0, 100, 255]
+    err, _ = _run(cfg, "mixed", X, cols, 43, k=kpts[5])
+    print(f"[gpu] filter c2 complex fp32: rel err {err:.2e}", flush=True)
+    assert err < FP32_BAR
+
+
+def test_apply_h_lowdin_off_matches_oracle():
+    """The paper-literal reading (continuum-normalised orbitals without
+    Loewdin orthonormalisation) through the operator, FP64, on the 6-atom
+    cell whose Hubbard supports overlap their periodic images."""
+    torch = _torch()
+    from oracle.hamiltonian import Hamiltonian
+    from paper_2507_23612_amd import hcu
+    cfg = workloads.make_config("c1")
+    cfg["lowdin"] = False
+    ctx = hcu.HcuContext(cfg)
+    D = _rand_D(ctx.nhub, 44)
+    ctx.set_hubbard_occupation(D)
+    X = workloads.random_block(ctx.nd, ctx.ns, 34)
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.empty_like(Xd)
+    ctx.apply_h(Xd, Yd)
+    torch.cuda.synchronize()
+    want = Hamiltonian(cfg, D=list(D[0])).apply(X)
+    err = np.max(np.abs(Yd.cpu().numpy() - want)) / np.max(np.abs(want))
+    # the orbitals really differ from the orthonormalised ones
+    cfg_on = dict(cfg)
+    cfg_on["lowdin"] = True
+    other = Hamiltonian(cfg_on, D=list(D[0])).apply(X)
+    print(f"[gpu] apply_h lowdin off: rel err {err:.2e} "
+          f"(lowdin on differs by {np.max(np.abs(other - want)) / np.max(np.abs(want)):.2e})", flush=True)
+    assert np.max(np.abs(other - want)) > 1e-6 * np.max(np.abs(want))
+    assert err < 1e-12

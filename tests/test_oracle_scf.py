@@ -128,3 +128,91 @@ def test_free_energy_stationary_at_fixed_point(tiny_run):
     # scale of a non-stationary slope: derivative of the band energy alone
     band_slope = abs(sum(np.trace(-0.147 * x @ d) for x, d in zip(dirs, D))) * 2
     assert abs(slope) < 1e-4 * band_slope
+
+
+def test_d_vec_roundtrip_complex_hermitian():
+    """Complex (Bloch) occupation matrices: the upper-triangle vector keeps
+    the real and imaginary parts, and mapping back rebuilds the Hermitian
+    matrix.  A wrong conjugation of the lower triangle, or an imaginary part
+    left on the diagonal, breaks the round trip or the Hermiticity."""
+    rng = np.random.default_rng(5)
+    D = []
+    for s in range(2):
+        row = []
+        for m in (5, 3):
+            A = rng.normal(size=(m, m)) + 1j * rng.normal(size=(m, m))
+            row.append(0.5 * (A + A.conj().T))
+        D.append(row)
+    v = scf.d_to_vec(D)
+    nreal = 2 * (15 + 6)
+    assert v.shape == (2 * nreal,)            # real parts, then imaginary parts
+    back = scf.vec_to_d(v, D)
+    for s in range(2):
+        for i in range(2):
+            np.testing.assert_allclose(back[s][i], D[s][i], atol=1e-15)
+            assert np.max(np.abs(back[s][i] - back[s][i].conj().T)) == 0.0
+            assert np.all(np.imag(np.diag(back[s][i])) == 0.0)
+    # the map is linear: mixing two matrices through the vector equals mixing
+    # the matrices
+    E = [[1j * (x - x.conj().T) / 2 + (x + x.conj().T) / 2 for x in row] for row in D]
+    w = scf.vec_to_d(0.3 * scf.d_to_vec(D) + 0.7 * scf.d_to_vec(E), D)
+    for s in range(2):
+        for i in range(2):
+            np.testing.assert_allclose(w[s][i], 0.3 * D[s][i] + 0.7 * E[s][i], atol=1e-14)
+
+
+def test_pulay_history_truncation():
+    """With history h only the last h + 1 (x, f) pairs enter a step: a mixer
+    fed a long sequence gives the same step as a fresh mixer fed just the last
+    h + 1 pairs (dropping the oldest pair, not the newest, and dropping at
+    all, are both checked); on a contractive linear map whose dimension
+    exceeds the history the truncated iteration still reaches the fixed
+    point."""
+    rng = np.random.default_rng(7)
+    dim, h = 9, 3
+    xs = [rng.normal(size=dim) for _ in range(12)]
+    fs = [rng.normal(size=dim) for _ in range(12)]
+    long_mix = scf.Pulay(history=h, beta=0.3)
+    for x, f in zip(xs, fs):
+        out_long = long_mix.step(x, f)
+    short_mix = scf.Pulay(history=h, beta=0.3)
+    for x, f in zip(xs[-(h + 1):], fs[-(h + 1):]):
+        out_short = short_mix.step(x, f)
+    np.testing.assert_allclose(out_long, out_short, rtol=1e-13, atol=1e-13)
+    full_mix = scf.Pulay(history=50, beta=0.3)
+    for x, f in zip(xs, fs):
+        out_full = full_mix.step(x, f)
+    assert np.max(np.abs(out_full - out_long)) > 1e-6
+    Q, _ = np.linalg.qr(rng.normal(size=(dim, dim)))
+    A = Q @ np.diag(rng.uniform(-0.7, 0.7, dim)) @ Q.T
+    b = rng.normal(size=dim)
+    xstar = np.linalg.solve(np.eye(dim) - A, b)
+    mix = scf.Pulay(history=h, beta=0.3)
+    x = np.zeros(dim)
+    for _ in range(60):
+        x = mix.step(x, A @ x + b - x)
+    assert np.linalg.norm(x - xstar) < 1e-9 * np.linalg.norm(xstar)
+
+
+def test_spin_polarised_density_integrates_to_electron_count():
+    """nspin = 2: each spin density carries g_s = 1, and the two integrate
+    (trapezoid rule) to N_e with the Fermi level found with g_s = 1; with
+    the unpolarised factor 2 they would give 2 N_e."""
+    rng = np.random.default_rng(9)
+    nd, ns, dv, nelec = 300, 12, 0.01, 9.0
+    kw = np.array([0.25, 0.75])
+    X_sk, eigs = [], np.zeros((2, 2, ns))
+    for s in range(2):
+        row = []
+        for k in range(2):
+            Q, _ = np.linalg.qr(rng.normal(size=(nd, ns)) + 1j * rng.normal(size=(nd, ns)))
+            row.append(Q.T / np.sqrt(dv))           # dV sum |x|^2 = 1, orthogonal
+            eigs[s, k] = np.sort(rng.uniform(-1, 1, ns))
+        X_sk.append(row)
+    mu = scf.fermi_level(eigs, kw, nelec, 0.05, 1.0)
+    f = scf.occupations(eigs, mu, 0.05)
+    rho = scf.density(X_sk, [[f[s, k] for k in range(2)] for s in range(2)], kw, 2)
+    assert rho.shape == (2, nd)
+    assert abs(dv * rho.sum() - nelec) < 1e-10
+    for s in range(2):
+        assert abs(dv * rho[s].sum() - float(np.sum(kw[:, None] * f[s]))) < 1e-10
