@@ -154,25 +154,32 @@ size_t gram_partial_elems(int n, int64_t nd) {
   return (size_t)nc * nt * 2 * GT * GT;
 }
 
-// upper-triangular tile list (i <= j) of an n x n Gram matrix
+// Upper-triangular tile list (i <= j) of an n x n Gram matrix, column by
+// column: tile t = j (j + 1) / 2 + i.  Every prefix is the list of a smaller
+// matrix, so the list built for the context's states serves any ncol <= ns.
 std::vector<int2> gram_tiles(int n, bool cplx_) {
   const int t = cplx_ ? 32 : 64;
   const int t1 = (n + t - 1) / t;
   std::vector<int2> tl;
-  for (int i = 0; i < t1; ++i)
-    for (int j = i; j < t1; ++j) tl.push_back(make_int2(i, j));
+  for (int j = 0; j < t1; ++j)
+    for (int i = 0; i <= j; ++i) tl.push_back(make_int2(i, j));
   return tl;
+}
+
+template <typename T>
+void launch_gram2_into(const T* Y, const T* HY, int ncol, int64_t ld, int64_t nd, double dv, const int2* tiles,
+                       double* part, double* S, double* Hs, hipStream_t st) {
+  int t1, nt, nc;
+  int64_t kc;
+  gram_plan(ncol, nd, t1, nt, kc, nc);
+  launch_k(k_gram2<T>, dim3(nt, nc), 256, 0, st, Y, HY, ld, ncol, nd, kc, tiles, nt, part);
+  launch_k(k_gram_reduce, dim3(nt, GT * GT / 256, 2), 256, 0, st, part, nc, nt, tiles, ncol, dv, S, Hs);
 }
 
 template <typename T>
 void launch_gram2(const Ctx& c, const T* Y, const T* HY, int ncol, int64_t ld, double* S, double* Hs,
                   hipStream_t st) {
-  int t1, nt, nc;
-  int64_t kc;
-  gram_plan(ncol, c.nd, t1, nt, kc, nc);
-  const int2* d_tiles = c.d_tiles;
-  launch_k(k_gram2<T>, dim3(nt, nc), 256, 0, st, Y, HY, ld, ncol, c.nd, kc, d_tiles, nt, c.d_part);
-  launch_k(k_gram_reduce, dim3(nt, GT * GT / 256, 2), 256, 0, st, c.d_part, nc, nt, d_tiles, ncol, c.dv, S, Hs);
+  launch_gram2_into<T>(Y, HY, ncol, ld, c.nd, c.dv, c.d_tiles, c.d_part, S, Hs, st);
 }
 
 // X = Y C, computed as X^T = C^T Y^T so that each lane's outputs run along the
@@ -448,17 +455,22 @@ size_t gram_partial_elems_c(int n, int64_t nd) {
 }
 
 template <typename T>
-void launch_gram2_c(const Ctx& c, const T* Y, const T* HY, int ncol, int64_t ld, double* S, double* Hs,
-                    hipStream_t st) {
+void launch_gram2_c_into(const T* Y, const T* HY, int ncol, int64_t ld, int64_t nd, double dv, const int2* tiles,
+                         double* part, double* S, double* Hs, hipStream_t st) {
   int t1, nt, nc;
   int64_t kc;
-  gram_plan_c(ncol, c.nd, t1, nt, kc, nc);
-  const int2* d_tiles = c.d_tiles;
+  gram_plan_c(ncol, nd, t1, nt, kc, nc);
   if constexpr (std::is_same<T, cplx<float>>::value)
-    launch_k(k_gram2_cm<float>, dim3(nt, nc), 256, 0, st, Y, HY, ld, ncol, c.nd, kc, d_tiles, nt, c.d_part);
+    launch_k(k_gram2_cm<float>, dim3(nt, nc), 256, 0, st, Y, HY, ld, ncol, nd, kc, tiles, nt, part);
   else
-    launch_k(k_gram2_c<T>, dim3(nt, nc), 256, 0, st, Y, HY, ld, ncol, c.nd, kc, d_tiles, nt, c.d_part);
-  launch_k(k_gram_reduce_c, nt, 256, 0, st, c.d_part, nc, nt, d_tiles, ncol, c.dv, S, Hs);
+    launch_k(k_gram2_c<T>, dim3(nt, nc), 256, 0, st, Y, HY, ld, ncol, nd, kc, tiles, nt, part);
+  launch_k(k_gram_reduce_c, nt, 256, 0, st, part, nc, nt, tiles, ncol, dv, S, Hs);
+}
+
+template <typename T>
+void launch_gram2_c(const Ctx& c, const T* Y, const T* HY, int ncol, int64_t ld, double* S, double* Hs,
+                    hipStream_t st) {
+  launch_gram2_c_into<T>(Y, HY, ncol, ld, c.nd, c.dv, c.d_tiles, c.d_part, S, Hs, st);
 }
 
 // X = Y C for complex blocks: workgroup = 64 grid points x 32 states.

@@ -333,6 +333,38 @@ def test_gram_and_rotate_match_numpy(ns):
     np.testing.assert_allclose(Xd.cpu().numpy(), (Y.T @ Cm).T, atol=1e-12 * np.abs(Y).max() * ns)
 
 
+@pytest.mark.parametrize("kind", ["f64", "c64"])
+def test_gram_fewer_columns_than_states(kind):
+    """hcu_gram on the first ncol < ns states where ncol spans fewer output
+    tiles than ns (the tile list built for ns must serve ncol): every entry
+    of S and Hs against numpy."""
+    torch = _torch()
+    cfg = workloads.make_config("tiny")
+    cfg["ns"] = 200
+    cp = kind == "c64"
+    if cp:
+        cfg["kpts"] = np.array([KPT])
+    ctx = _ctx(cfg, "fp64" if kind == "f64" else "mixed")
+    dv = float(np.prod(cfg["L"] / cfg["n"]))
+    ncol = 130
+    Y = workloads.random_block(ctx.nd, 200, 23, complex_=cp)
+    Z = workloads.random_block(ctx.nd, 200, 24, complex_=cp)
+    Yd = torch.from_numpy(Y).cuda().to(ctx.dtype)
+    Zd = torch.from_numpy(Z).cuda().to(ctx.dtype)
+    S, Hs = ctx.gram(Yd, Zd, ncol=ncol, ld=ctx.nd)
+    Yr = Yd.cpu().numpy().astype(np.complex128 if cp else np.float64)[:ncol]
+    Zr = Zd.cpu().numpy().astype(np.complex128 if cp else np.float64)[:ncol]
+    Sw = dv * Yr.conj() @ Yr.T
+    Hw = dv * Yr.conj() @ Zr.T
+    bar = 1e-12 if kind == "f64" else 1e-5
+    assert np.max(np.abs(S - Sw)) < bar * np.abs(Sw).max()
+    t = 32 if cp else 64
+    for i in range(ncol):
+        for j in range(i, ncol):
+            want = 0.5 * (Hw[i, j] + np.conj(Hw[j, i])) if i // t == j // t else Hw[i, j]
+            assert abs(Hs[i, j] - want) < bar * np.abs(Hw).max()
+
+
 def test_apply_h_mixed_c1():
     """Mixed mode: FP32 blocks and tables (FP32 stencil, FP32 MFMA scatter)
     against the FP64 oracle; bound ~ a few FP32 ulps of the largest term."""
