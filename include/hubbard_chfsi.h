@@ -422,6 +422,32 @@ hcu_status hcu_mlp_train_step(hcu_mlp* m, const float* X, const float* T, const 
  * physical outputs (entries 15..29: predicted density shells). */
 hcu_status hcu_mlp_guess(hcu_ctx* ctx, hcu_mlp* m, int bf16, float* outputs);
 
+/* ------------------------------------------------------- no allocation
+ * For callers that cannot allocate device memory or synchronise (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the contractions of hcu_gram without a context,
+ *   S = Y^H Y dv,  Hs = Y^H HY dv   (ncol x ncol, column-major doubles,
+ *   complex interleaved; diagonal 64 x 64 (complex: 32 x 32) tiles
+ *   symmetrised, the rest mirrored, as hcu_gram),
+ * with the same kernels and summation order as hcu_gram.  Y and HY are
+ * device blocks of ncol states, nd grid values each, leading dimension
+ * ld >= nd, element type double (precision HCU_FP64) or float (HCU_MIXED),
+ * complex interleaved when is_complex.  S and Hs are caller-owned device
+ * buffers.  The work is queued on `stream` (NULL = default stream) and the
+ * call returns without waiting; nothing is allocated or freed.
+ * Scratch: split-K partial sums and the tile list live in a fixed 80 MiB
+ * device array that the library holds on each GPU it runs on until the
+ * process ends; every call on one GPU uses the same array, so calls that
+ * overlap on one GPU race (serialise them).  Each call rewrites all the
+ * scratch it reads.  The first call on a device looks up the array's
+ * device address (hipGetSymbolAddress).
+ * Errors (nothing is queued): HCU_INVALID_ARG (null pointer, ncol < 1,
+ * nd < 1, ld < nd, dv <= 0, unknown precision); HCU_OOM when the
+ * contraction's partial sums exceed the 80 MiB (about ncol > 3200 real or
+ * > 2200 complex on any grid); HCU_DEVICE for a HIP error. */
+hcu_status hcu_gram_noalloc(const void* Y, const void* HY, int ncol, int64_t nd, int64_t ld, int precision,
+                            int is_complex, double dv, double* S, double* Hs, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

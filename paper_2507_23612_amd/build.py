@@ -25,7 +25,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
 ]
-SOURCES = ["setup.hip", "stencil.hip", "nonlocal.hip", "proj.hip", "gemm.hip", "scf_kernels.hip", "mlp.hip", "state.hip", "api.hip"]
+SOURCES = ["setup.hip", "stencil.hip", "nonlocal.hip", "proj.hip", "gemm.hip", "scf_kernels.hip", "mlp.hip", "state.hip",
+           "noalloc.hip", "api.hip"]
 
 
 def _compile(src):

@@ -403,6 +403,11 @@ std::vector<int2> gram_tiles(int n, bool cplx_);
 template <typename T>
 void launch_gram2(const Ctx& c, const T* Y, const T* HY, int ncol, int64_t ld, double* S, double* Hs,
                   hipStream_t st);
+// the same contraction with caller-given scratch of gram_scratch_bytes()
+// (partials, then the tile list); no context
+size_t gram_scratch_bytes(int ncol, int64_t nd, bool cplx_);
+void launch_gram_scratch(const void* Y, const void* HY, int ncol, int64_t ld, int64_t nd, double dv, bool fp32,
+                         bool cplx_, void* scratch, double* S, double* Hs, hipStream_t st);
 template <typename T>
 void launch_rotate(const Ctx& c, const T* Y, int64_t ld, const T* Cb, T* X, int ncol, hipStream_t st);
 template <typename T>

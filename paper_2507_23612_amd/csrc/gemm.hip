@@ -166,6 +166,16 @@ std::vector<int2> gram_tiles(int n, bool cplx_) {
   return tl;
 }
 
+// The same list written on the device (no host copy).
+__global__ void k_gram_tiles(int2* tiles, int nt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  int j = (int)((sqrt(8.0 * t + 1.0) - 1.0) / 2.0);
+  while (j * (j + 1) / 2 > t) --j;
+  while ((j + 1) * (j + 2) / 2 <= t) ++j;
+  tiles[t] = make_int2(t - j * (j + 1) / 2, j);
+}
+
 template <typename T>
 void launch_gram2_into(const T* Y, const T* HY, int ncol, int64_t ld, int64_t nd, double dv, const int2* tiles,
                        double* part, double* S, double* Hs, hipStream_t st) {
@@ -617,6 +627,42 @@ void launch_rotate<cplx<float>>(const Ctx& c, const cplx<float>* Y, int64_t ld, 
                                 cplx<float>* X, int ncol, hipStream_t st) {
   launch_rotate_c(c, Y, ld, Cb, X, ncol, st);
 }
+// Gram contractions with caller-given scratch (partials and tile list): the
+// tile list is written on the device first, then the contraction and its
+// reduction run as in launch_gram2.
+static int gram_ntiles(int ncol, bool cplx_) {
+  const int t = cplx_ ? CT : GT;
+  const int t1 = (ncol + t - 1) / t;
+  return t1 * (t1 + 1) / 2;
+}
+
+size_t gram_scratch_bytes(int ncol, int64_t nd, bool cplx_) {
+  const size_t part = sizeof(double) * (cplx_ ? gram_partial_elems_c(ncol, nd) : gram_partial_elems(ncol, nd));
+  return ((part + 255) & ~size_t(255)) + sizeof(int2) * (size_t)gram_ntiles(ncol, cplx_);
+}
+
+void launch_gram_scratch(const void* Y, const void* HY, int ncol, int64_t ld, int64_t nd, double dv, bool fp32,
+                         bool cplx_, void* scratch, double* S, double* Hs, hipStream_t st) {
+  const size_t part_bytes = sizeof(double) * (cplx_ ? gram_partial_elems_c(ncol, nd) : gram_partial_elems(ncol, nd));
+  double* part = reinterpret_cast<double*>(scratch);
+  int2* tiles = reinterpret_cast<int2*>(reinterpret_cast<char*>(scratch) + ((part_bytes + 255) & ~size_t(255)));
+  const int nt = gram_ntiles(ncol, cplx_);
+  launch_k(k_gram_tiles, (nt + 255) / 256, 256, 0, st, tiles, nt);
+  if (!cplx_) {
+    if (fp32)
+      launch_gram2_into<float>((const float*)Y, (const float*)HY, ncol, ld, nd, dv, tiles, part, S, Hs, st);
+    else
+      launch_gram2_into<double>((const double*)Y, (const double*)HY, ncol, ld, nd, dv, tiles, part, S, Hs, st);
+  } else {
+    if (fp32)
+      launch_gram2_c_into<cplx<float>>((const cplx<float>*)Y, (const cplx<float>*)HY, ncol, ld, nd, dv, tiles, part,
+                                       S, Hs, st);
+    else
+      launch_gram2_c_into<cplx<double>>((const cplx<double>*)Y, (const cplx<double>*)HY, ncol, ld, nd, dv, tiles,
+                                        part, S, Hs, st);
+  }
+}
+
 template void launch_rotate_proj<cplx<double>>(const Ctx&, const cplx<double>*, const cplx<double>*, cplx<double>*,
                                                int, hipStream_t);
 template void launch_rotate_proj<cplx<float>>(const Ctx&, const cplx<float>*, const cplx<float>*, cplx<float>*, int,

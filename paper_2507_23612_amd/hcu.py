@@ -148,6 +148,7 @@ def load_library(path=LIB_PATH):
         "hcu_mlp_gradient": (C.c_int, [P, P, P, P, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_double)]),
         "hcu_mlp_train_step": (C.c_int, [P, P, P, P, C.c_int, C.c_float, C.POINTER(C.c_double)]),
         "hcu_mlp_guess": (C.c_int, [P, P, C.c_int, C.POINTER(C.c_float)]),
+        "hcu_gram_noalloc": (C.c_int, [P, P, C.c_int, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_double, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -639,6 +640,16 @@ class HcuMlp:
             msg = self.lib.hcu_mlp_last_error(self.h).decode() or self.lib.hcu_last_error(ctx.h).decode()
             raise HcuError(st, msg)
         return out[:ctx.nhub]
+
+
+def gram_noalloc(Y, HY, ncol, nd, ld, precision, is_complex, dv, S, Hs, stream=None):
+    """hcu_gram_noalloc on device tensors (S, Hs: ncol x ncol device buffers
+    written column-major); returns the status code."""
+    lib = load_library()
+    st = stream.cuda_stream if stream is not None else 0
+    return lib.hcu_gram_noalloc(C.c_void_p(Y.data_ptr()), C.c_void_p(HY.data_ptr()), int(ncol), int(nd), int(ld),
+                                HCU_MIXED if precision == "mixed" else HCU_FP64, 1 if is_complex else 0,
+                                float(dv), C.c_void_p(S.data_ptr()), C.c_void_p(Hs.data_ptr()), C.c_void_p(st))
 
 
 def start_inputs(ctx, cfg, spin=0, ik=0):
