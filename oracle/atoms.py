@@ -128,11 +128,13 @@ def _box_indices(c, rc, L, n):
     return lin, d
 
 
-def bloch_function_at(points, center, L, k, radial, l, rc):
+def bloch_function_at(points, center, L, k, radial, l, rc, moment=None):
     """Bloch-mapped atom-centred functions at arbitrary points.
 
     Returns (2l+1, N) values of sum_T radial(|x-c-T|) Y_lm(x-c-T) e^{i k.T},
-    with the radial factor zero beyond rc.
+    with the radial factor zero beyond rc.  With moment = b (0, 1, 2) every
+    image term is multiplied by its own displacement component (x-c-T)_b
+    (the moment functions of the stress expression).
     """
     L = np.asarray(L, float)
     k = np.asarray(k, float)
@@ -155,6 +157,8 @@ def bloch_function_at(points, center, L, k, radial, l, rc):
                 if not np.any(m):
                     continue
                 val = radial(r[m]) * real_ylm(l, d[m])
+                if moment is not None:
+                    val = val * d[m][:, moment][None, :]
                 if cplx:
                     val = val * np.exp(1j * np.dot(k, T))
                 out[:, m] += val
@@ -226,6 +230,54 @@ def atom_functions(cfg, k=(0.0, 0.0, 0.0)):
             ent["hub_U"] = sp["hub_U"]
         out.append(ent)
     return out
+
+
+def hubbard_functions(cfg, k=(0.0, 0.0, 0.0), threshold=None):
+    """Hubbard orbitals of every Hubbard atom with their moment functions.
+
+    Returns a list (one entry per Hubbard atom, atom order) of dicts:
+      atom  : atom index;  U : effective U;  idx : support indices
+      vals  : (2l+1, nsupp) orbitals (Loewdin-combined when cfg['lowdin'])
+      moms  : (3, 2l+1, nsupp) moment functions sum_T phi(x-R-T) (x-R-T)_b
+              e^{ik.T}, combined with the same Loewdin coefficients
+      C     : the (2l+1)x(2l+1) Loewdin coefficients (identity without it)
+    `threshold` overrides the species' truncation value (the force and
+    stress pins use a tiny one so that the orbitals are smooth).
+    """
+    L = np.asarray(cfg["L"], float)
+    n = np.asarray(cfg["n"])
+    coords = fd.grid_coords(L, n)
+    dv = float(np.prod(L / n))
+    out = []
+    for ia, s in enumerate(cfg["atom_species"]):
+        sp = cfg["species"][s]
+        if sp["hub_l"] < 0:
+            continue
+        thr = sp["threshold"] if threshold is None else threshold
+        rad = (lambda r, sp=sp: hubbard_radial(r, sp["hub_power"], sp["hub_alpha"]))
+        rc = truncation_radius(rad, thr)
+        R = np.asarray(cfg["pos"][ia], float)
+        idx = support_indices(R, L, n, rc)
+        pts = coords[idx]
+        raw = bloch_function_at(pts, R, L, k, rad, sp["hub_l"], rc)
+        mom = [bloch_function_at(pts, R, L, k, rad, sp["hub_l"], rc, moment=b) for b in range(3)]
+        m = raw.shape[0]
+        C = np.eye(m)
+        if cfg.get("lowdin", True):
+            C = lowdin_coefficients(raw, dv)
+        out.append(dict(atom=ia, U=sp["hub_U"], idx=idx, vals=C.T @ raw,
+                        moms=np.stack([C.T @ x for x in mom]), C=C))
+    return out
+
+
+def lowdin_coefficients(vals, dv):
+    """O^{-1/2} with O = Phi^H Phi dV (Phi = vals^T); the orthonormal
+    orbitals are Phi O^{-1/2}."""
+    phi = vals.T
+    O = dv * (phi.conj().T @ phi)
+    O = 0.5 * (O + O.conj().T)
+    lam, U = np.linalg.eigh(O)
+    return (U * (1.0 / np.sqrt(lam))) @ U.conj().T
 
 
 def lowdin(vals, dv):
