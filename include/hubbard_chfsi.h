@@ -282,6 +282,35 @@ hcu_status hcu_scf_step(hcu_ctx* ctx, hcu_scf_step_info* info);
  * callable after hcu_chfsi_pass on every (spin, k)). */
 hcu_status hcu_update_occupations(hcu_ctx* ctx);
 
+/* ------------------------------------------------- Hubbard forces, stress
+ * Hellmann-Feynman Hubbard atomic forces (Sec. II.A force section: Eq.
+ * Force1, Eq. DerR and the final force expression) and Hubbard stress tensor
+ * (Sec. II.A stress section: Eq. StressDef and the final stress expression,
+ * orthorhombic cell, S = I) of the context's current orbitals (after
+ * hcu_scf, hcu_chfsi_pass or hcu_set_start) with occupations `occ` (host
+ * [nspin][nk][ns] doubles; NULL = the occupations of the last
+ * hcu_update_occupations / SCF iteration).  The derivative is moved to the
+ * Kohn-Sham orbitals and taken with the paper's centred finite-difference
+ * gradient (Sec. II.B weights, Bloch wrap):
+ *   f^J_a = g sum_k w_k Re sum_mm' U (2 D_m'm - delta_mm') sum_j f_j P_mj conj(G^a_m'j)
+ *   sigma_ab = g/|Omega| sum_J sum_mm' U/2 (delta_mm' - 2 D_m'm)
+ *              [-2 sum_k w_k Re sum_j f_j Q^ab_mj conj(P_m'j) - delta_ab D_mm']
+ * with P = <phi|psi> dV, G^a = <phi|d_a psi> dV, Q^ab = <phi^b|d_a psi> dV,
+ * phi^b = sum_T phi(x-R-T) (x-R-T)_b e^{ik.T} (Loewdin coefficients of the
+ * orbitals, when used, held fixed: the orbital moves rigidly), g = 2 for
+ * nspin = 1 and 1 otherwise, and D the occupation matrix of these orbitals
+ * and occupations (complex in general).  The printed expressions carry
+ * D_mm' in the first factor; that equals D_m'm whenever D is real (Gamma,
+ * k-sets closed under k -> -k) and D_m'm is the exact derivative for complex
+ * D.  forces: host [natom][3] doubles, Ha/bohr, zero for atoms without a
+ * Hubbard manifold; stress: host [3][3] row-major (a = gradient direction,
+ * b = moment direction), Ha/bohr^3.  The context's three filter work blocks
+ * of each (spin, k) are overwritten (the next filter recomputes them).
+ * Errors: HCU_NOT_BOUND, HCU_INVALID_ARG (NULL output, no occupations yet),
+ * HCU_NAN (non-finite occupations or results), HCU_DEVICE. */
+hcu_status hcu_hubbard_forces(hcu_ctx* ctx, const double* occ, double* forces);
+hcu_status hcu_hubbard_stress(hcu_ctx* ctx, const double* occ, double* stress);
+
 /* Stencil tile shape: tile_x threads along x (== n1: the x halo is taken
  * from the tile itself), tile_yt thread rows of ry points, tile_z planes
  * streamed per workgroup; stencil_ms = measured time of one full-block

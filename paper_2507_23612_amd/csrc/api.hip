@@ -91,6 +91,12 @@ size_t layout(Ctx& c, char* base) {
   b.take(c.d_jobs, kBatchJobBytes);
   b.take(c.d_counters, sizeof(unsigned long long) * kNumXcd);
   b.take(c.d_ppart, es * project_partial_elems(c));
+  b.take(c.d_lowC, sizeof(double) * 50 * (size_t)c.p.nk * nh);
+  b.take(c.d_momcsc, es * (size_t)c.nval);
+  for (int d = 0; d < 3; ++d) b.take(c.d_mom[d], es * c.pbsrc.size());
+  b.take(c.d_fproj, es * 13 * (size_t)ns * c.nproj);
+  b.take(c.d_fsum, sizeof(double) * 650 * (size_t)nh);
+  b.take(c.d_focc, sizeof(double) * (size_t)nsk * ns);
   c.part_elems = c.any_complex ? gram_partial_elems_c(ns, c.nd) : gram_partial_elems(ns, c.nd);
   b.take(c.d_part, sizeof(double) * c.part_elems);
   b.take(c.d_tiles, sizeof(int2) * gram_tiles(ns, c.any_complex).size());
@@ -1326,6 +1332,26 @@ hcu_status hcu_chfsi_pass(hcu_ctx* ctx, int spin, int ik) {
   const int sk = sk_index(c, spin, ik);
   if (!(c.bounds[3 * sk + 1] > c.bounds[3 * sk])) return fail(c, HCU_INVALID_ARG, "bounds not set (run hcu_lanczos_bounds)");
   return DISPATCH(c, pass_t, c, spin, ik, (double*)nullptr);
+}
+
+static hcu_status forces_stress_entry(hcu_ctx* ctx, const double* occ, double* forces, double* stress) {
+  hcu_status s = check_ctx(ctx);
+  if (s != HCU_OK) return s;
+  Ctx& c = *ctx;
+  if (!forces && !stress) return fail(c, HCU_INVALID_ARG, "null output");
+  if (!occ && !c.have_results)
+    return fail(c, HCU_INVALID_ARG, "no occupations yet: run hcu_scf or hcu_update_occupations, or pass occ");
+  s = hubbard_forces_stress(c, occ, forces, stress);
+  if (s == HCU_NAN) return fail(c, s, "non-finite occupations or results");
+  return s;
+}
+
+hcu_status hcu_hubbard_forces(hcu_ctx* ctx, const double* occ, double* forces) {
+  return forces_stress_entry(ctx, occ, forces, nullptr);
+}
+
+hcu_status hcu_hubbard_stress(hcu_ctx* ctx, const double* occ, double* stress) {
+  return forces_stress_entry(ctx, occ, nullptr, stress);
 }
 
 hcu_status hcu_update_occupations(hcu_ctx* ctx) {

@@ -179,6 +179,13 @@ struct Ctx {
   void* d_jobs = nullptr;            // batched-stencil job table (used when this context leads a batch)
   unsigned long long* d_counters = nullptr;
   void* d_ppart = nullptr;           // projection partial sums [chunk][nproj][ns]
+  // Hubbard forces and stress
+  double* d_lowC = nullptr;          // Loewdin coefficients [nk][nhub][re 25, im 25]
+  void* d_momcsc = nullptr;          // moment values on the supports (nval elements)
+  void* d_mom[3] = {nullptr, nullptr, nullptr};   // moment tables, projection-brick layout
+  void* d_fproj = nullptr;           // 13 projection arrays [ns][nproj]: P, G^a, Q^ab
+  double* d_fsum = nullptr;          // per Hubbard atom 325 complex bilinear sums
+  double* d_focc = nullptr;          // caller occupations [nspin*nk][ns]
   std::vector<void*> d_PX;           // per (spin,k) projections of X [ns][nproj]
   double* d_part = nullptr;          // split-K partials of the Gram matrices
   int2* d_tiles = nullptr;           // upper-triangular output tiles of the Gram kernels
@@ -388,6 +395,15 @@ template <typename T>
 void launch_project_brick(const Ctx& c, int ik, const T* Y, int ncol, int64_t ld, const double* coup, T* P, T* Q,
                           hipStream_t st);
 size_t project_partial_elems(const Ctx& c);
+// projections only (no coupling) with a caller-chosen function table in the
+// projection-brick layout
+template <typename T>
+void launch_project_table(const Ctx& c, const T* table, const T* Y, int ncol, int64_t ld, T* P, hipStream_t st);
+// setup.hip: moment functions sum_T phi(x-R-T)(x-R-T)_b e^{ik.T} of the
+// Hubbard orbitals (orbitals' Loewdin coefficients applied) in the
+// projection-brick layout; csc: scratch of nval elements
+template <typename T>
+hcu_status build_moment_table(Ctx& c, int ik, int b, T* csc, T* table, hipStream_t st);
 // Real blocks: Y += alpha Phi Q and, in the same pass, P and Q of the
 // updated Y (the next Chebyshev step's input); usable when scatter_project_ok.
 template <typename T>
@@ -395,6 +411,11 @@ bool scatter_project_ok(const Ctx& c);
 template <typename T>
 void launch_scatter_project(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T* Qt, double alpha,
                             const double* coup, T* P, T* Q, hipStream_t st);
+
+// forces.hip: Hubbard forces [natom][3] and/or stress [3][3] of the current
+// orbitals with the given occupations (host [nspin][nk][ns], NULL = the
+// context's); either output may be NULL
+hcu_status hubbard_forces_stress(Ctx& c, const double* occ, double* forces, double* stress);
 
 // gemm.hip
 size_t gram_partial_elems(int n, int64_t nd);

@@ -548,9 +548,11 @@ size_t project_partial_elems(const Ctx& c) {
   return (size_t)c.pboff.back() * c.p.ns;
 }
 
+// P = Phi^H Y dV with the function values of `table` (projection-brick
+// layout: the context's orbitals/projectors at a k-point, or other functions
+// on the same supports, e.g. their moments).
 template <typename T>
-void launch_project_brick(const Ctx& c, int ik, const T* Y, int ncol, int64_t ld, const double* coup, T* P, T* Q,
-                          hipStream_t st) {
+void launch_project_table(const Ctx& c, const T* table, const T* Y, int ncol, int64_t ld, T* P, hipStream_t st) {
   if (c.nproj == 0) return;
   T* part = reinterpret_cast<T*>(c.d_ppart);
   const int npb = (int)c.pboff.size() - 1;
@@ -560,19 +562,34 @@ void launch_project_brick(const Ctx& c, int ik, const T* Y, int ncol, int64_t ld
   auto run = [&](auto g) {
     constexpr int G = decltype(g)::value;
     if constexpr (sizeof(T) == sizeof(typename real_of<T>::type))
-      launch_k(k_proj_brick<T, G>, (unsigned)npb * nst, 256, 0, st, Y, ld, ncol, c.d_pboff, c.d_pbnj,
-               (const T*)c.d_pbval[ik], c.d_pdest, part, c.p.ns, c.nd, nst, vec);
+      launch_k(k_proj_brick<T, G>, (unsigned)npb * nst, 256, 0, st, Y, ld, ncol, c.d_pboff, c.d_pbnj, table,
+               c.d_pdest, part, c.p.ns, c.nd, nst, vec);
     else
       launch_k(k_proj_brick_c<typename real_of<T>::type, G>, (unsigned)npb * nst, 256, 0, st, Y, ld, ncol,
-               c.d_pboff, c.d_pbnj, (const T*)c.d_pbval[ik], c.d_pdest, part, c.p.ns, c.nd, nst, vec);
+               c.d_pboff, c.d_pbnj, table, c.d_pdest, part, c.p.ns, c.nd, nst, vec);
   };
   if (c.pgroup == 4) run(std::integral_constant<int, 4>());
   else run(std::integral_constant<int, 2>());
   dim3 g2((ncol + 63) / 64, c.nproj);
   launch_k(k_slot_sum<T>, g2, 1024, 0, st, part, c.p.ns, ncol, c.d_jrow, P, c.nproj, c.dv);
+}
+
+template <typename T>
+void launch_project_brick(const Ctx& c, int ik, const T* Y, int ncol, int64_t ld, const double* coup, T* P, T* Q,
+                          hipStream_t st) {
+  if (c.nproj == 0) return;
+  launch_project_table<T>(c, (const T*)c.d_pbval[ik], Y, ncol, ld, P, st);
   dim3 g3((ncol + 63) / 64, (unsigned)c.blocks.size());
   launch_k(k_couple<T>, g3, 64, 0, st, P, c.d_blocks, ncol, coup, Q, c.nproj, c.p.ns);
 }
+
+template void launch_project_table<double>(const Ctx&, const double*, const double*, int, int64_t, double*,
+                                           hipStream_t);
+template void launch_project_table<float>(const Ctx&, const float*, const float*, int, int64_t, float*, hipStream_t);
+template void launch_project_table<cplx<double>>(const Ctx&, const cplx<double>*, const cplx<double>*, int, int64_t,
+                                                 cplx<double>*, hipStream_t);
+template void launch_project_table<cplx<float>>(const Ctx&, const cplx<float>*, const cplx<float>*, int, int64_t,
+                                                cplx<float>*, hipStream_t);
 
 template void launch_project_brick<double>(const Ctx&, int, const double*, int, int64_t, const double*, double*,
                                            double*, hipStream_t);

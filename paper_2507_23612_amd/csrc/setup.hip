@@ -350,14 +350,20 @@ __global__ void k_vloc(double* V, float* Vf, const AtomV* atoms, int natom, int 
 }
 
 // Values of one block's functions on its support, summed over periodic images
-// with Bloch phase e^{+i k.T} (T = image translation).
+// with Bloch phase e^{+i k.T} (T = image translation).  moment = 0, 1, 2:
+// the moment functions of the Hubbard blocks instead, every image term times
+// its own displacement component (x - R - T)_moment (KB blocks get zeros).
 template <typename T>
 __global__ void k_block_values(const BlockDesc* blocks, const int* supp, T* val, int n1, int n2,
                                double h1, double h2, double h3, double L1, double L2, double L3,
-                               double k1, double k2, double k3) {
+                               double k1, double k2, double k3, int moment) {
   const BlockDesc b = blocks[blockIdx.y];
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= b.nsupp) return;
+  if (moment >= 0 && b.type == 0) {
+    for (int m = 0; m < b.nm; ++m) val[b.val_off + (int64_t)m * b.nsupp + q] = T(0);
+    return;
+  }
   int pt = supp[b.supp_off + q];
   int i = pt % n1, j = (pt / n1) % n2, k = pt / (n1 * n2);
   double x = i * h1, y = j * h2, z = k * h3;
@@ -382,9 +388,10 @@ __global__ void k_block_values(const BlockDesc* blocks, const int* supp, T* val,
             double rad = (b.type == 0) ? kb_radial(r, b.chan_norm[ch], l, b.width)
                                        : hub_radial(r, b.chan_norm[ch], b.power, b.alpha);
             real_ylm(l, dx, dy, dz, ylm);
+            const double w = moment == 0 ? dx : moment == 1 ? dy : moment == 2 ? dz : 1.0;
             for (int m = 0; m < 2 * l + 1; ++m) {
-              acc_re[m0 + m] += rad * ylm[m] * cr;
-              acc_im[m0 + m] += rad * ylm[m] * ci;
+              acc_re[m0 + m] += rad * ylm[m] * w * cr;
+              acc_im[m0 + m] += rad * ylm[m] * w * ci;
             }
           }
           m0 += 2 * l + 1;
@@ -444,7 +451,7 @@ __device__ void jacobi_inv_sqrt(double* A, int n) {
 // symmetric embedding [[Re, -Im], [Im, Re]], whose inverse square root embeds
 // the complex one.
 template <typename T>
-__global__ void k_lowdin(const BlockDesc* blocks, const int* hub_blocks, T* val, double dv) {
+__global__ void k_lowdin(const BlockDesc* blocks, const int* hub_blocks, T* val, double dv, double* Cout) {
   using R = typename real_of<T>::type;
   const BlockDesc b = blocks[hub_blocks[blockIdx.x]];
   const int nm = b.nm;
@@ -490,6 +497,11 @@ __global__ void k_lowdin(const BlockDesc* blocks, const int* hub_blocks, T* val,
         sO_re[i * nm + j] = M[i * n + j];
         sO_im[i * nm + j] = cp ? M[(i + nm) * n + j] : 0.0;
       }
+    if (Cout)   // the coefficients, kept for the moment functions
+      for (int e = 0; e < nm * nm; ++e) {
+        Cout[50 * blockIdx.x + e] = sO_re[e];
+        Cout[50 * blockIdx.x + 25 + e] = sO_im[e];
+      }
   }
   __syncthreads();
   for (int q = threadIdx.x; q < b.nsupp; q += blockDim.x) {
@@ -500,6 +512,27 @@ __global__ void k_lowdin(const BlockDesc* blocks, const int* hub_blocks, T* val,
       for (int mp = 0; mp < nm; ++mp)
         s += make_scalar<T>(sO_re[mp * nm + m], sO_im[mp * nm + m]) * old[mp];
       v[(int64_t)m * b.nsupp + q] = s;
+    }
+  }
+}
+
+// The stored Loewdin coefficients C of each Hubbard block (re at [0, 25),
+// im at [25, 50) of the block's record) applied to other values on the same
+// support: v_m <- sum_m' C_m'm v_m' (as k_lowdin applies them to the orbitals).
+template <typename T>
+__global__ void k_apply_lowdin(const BlockDesc* blocks, const int* hub_blocks, T* val, const double* C) {
+  const BlockDesc b = blocks[hub_blocks[blockIdx.x]];
+  const int nm = b.nm;
+  const double* cr = C + 50 * blockIdx.x;
+  const double* ci = cr + 25;
+  T* v = val + b.val_off;
+  for (int q = threadIdx.x; q < b.nsupp; q += blockDim.x) {
+    T old[5];
+    for (int m = 0; m < nm; ++m) old[m] = v[(int64_t)m * b.nsupp + q];
+    for (int m = 0; m < nm; ++m) {
+      T acc = T(0);
+      for (int mp = 0; mp < nm; ++mp) acc += make_scalar<T>(cr[mp * nm + m], ci[mp * nm + m]) * old[mp];
+      v[(int64_t)m * b.nsupp + q] = acc;
     }
   }
 }
@@ -527,11 +560,12 @@ static hcu_status tables_for(Ctx& c) {
       dim3 grid((maxs + 127) / 128, nblk);
       k_block_values<T><<<grid, 128, 0, st>>>(c.d_blocks, c.d_supp, cscv, c.p.n[0], c.p.n[1], c.h[0], c.h[1],
                                               c.h[2], c.p.L[0], c.p.L[1], c.p.L[2], c.kpts[3 * ik],
-                                              c.kpts[3 * ik + 1], c.kpts[3 * ik + 2]);
+                                              c.kpts[3 * ik + 1], c.kpts[3 * ik + 2], -1);
       HCU_HIP(hipGetLastError());
     }
     if (c.p.lowdin && !hub_blocks.empty()) {
-      k_lowdin<T><<<(int)hub_blocks.size(), 256, 0, st>>>(c.d_blocks, d_hb, cscv, c.dv);
+      k_lowdin<T><<<(int)hub_blocks.size(), 256, 0, st>>>(c.d_blocks, d_hb, cscv, c.dv,
+                                                          c.d_lowC + (size_t)ik * hub_blocks.size() * 50);
       HCU_HIP(hipGetLastError());
     }
     const int64_t nbv = (int64_t)c.bsrc.size();
@@ -548,6 +582,38 @@ static hcu_status tables_for(Ctx& c) {
   HCU_HIP(hipStreamSynchronize(st));   // hub_blocks (host) must outlive its copy
   return HCU_OK;
 }
+
+// Moment functions of the Hubbard orbitals at k-point ik, direction b, in
+// the projection-brick layout: values on each block's support (KB blocks
+// zero) into `csc` (nval elements), the orbitals' Loewdin coefficients
+// applied, then gathered into `table` (the layout of d_pbval).
+template <typename T>
+hcu_status build_moment_table(Ctx& c, int ik, int b, T* csc, T* table, hipStream_t st) {
+  const int nblk = (int)c.blocks.size();
+  const int nh = (int)c.hub_atoms.size();
+  int maxs = 0;
+  for (auto& bl : c.blocks) maxs = std::max(maxs, bl.nsupp);
+  if (nblk == 0 || maxs == 0 || nh == 0) return HCU_OK;
+  dim3 grid((maxs + 127) / 128, nblk);
+  k_block_values<T><<<grid, 128, 0, st>>>(c.d_blocks, c.d_supp, csc, c.p.n[0], c.p.n[1], c.h[0], c.h[1], c.h[2],
+                                          c.p.L[0], c.p.L[1], c.p.L[2], c.kpts[3 * ik], c.kpts[3 * ik + 1],
+                                          c.kpts[3 * ik + 2], b);
+  HCU_HIP(hipGetLastError());
+  if (c.p.lowdin) {
+    k_apply_lowdin<T><<<nh, 256, 0, st>>>(c.d_blocks, c.d_hub_blocks, csc, c.d_lowC + (size_t)ik * nh * 50);
+    HCU_HIP(hipGetLastError());
+  }
+  const int64_t npv = (int64_t)c.pbsrc.size();
+  if (npv > 0) {
+    k_gather_csr<T><<<(unsigned)((npv + 255) / 256), 256, 0, st>>>(csc, c.d_pbsrc, table, npv);
+    HCU_HIP(hipGetLastError());
+  }
+  return HCU_OK;
+}
+template hcu_status build_moment_table<double>(Ctx&, int, int, double*, double*, hipStream_t);
+template hcu_status build_moment_table<float>(Ctx&, int, int, float*, float*, hipStream_t);
+template hcu_status build_moment_table<cplx<double>>(Ctx&, int, int, cplx<double>*, cplx<double>*, hipStream_t);
+template hcu_status build_moment_table<cplx<float>>(Ctx&, int, int, cplx<float>*, cplx<float>*, hipStream_t);
 
 hcu_status device_tables(Ctx& c) {
   hipStream_t st = c.stream;

@@ -149,6 +149,8 @@ def load_library(path=LIB_PATH):
         "hcu_mlp_train_step": (C.c_int, [P, P, P, P, C.c_int, C.c_float, C.POINTER(C.c_double)]),
         "hcu_mlp_guess": (C.c_int, [P, P, C.c_int, C.POINTER(C.c_float)]),
         "hcu_gram_noalloc": (C.c_int, [P, P, C.c_int, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_double, P, P, P]),
+        "hcu_hubbard_forces": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "hcu_hubbard_stress": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -359,6 +361,29 @@ class HcuContext:
             self._check(st)
         out = {k: getattr(r, k) for k, _ in hcu_scf_report._fields_}
         out["status"] = st
+        return out
+
+    def _occ_arg(self, occ):
+        if occ is None:
+            return None, None
+        o = np.ascontiguousarray(np.asarray(occ, np.float64))
+        if o.size != self.nspin * self.nk * self.ns:
+            raise HcuError(HCU_INVALID_ARG, f"occ has {o.size} values, expected [nspin][nk][ns]")
+        return o, _dptr(o)
+
+    def hubbard_forces(self, occ=None):
+        """Hubbard forces (natom, 3) in Ha/bohr of the current orbitals with
+        occupations occ [nspin][nk][ns] (None: the context's)."""
+        o, p = self._occ_arg(occ)
+        out = np.zeros((len(self.prob.spec), 3))
+        self._check(self.lib.hcu_hubbard_forces(self.h, p, _dptr(out)))
+        return out
+
+    def hubbard_stress(self, occ=None):
+        """Hubbard stress tensor (3, 3) in Ha/bohr^3."""
+        o, p = self._occ_arg(occ)
+        out = np.zeros((3, 3))
+        self._check(self.lib.hcu_hubbard_stress(self.h, p, _dptr(out)))
         return out
 
     def get_sizes(self):
