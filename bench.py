@@ -11,9 +11,12 @@ and not timed.
 value = nd * ns * (m + 1) / seconds per step / 1e9  [Gpts.states/s]
 (m filter applications plus the H Y of Rayleigh-Ritz).
 
-Also reported: the stencil kernel's achieved HBM bandwidth against the
-MI355X peak (algorithmic bytes / event-timed average launch), the SCF wall
-time to convergence, and the CPU oracle's throughput on a bounded sample.
+Also reported: the stencil kernel's and the fused scatter + projection
+kernel's achieved rates against the MI355X peaks (algorithmic bytes or
+flops / event-timed average launch), the mixed-precision figure on the
+108-atom cell beside the FP64 one (default run), the SCF wall time to
+convergence, the time of one Hubbard force and one stress evaluation, and
+the CPU oracle's throughput on a bounded sample.
 """
 from __future__ import annotations
 
@@ -29,6 +32,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# dense matrix-core peaks of the MI355X (published): FP64 78.6, FP32 157.3 TFLOP/s
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}
 METRIC = "ChFSI H·X Gpts·states/s (FP64 vs mixed); SCF wall-time to 1e-5 Ha/atom"
 
 WORKLOADS = {
@@ -61,16 +66,16 @@ def stencil_bytes(cfg, elem):
     return nsk * (3 * elem * nd * ns + elem * nd)
 
 
-def measured_traffic(config, prec, tile):
-    """HBM bytes per stencil launch from the committed counter summaries
-    profiles/k_stencil_<config>_<prec>*.md (FETCH_SIZE and WRITE_SIZE runs,
+def measured_traffic(kernel, config, prec, tile, sources):
+    """HBM bytes per launch of `kernel` from the committed counter summaries
+    profiles/<kernel>_<config>_<prec>*.md (FETCH_SIZE and WRITE_SIZE runs,
     calibrated on a plain copy; one file per tile shape), or None if there is
-    none for this tile shape or the kernel sources changed since it was
+    none for this tile shape or the kernel's sources changed since it was
     taken."""
     import glob
     from paper_2507_23612_amd.tracesum import kernel_source_digest
-    digest = kernel_source_digest()
-    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"k_stencil_{config}_{prec}*.md"))):
+    digest = kernel_source_digest(sources)
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"{kernel}_{config}_{prec}*.md"))):
         rec = {}
         with open(path) as fh:
             for line in fh:
@@ -101,11 +106,21 @@ def cpu_baseline(cfg, nstates=24, degree=16):
     dt = time.perf_counter() - t0
     c1 = proc.cpu_times()
     cores = max(1, int(round(((c1.user - c0.user) + (c1.system - c0.system)) / dt)))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": h.nd * nstates * degree / dt / 1e9, "unit": "Gpts·states/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{nstates} of {cfg['ns']} states, one degree-{degree} Chebyshev filter "
                       f"({degree} H applications) on the full {cfg['n'][0]}x{cfg['n'][1]}x{cfg['n'][2]} grid, "
-                      f"{dt:.1f} s on host cores"}
+                      f"{dt:.1f} s on host cores",
+            "cores_note": "threads actually used = process CPU time / wall time over the sample (numpy/BLAS "
+                          "threads)",
+            "nproc": os.cpu_count(), "cpu_model": model or None,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 MODEL = os.path.join(ROOT, "paper_2507_23612_amd", "models", "site_mlp_c5.npz")
@@ -228,6 +243,7 @@ def main():
     ap.add_argument("--precision", default=None, help="fp64 | mixed (default: the config's)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-scf", action="store_true", help="skip the SCF wall-time run")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision (c3) figure of the default run")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (calibrates hardware byte counters)")
     ap.add_argument("--tile", default=None,
@@ -263,8 +279,51 @@ def main():
     if args.scf_compare:
         print(json.dumps(bench_scf_compare(args)), flush=True)
         return
-    cfg = make_workload(args.config)
-    prec = args.precision or cfg["precision"]
+    out = measure(args, args.config, args.precision, hcu, torch, top=True)
+    if args.config == "c2" and args.precision in (None, "fp64") and not args.no_mixed:
+        # the mixed-precision half of the metric, on its own workload (c3)
+        mixed = measure(args, "c3", "mixed", hcu, torch, top=False)
+        out["mixed"] = mixed
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(make_workload(args.config))
+    print(json.dumps(out), flush=True)
+
+
+def fused_roofline(cfg, prec, sizes, kt, config, tile, complex_):
+    """Roofline of the fused scatter + projection kernel of one Chebyshev
+    step (the stage that follows the stencil): algorithmic HBM bytes = the
+    block read and written once (2 words per point-state) + the function
+    values once (nnz of the per-point table) + the projection partial sums
+    written once; algorithmic flops = 2 per (point, function, state) for the
+    scatter and 2 for the projection (x4 for complex blocks)."""
+    nd, ns = sizes["nd"], int(cfg["ns"])
+    nsk = int(cfg["nspin"]) * len(cfg["kw"])
+    elem = (4 if prec == "mixed" else 8) * (2 if complex_ else 1)
+    nbytes = nsk * (2 * elem * nd * ns + elem * sizes["table_nnz"] + elem * sizes["brick_slots"] * ns)
+    flops = nsk * 4 * sizes["table_nnz"] * ns * (4 if complex_ else 1)
+    if kt["fused_launches"] == 0:
+        return None
+    ms = kt["fused_ms"] / kt["fused_launches"]
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    tf = flops / (ms * 1e-3) / 1e12
+    peak_tf = MFMA_PEAK_TFLOPS["mixed" if prec == "mixed" else "fp64"]
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic("k_scatter_project", config, prec, tile, ("proj.hip",)),
+            "kernel": "k_scatter_project (projector scatter of a Chebyshev step fused with the projections of "
+                      "its output)",
+            "avg_launch_ms": round(ms, 4), "algorithmic_bytes_per_launch": int(nbytes),
+            "algorithmic_flops_per_launch": int(flops), "achieved_tflops": round(tf, 2),
+            "mfma_peak_tflops": peak_tf, "mfma_frac": round(tf / peak_tf, 4)}
+
+
+def measure(args, config, precision, hcu, torch, top):
+    """Throughput of K timed SCF iterations of one workload (inputs resident,
+    setup and tuning untimed), with the stencil and fused-kernel rooflines
+    from HIP events on the library's stream; the top-level line also gets
+    the SCF wall time and the forces/stress timing."""
+    cfg = make_workload(config)
+    prec = precision or cfg["precision"]
     nd = int(np.prod(cfg["n"]))
     ns = int(cfg["ns"])
     m = int(cfg["degree"])
@@ -278,7 +337,7 @@ def main():
             ctx.set_start(sp, ik, X0, v0)
             del X0, v0
     torch.cuda.synchronize()
-    if args.tile:
+    if args.tile and top:
         tx, tyt, ry, tz = (int(v) for v in args.tile.split(","))
         ctx.set_tuning(tx, tyt, ry, tz)
         tuning = {"tile_x": tx, "tile_yt": tyt, "ry": ry, "tile_z": tz, "stencil_ms": None}
@@ -306,24 +365,40 @@ def main():
     tile = f'{tuning["tile_x"]},{tuning["tile_yt"]},{tuning["ry"]},{tuning["tile_z"]}'
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(args.config, prec, tile),
+                "traffic": measured_traffic("k_stencil", config, prec, tile, ("stencil.hip",)),
                 "kernel": ("k_stencil_batch (persistent, all (spin, k) blocks)" if nsk > 1 else
                            "k_stencil_big" if tuning["tile_x"] * tuning["tile_yt"] > 512 else "k_stencil")
                           + " (12th-order FD stencil + V_loc + Chebyshev three-term step)",
                 "avg_launch_ms": round(st_ms, 4), "algorithmic_bytes_per_launch": int(bytes_launch),
                 "tile": tile}
     breakdown = {k: round(v / args.steps, 3) for k, v in kt.items() if k.endswith("_ms")}
-
+    sizes = ctx.get_sizes()
+    fused = fused_roofline(cfg, prec, sizes, kt, config, tile, ctx.complex)
+    dtype = ("c64" if prec == "mixed" else "c128") if ctx.complex else ("f32" if prec == "mixed" else "f64")
     out = {"metric": METRIC, "value": round(value, 3), "unit": "Gpts·states/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": ("c64" if prec == "mixed" else "c128") if ctx.complex else ("f32" if prec == "mixed" else "f64"),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
            "data": "synthetic",
-           "config": {"workload": f"{args.config}: {WORKLOADS.get(args.config, args.config)}",
+           "config": {"workload": f"{config}: {WORKLOADS.get(config, config)}",
                       "precision": prec, "nd": nd, "ns": ns, "degree": m},
-           "roofline": roofline, "kernel_ms_per_step": breakdown, "stencil_tuning": tuning}
+           "roofline": roofline, "roofline_fused": fused, "kernel_ms_per_step": breakdown,
+           "stencil_tuning": tuning}
+    if not top:
+        out = {k: out[k] for k in ("value", "unit", "ms_per_step", "dtype", "config", "roofline", "roofline_fused",
+                                   "kernel_ms_per_step", "stencil_tuning")}
+    # forces and stress of the state reached (one call each, outside the timed region)
+    ctx.update_occupations()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.hubbard_forces()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.hubbard_stress()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out["forces_stress_ms"] = {"forces": round((t1 - t0) * 1e3, 2), "stress": round((t2 - t1) * 1e3, 2)}
 
-    if not args.no_scf:
+    if top and not args.no_scf:
         ctx2 = hcu.HcuContext(cfg, prec)
         ctx2.set_tuning(tuning["tile_x"], tuning["tile_yt"], tuning["ry"], tuning["tile_z"])
         ctx2.set_hubbard_occupation(hcu.initial_occupation(ctx2, cfg))
@@ -342,9 +417,9 @@ def main():
                       "criterion": f"|D_out-D_in|_F < {tol_d:g} and |dF|/atom < 1e-7 Ha"}
         ctx2.close()
     ctx.close()
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(cfg)
-    print(json.dumps(out), flush=True)
+    del ctx
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

@@ -160,6 +160,8 @@ typedef struct hcu_kernel_times {
   double eig_ms;      long long eig_launches;      /* generalized eigensolve (rocSOLVER) */
   double rotate_ms;   long long rotate_launches;   /* X = Y C                            */
   double scatter_ms;  long long scatter_launches;  /* projector scatter (KB + Hubbard)   */
+  double fused_ms;    long long fused_launches;    /* of scatter: the fused scatter +
+                                                      projection kernel alone           */
 } hcu_kernel_times;
 
 typedef struct hcu_ctx hcu_ctx;

@@ -263,10 +263,15 @@ void scatter_t(Ctx& c, int spin, int ik, T* Y, int64_t ldy, int ncol, double alp
 // updated Y for the next Chebyshev step.
 template <typename T>
 void scatter_project_t(Ctx& c, int spin, int ik, T* Y, int64_t ldy, int ncol, double alpha) {
-  ProfScope ps(c, PK_SCATTER);
   const int sk = sk_index(c, spin, ik);
+  {
+    ProfScope ps(c, PK_FUSED);   // the fused kernel alone
+    launch_scatter_project<T>(c, ik, Y, ldy, ncol, (const T*)c.d_Q[sk], alpha, c.d_coup[spin], (T*)c.d_P[sk],
+                              (T*)c.d_Q[sk], c.stream, 1);
+  }
+  ProfScope ps(c, PK_SCATTER);   // partial sums and coupling of the projections
   launch_scatter_project<T>(c, ik, Y, ldy, ncol, (const T*)c.d_Q[sk], alpha, c.d_coup[spin], (T*)c.d_P[sk],
-                            (T*)c.d_Q[sk], c.stream);
+                            (T*)c.d_Q[sk], c.stream, 2);
 }
 
 // proj_in = false: P and Q of X are already current (left by the step that
@@ -1149,7 +1154,9 @@ hcu_status hcu_get_kernel_times(hcu_ctx* ctx, hcu_kernel_times* t) {
   t->gram_ms = ctx->prof_ms[PK_GRAM]; t->gram_launches = ctx->prof_count[PK_GRAM];
   t->eig_ms = ctx->prof_ms[PK_EIG]; t->eig_launches = ctx->prof_count[PK_EIG];
   t->rotate_ms = ctx->prof_ms[PK_ROTATE]; t->rotate_launches = ctx->prof_count[PK_ROTATE];
-  t->scatter_ms = ctx->prof_ms[PK_SCATTER]; t->scatter_launches = ctx->prof_count[PK_SCATTER];
+  t->scatter_ms = ctx->prof_ms[PK_SCATTER] + ctx->prof_ms[PK_FUSED];
+  t->scatter_launches = ctx->prof_count[PK_SCATTER];
+  t->fused_ms = ctx->prof_ms[PK_FUSED]; t->fused_launches = ctx->prof_count[PK_FUSED];
   return HCU_OK;
 }
 

@@ -248,7 +248,8 @@ struct Ctx {
   long prof_count[8] = {0};
 };
 
-enum ProfKind { PK_STENCIL = 0, PK_PROJECT = 1, PK_GRAM = 2, PK_EIG = 3, PK_ROTATE = 4, PK_SCATTER = 5 };
+enum ProfKind { PK_STENCIL = 0, PK_PROJECT = 1, PK_GRAM = 2, PK_EIG = 3, PK_ROTATE = 4, PK_SCATTER = 5,
+                PK_FUSED = 6 };
 
 // Scoped timing of the launches queued inside it (no-op unless profiling).
 // Per-phase GPU time.  A marker event recorded between two kernels on a
@@ -410,7 +411,7 @@ template <typename T>
 bool scatter_project_ok(const Ctx& c);
 template <typename T>
 void launch_scatter_project(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T* Qt, double alpha,
-                            const double* coup, T* P, T* Q, hipStream_t st);
+                            const double* coup, T* P, T* Q, hipStream_t st, int part = 3);
 
 // forces.hip: Hubbard forces [natom][3] and/or stress [3][3] of the current
 // orbitals with the given occupations (host [nspin][nk][ns], NULL = the

@@ -488,9 +488,11 @@ bool scatter_project_ok(const Ctx& c) {
   else return false;   // complex FP64: the accumulators do not fit the register budget
 }
 
+// part: 1 = the fused kernel only, 2 = the partial sums and coupling that
+// follow it only, 3 = both (separate parts let the caller time the kernel)
 template <typename T>
 void launch_scatter_project(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T* Qt, double alpha,
-                            const double* coup, T* P, T* Q, hipStream_t st) {
+                            const double* coup, T* P, T* Q, hipStream_t st, int part_sel) {
   if constexpr (sizeof(T) == sizeof(typename real_of<T>::type)) {
     T* part = reinterpret_cast<T*>(c.d_ppart);
     const int npb = (int)c.pboff.size() - 1;
@@ -505,27 +507,34 @@ void launch_scatter_project(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, co
     using I2 = std::integral_constant<int, 2>;
     using I4 = std::integral_constant<int, 4>;
     using I8 = std::integral_constant<int, 8>;
-    if (c.pgroup == 2) {
-      if (c.max_ptiles <= 4) run(I2(), I4()); else run(I2(), I8());
-    } else {
-      if (c.max_ptiles <= 4) run(I4(), I4()); else run(I4(), I8());
+    if (part_sel & 1) {
+      if (c.pgroup == 2) {
+        if (c.max_ptiles <= 4) run(I2(), I4()); else run(I2(), I8());
+      } else {
+        if (c.max_ptiles <= 4) run(I4(), I4()); else run(I4(), I8());
+      }
     }
-    dim3 g2((ncol + 63) / 64, c.nproj);
-    launch_k(k_slot_sum<T>, g2, 1024, 0, st, part, c.p.ns, ncol, c.d_jrow, P, c.nproj, c.dv);
-    dim3 g3((ncol + 63) / 64, (unsigned)c.blocks.size());
-    launch_k(k_couple<T>, g3, 64, 0, st, P, c.d_blocks, ncol, coup, Q, c.nproj, c.p.ns);
+    if (part_sel & 2) {
+      dim3 g2((ncol + 63) / 64, c.nproj);
+      launch_k(k_slot_sum<T>, g2, 1024, 0, st, part, c.p.ns, ncol, c.d_jrow, P, c.nproj, c.dv);
+      dim3 g3((ncol + 63) / 64, (unsigned)c.blocks.size());
+      launch_k(k_couple<T>, g3, 64, 0, st, P, c.d_blocks, ncol, coup, Q, c.nproj, c.p.ns);
+    }
   } else if constexpr (std::is_same<T, cplx<float>>::value) {
     T* part = reinterpret_cast<T*>(c.d_ppart);
     const int npb = (int)c.pboff.size() - 1;
     const int nbrick = (int)c.boff.size() - 1;
     const int nst = (ncol + 63) / 64;
-    launch_k(k_scatter_project_c<float, 2, 4>, (unsigned)npb * nst, 256, 0, st, Y, ld, ncol, c.d_boff, c.d_bnj,
-             c.d_bj, (const T*)c.d_bval[ik], Qt, c.p.ns, (float)alpha, nbrick, c.d_pboff, c.d_pbnj,
-             (const T*)c.d_pbval[ik], c.d_pdest, part, c.p.ns, c.nd, nst);
-    dim3 g2((ncol + 63) / 64, c.nproj);
-    launch_k(k_slot_sum<T>, g2, 1024, 0, st, part, c.p.ns, ncol, c.d_jrow, P, c.nproj, c.dv);
-    dim3 g3((ncol + 63) / 64, (unsigned)c.blocks.size());
-    launch_k(k_couple<T>, g3, 64, 0, st, P, c.d_blocks, ncol, coup, Q, c.nproj, c.p.ns);
+    if (part_sel & 1)
+      launch_k(k_scatter_project_c<float, 2, 4>, (unsigned)npb * nst, 256, 0, st, Y, ld, ncol, c.d_boff, c.d_bnj,
+               c.d_bj, (const T*)c.d_bval[ik], Qt, c.p.ns, (float)alpha, nbrick, c.d_pboff, c.d_pbnj,
+               (const T*)c.d_pbval[ik], c.d_pdest, part, c.p.ns, c.nd, nst);
+    if (part_sel & 2) {
+      dim3 g2((ncol + 63) / 64, c.nproj);
+      launch_k(k_slot_sum<T>, g2, 1024, 0, st, part, c.p.ns, ncol, c.d_jrow, P, c.nproj, c.dv);
+      dim3 g3((ncol + 63) / 64, (unsigned)c.blocks.size());
+      launch_k(k_couple<T>, g3, 64, 0, st, P, c.d_blocks, ncol, coup, Q, c.nproj, c.p.ns);
+    }
   }
 }
 
@@ -534,14 +543,15 @@ template bool scatter_project_ok<float>(const Ctx&);
 template bool scatter_project_ok<cplx<double>>(const Ctx&);
 template bool scatter_project_ok<cplx<float>>(const Ctx&);
 template void launch_scatter_project<double>(const Ctx&, int, double*, int64_t, int, const double*, double,
-                                             const double*, double*, double*, hipStream_t);
+                                             const double*, double*, double*, hipStream_t, int);
 template void launch_scatter_project<float>(const Ctx&, int, float*, int64_t, int, const float*, double,
-                                            const double*, float*, float*, hipStream_t);
+                                            const double*, float*, float*, hipStream_t, int);
 template void launch_scatter_project<cplx<double>>(const Ctx&, int, cplx<double>*, int64_t, int,
                                                    const cplx<double>*, double, const double*, cplx<double>*,
-                                                   cplx<double>*, hipStream_t);
+                                                   cplx<double>*, hipStream_t, int);
 template void launch_scatter_project<cplx<float>>(const Ctx&, int, cplx<float>*, int64_t, int, const cplx<float>*,
-                                                  double, const double*, cplx<float>*, cplx<float>*, hipStream_t);
+                                                  double, const double*, cplx<float>*, cplx<float>*, hipStream_t,
+                                                  int);
 
 size_t project_partial_elems(const Ctx& c) {
   if (c.pboff.empty()) return 0;

@@ -70,7 +70,8 @@ class hcu_kernel_times(C.Structure):
                 ("gram_ms", C.c_double), ("gram_launches", C.c_longlong),
                 ("eig_ms", C.c_double), ("eig_launches", C.c_longlong),
                 ("rotate_ms", C.c_double), ("rotate_launches", C.c_longlong),
-                ("scatter_ms", C.c_double), ("scatter_launches", C.c_longlong)]
+                ("scatter_ms", C.c_double), ("scatter_launches", C.c_longlong),
+                ("fused_ms", C.c_double), ("fused_launches", C.c_longlong)]
 
 
 class hcu_tuning(C.Structure):

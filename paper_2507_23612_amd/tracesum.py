@@ -3,7 +3,7 @@
     python -m paper_2507_23612_amd.tracesum <dir-with-*_kernel_trace.csv> [top]
     python -m paper_2507_23612_amd.tracesum --counter <dir> <kernel substring> <counter>
     python -m paper_2507_23612_amd.tracesum --record <trace dir> <FETCH_SIZE dir> <WRITE_SIZE dir> \
-        <kernel substring> <tile> <title> <command file>
+        <kernel substring> <tile> <title> <command file> [source files, comma-separated]
 
 Prints, per (kernel, grid, workgroup) group: launches, total, average, min
 and max duration in ms, sorted by total time.  Grouping by launch shape
@@ -56,12 +56,12 @@ def counters(path, kernel_sub, counter):
     return out
 
 
-def kernel_source_digest():
-    """sha256 of the stencil kernel's source file: a counter record applies
-    only to the kernel code it was taken on."""
+def kernel_source_digest(sources=("stencil.hip",)):
+    """sha256 of a kernel's source files: a counter record applies only to
+    the kernel code it was taken on."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("stencil.hip",):
+    for f in sources:
         with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -138,8 +138,9 @@ if __name__ == "__main__":
     if len(sys.argv) > 2 and sys.argv[1] == "--record":
         with open(sys.argv[8]) as fh:
             cmds = [ln.rstrip("\n") for ln in fh if ln.strip()]
+        srcs = tuple(sys.argv[9].split(",")) if len(sys.argv) > 9 else ("stencil.hip",)
         print(record(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6], sys.argv[7], cmds,
-                     kernel_source_digest()))
+                     kernel_source_digest(srcs)))
         sys.exit(0)
     if len(sys.argv) > 2 and sys.argv[1] == "--counter":
         # --counter <dir> <kernel substring> <counter name>

@@ -119,3 +119,44 @@ def test_forces_and_stress_after_scf_c1():
     print(f"[gpu] SCF c1: max |f| {np.max(np.abs(Fo)):.3e} Ha/bohr, rel err {ef:.2e}; "
           f"max |sigma| {np.max(np.abs(So)):.3e} Ha/bohr^3, rel err {es:.2e}", flush=True)
     assert ef < 1e-5 and es < 1e-5
+
+
+@pytest.mark.parametrize("name,precision", [("c2", "fp64"), ("c3", "mixed")])
+def test_forces_and_stress_full_size_sampled_states(name, precision):
+    """Full-size blocks (c2: 256 states FP64; c3: 640 states FP32) in the
+    benchmark's configuration; occupations are zero except on four states
+    in different 64-state tiles, so the oracle needs only those columns
+    (a state with f = 0 contributes nothing to D, the forces or the stress)."""
+    torch = _torch()
+    from oracle import forces as oforces
+    from paper_2507_23612_amd import hcu
+    cfg = workloads.make_config(name)
+    nd, ns = int(np.prod(cfg["n"])), int(cfg["ns"])
+    print(f"[gpu] forces/stress full size {name} {precision}", flush=True)
+    if precision == "fp64":
+        X = workloads.random_block(nd, ns, 91)
+    else:
+        X = np.random.default_rng(91).random((ns, nd), dtype=np.float32) - np.float32(0.5)
+    cols = [5, 70, 141, 250] if ns == 256 else [3, 200, 411, 637]
+    f = np.zeros(ns)
+    f[cols] = [0.9, 0.6, 0.35, 0.1]
+    ctx = hcu.HcuContext(cfg, precision)
+    ctx.set_hubbard_occupation(hcu.initial_occupation(ctx, cfg))
+    Xd = torch.from_numpy(X).to(ctx.device).to(ctx.dtype)
+    ctx.set_start(0, 0, Xd, Xd[0].clone())
+    torch.cuda.synchronize()
+    import time
+    t0 = time.perf_counter()
+    F = ctx.hubbard_forces(f[None, None, :])
+    S = ctx.hubbard_stress(f[None, None, :])
+    dt = time.perf_counter() - t0
+    ctx.close()
+    del Xd
+    Xo = X[cols].astype(np.float64)
+    Fo, So = oforces.forces_and_stress(cfg, [[Xo]], [[f[cols]]])
+    ef = np.max(np.abs(F - Fo)) / np.max(np.abs(Fo))
+    es = np.max(np.abs(S - So)) / np.max(np.abs(So))
+    print(f"[gpu] full size {name}: forces + stress {dt * 1e3:.1f} ms; rel err forces {ef:.2e} stress {es:.2e}",
+          flush=True)
+    bar = 1e-10 if precision == "fp64" else 1e-4
+    assert ef < bar and es < bar
