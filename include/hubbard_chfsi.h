@@ -194,6 +194,30 @@ hcu_status hcu_workspace_size(const hcu_ctx* ctx, size_t* bytes);
  * a HIP error. */
 hcu_status hcu_bind(hcu_ctx* ctx, void* dev_ptr, size_t bytes, void* stream);
 
+/* Move the atoms of a bound context (ab initio molecular dynamics, Sec.
+ * II.B): pos is host [natom][3] bohr.  The supports, the atom-centred
+ * function tables and V_loc are rebuilt on the device for the new geometry;
+ * the orbitals are kept (the start of the next SCF) and the next hcu_scf /
+ * hcu_scf_begin recomputes the spectral bounds.  If the context holds
+ * converged results (after hcu_scf or hcu_update_occupations), their
+ * positions and occupation matrices D_out first join a history of the last
+ * three geometries.  extrapolate = 1 then sets the input occupation
+ * matrices by the second-order extrapolation the paper uses for D in AIMD:
+ * D split into the isolated-atom part and a residual, the residual carried
+ * forward as
+ *   D(t+dt) = D(t) + a (D(t) - D(t-dt)) + b (D(t-dt) - D(t-2dt)),
+ * with a, b the least-squares fit of the atomic trajectory
+ *   R(t+dt) - R(t) ~ a (R(t) - R(t-dt)) + b (R(t-dt) - R(t-2dt))
+ * (minimum-norm solution when the two steps are parallel; with one or two
+ * recorded geometries b = 0, and a = 0 with one).  The isolated-atom part
+ * does not depend on the positions, so it cancels from the differences.
+ * extrapolate = 0 leaves D_in unchanged.  coeffs (optional, host double[3])
+ * receives {a, b, order}.  Errors: HCU_NOT_BOUND, HCU_INVALID_ARG, HCU_NAN
+ * (non-finite position), HCU_OOM when the moved supports need more than the
+ * bound workspace (nothing changes; bind a larger buffer - the binding may
+ * be larger than hcu_workspace_size() - and retry). */
+hcu_status hcu_move_atoms(hcu_ctx* ctx, const double* pos, int extrapolate, double* coeffs);
+
 /* Hubbard occupation matrices D_in (host, [nspin][nhub][5][5] row-major;
  * rows/cols beyond 2l+1 ignored for l < 2) defining H[D] (Sec. II.A). */
 hcu_status hcu_set_hubbard_occupation(hcu_ctx* ctx, const double* D);

@@ -23,11 +23,12 @@ namespace {
 
 struct Bump {
   char* base;
+  bool assign = true;   // false: only measure
   size_t off = 0;
   template <typename P>
   void take(P*& ptr, size_t bytes) {
     off = (off + 255) & ~size_t(255);
-    ptr = base ? reinterpret_cast<P*>(base + off) : nullptr;
+    if (assign) ptr = base ? reinterpret_cast<P*>(base + off) : nullptr;
     off += std::max<size_t>(bytes, 1);
   }
 };
@@ -38,67 +39,47 @@ constexpr int kInfoPerBlock = 4;   // eigensolve status words per (spin, k): Cho
 constexpr size_t kBatchJobBytes = 1 << 20;   // stencil job records of one batched pass (~2900 jobs)
 constexpr unsigned long long kPersistentMinItems = 4096;   // smaller batched launches use one workgroup per item
 
-size_t layout(Ctx& c, char* base) {
-  Bump b{base};
+// Workspace layout.  Buffers whose size does not depend on the atom
+// positions come first (orbitals, work blocks, small dense buffers), then the
+// position-dependent tables (supports, bricks, function values), so that
+// moving the atoms re-lays out only the tail and the orbitals stay in place.
+// assign = false measures without touching the context's pointers.
+size_t layout(Ctx& c, char* base, bool assign = true) {
+  Bump b{base, assign};
   const size_t es = esize(c);
   const int nsk = c.p.nspin * c.p.nk;
   const int ns = c.p.ns;
   const int nh = (int)c.hub_atoms.size();
   const int cp = c.any_complex ? 2 : 1;
+  // ---- position independent
   b.take(c.d_V, sizeof(double) * c.nd);
   if (c.mixed) b.take(c.d_Vf, sizeof(float) * c.nd);
-  b.take(c.d_supp, sizeof(int) * c.supp.size());
   b.take(c.d_blocks, sizeof(BlockDesc) * c.blocks.size());
   b.take(c.d_nm_lists, sizeof(int) * c.blocks.size());
   b.take(c.d_hub_blocks, sizeof(int) * nh);
-  b.take(c.d_boff, sizeof(int64_t) * c.boff.size());
-  b.take(c.d_bnj, sizeof(int) * c.bnj.size());
-  b.take(c.d_bj, sizeof(int) * c.bj.size());
-  b.take(c.d_bsrc, sizeof(int64_t) * c.bsrc.size());
-  b.take(c.d_pboff, sizeof(int64_t) * c.pboff.size());
-  b.take(c.d_pbnj, sizeof(int) * c.pbnj.size());
-  b.take(c.d_pbsrc, sizeof(int64_t) * c.pbsrc.size());
-  b.take(c.d_pdest, sizeof(int64_t) * c.pdest.size());
-  b.take(c.d_jrow, sizeof(int64_t) * c.jrow.size());
-  c.d_cscv.assign(c.p.nk, nullptr);
-  c.d_bval.assign(c.p.nk, nullptr);
-  c.d_pbval.assign(c.p.nk, nullptr);
-  for (int k = 0; k < c.p.nk; ++k) {
-    b.take(c.d_pbval[k], es * c.pbsrc.size());
-    b.take(c.d_cscv[k], es * c.nval);
-    b.take(c.d_bval[k], es * c.bsrc.size());
-  }
-  c.d_coup.assign(c.p.nspin, nullptr);
-  for (int s = 0; s < c.p.nspin; ++s) b.take(c.d_coup[s], sizeof(double) * c.coup_size);
-  c.d_X.assign(nsk, nullptr);
-  c.d_v0.assign(nsk, nullptr);
-  c.d_PX.assign(nsk, nullptr);
+  std::vector<double*> coup(c.p.nspin, nullptr);
+  for (int s = 0; s < c.p.nspin; ++s) b.take(coup[s], sizeof(double) * c.coup_size);
+  std::vector<void*> X(nsk), v0(nsk), PX(nsk), W(3 * nsk), P(nsk), Q(nsk), PY(nsk);
   for (int i = 0; i < nsk; ++i) {
-    b.take(c.d_X[i], es * (size_t)c.nd * ns);
-    b.take(c.d_v0[i], es * (size_t)c.nd);
-    b.take(c.d_PX[i], es * (size_t)ns * c.nproj);
+    b.take(X[i], es * (size_t)c.nd * ns);
+    b.take(v0[i], es * (size_t)c.nd);
+    b.take(PX[i], es * (size_t)ns * c.nproj);
   }
-  c.d_W.assign(3 * nsk, nullptr);
-  c.d_P.assign(nsk, nullptr);
-  c.d_Q.assign(nsk, nullptr);
-  c.d_PY.assign(nsk, nullptr);
   for (int i = 0; i < nsk; ++i) {
-    for (int w = 0; w < 3; ++w) b.take(c.d_W[3 * i + w], es * (size_t)c.nd * ns);
-    b.take(c.d_P[i], es * (size_t)ns * c.nproj);
-    b.take(c.d_Q[i], es * (size_t)ns * c.nproj);
-    b.take(c.d_PY[i], es * (size_t)ns * c.nproj);
+    for (int w = 0; w < 3; ++w) b.take(W[3 * i + w], es * (size_t)c.nd * ns);
+    b.take(P[i], es * (size_t)ns * c.nproj);
+    b.take(Q[i], es * (size_t)ns * c.nproj);
+    b.take(PY[i], es * (size_t)ns * c.nproj);
+  }
+  if (assign) {
+    c.d_coup = coup;
+    c.d_X = X; c.d_v0 = v0; c.d_PX = PX; c.d_W = W; c.d_P = P; c.d_Q = Q; c.d_PY = PY;
   }
   b.take(c.d_jobs, kBatchJobBytes);
   b.take(c.d_counters, sizeof(unsigned long long) * kNumXcd);
-  b.take(c.d_ppart, es * project_partial_elems(c));
-  b.take(c.d_lowC, sizeof(double) * 50 * (size_t)c.p.nk * nh);
-  b.take(c.d_momcsc, es * (size_t)c.nval);
-  for (int d = 0; d < 3; ++d) b.take(c.d_mom[d], es * c.pbsrc.size());
-  b.take(c.d_fproj, es * 13 * (size_t)ns * c.nproj);
-  b.take(c.d_fsum, sizeof(double) * 650 * (size_t)nh);
-  b.take(c.d_focc, sizeof(double) * (size_t)nsk * ns);
-  c.part_elems = c.any_complex ? gram_partial_elems_c(ns, c.nd) : gram_partial_elems(ns, c.nd);
-  b.take(c.d_part, sizeof(double) * c.part_elems);
+  const size_t part_elems = c.any_complex ? gram_partial_elems_c(ns, c.nd) : gram_partial_elems(ns, c.nd);
+  if (assign) c.part_elems = part_elems;
+  b.take(c.d_part, sizeof(double) * part_elems);
   b.take(c.d_tiles, sizeof(int2) * gram_tiles(ns, c.any_complex).size());
   b.take(c.d_S, sizeof(double) * (size_t)ns * ns * cp);
   b.take(c.d_Hs, sizeof(double) * (size_t)ns * ns * cp);
@@ -108,15 +89,18 @@ size_t layout(Ctx& c, char* base) {
   b.take(c.d_occ, sizeof(double) * (size_t)nsk * ns);
   b.take(c.d_E, sizeof(double) * (size_t)ns * 2);
   b.take(c.d_info, sizeof(int) * 4);
-  c.rr_slots.resize((size_t)std::max(0, std::min(nsk, kRRLanes) - 1));
-  for (Ctx::RRSlot& r : c.rr_slots) {
-    b.take(r.part, sizeof(double) * c.part_elems);
+  std::vector<Ctx::RRSlot> slots((size_t)std::max(0, std::min(nsk, kRRLanes) - 1));
+  for (size_t i = 0; i < slots.size(); ++i) {
+    Ctx::RRSlot& r = slots[i];
+    if (i < c.rr_slots.size()) r.blas = c.rr_slots[i].blas;
+    b.take(r.part, sizeof(double) * part_elems);
     b.take(r.S, sizeof(double) * (size_t)ns * ns * cp);
     b.take(r.Hs, sizeof(double) * (size_t)ns * ns * cp);
     b.take(r.Cb, es * (size_t)ns * ns);
     b.take(r.E, sizeof(double) * (size_t)ns * 2);
     b.take(r.info, sizeof(int) * 4);
   }
+  if (assign) c.rr_slots = slots;
   b.take(c.d_D, sizeof(double) * (size_t)c.p.nspin * nh * 25);
   size_t red = std::max<size_t>(16384 * sizeof(double), sizeof(double) * 8 * (size_t)c.p.natom);
   red = std::max(red, sizeof(int) * c.blocks.size());
@@ -124,8 +108,36 @@ size_t layout(Ctx& c, char* base) {
   b.take(c.d_scal, sizeof(double) * (64 + nsk + nh + c.p.nspin + 8));
   b.take(c.d_rho, sizeof(double) * (size_t)c.p.nspin * c.nd);
   b.take(c.d_vec, es * (size_t)c.nd * 4);
+  b.take(c.d_lowC, sizeof(double) * 50 * (size_t)c.p.nk * nh);
+  b.take(c.d_fproj, es * 13 * (size_t)ns * c.nproj);
+  b.take(c.d_fsum, sizeof(double) * 650 * (size_t)nh);
+  b.take(c.d_focc, sizeof(double) * (size_t)nsk * ns);
+  // ---- position dependent
+  b.take(c.d_supp, sizeof(int) * c.supp.size());
+  b.take(c.d_boff, sizeof(int64_t) * c.boff.size());
+  b.take(c.d_bnj, sizeof(int) * c.bnj.size());
+  b.take(c.d_bj, sizeof(int) * c.bj.size());
+  b.take(c.d_bsrc, sizeof(int64_t) * c.bsrc.size());
+  b.take(c.d_pboff, sizeof(int64_t) * c.pboff.size());
+  b.take(c.d_pbnj, sizeof(int) * c.pbnj.size());
+  b.take(c.d_pbsrc, sizeof(int64_t) * c.pbsrc.size());
+  b.take(c.d_pdest, sizeof(int64_t) * c.pdest.size());
+  b.take(c.d_jrow, sizeof(int64_t) * c.jrow.size());
+  std::vector<void*> cscv(c.p.nk), bval(c.p.nk), pbval(c.p.nk);
+  for (int k = 0; k < c.p.nk; ++k) {
+    b.take(pbval[k], es * c.pbsrc.size());
+    b.take(cscv[k], es * c.nval);
+    b.take(bval[k], es * c.bsrc.size());
+  }
+  if (assign) { c.d_cscv = cscv; c.d_bval = bval; c.d_pbval = pbval; }
+  b.take(c.d_ppart, es * project_partial_elems(c));
+  b.take(c.d_momcsc, es * (size_t)c.nval);
+  for (int d = 0; d < 3; ++d) b.take(c.d_mom[d], es * c.pbsrc.size());
   return b.off;
 }
+
+hcu_status upload_structure(Ctx& c);
+void aimd_coefficients(const Ctx& c, double* out);
 
 hcu_status check_ctx(const hcu_ctx* ctx) {
   if (!ctx) return HCU_INVALID_ARG;
@@ -1203,6 +1215,7 @@ hcu_status hcu_bind(hcu_ctx* ctx, void* dev_ptr, size_t bytes, void* stream) {
   if (((uintptr_t)dev_ptr) % 256) return fail(c, HCU_INVALID_ARG, "workspace must be 256-byte aligned");
   if (bytes < c.ws_bytes) return fail(c, HCU_OOM, "workspace smaller than hcu_workspace_size()");
   c.ws = (char*)dev_ptr;
+  c.ws_bound = bytes;
   c.stream = (hipStream_t)stream;
   layout(c, c.ws);
   if (!c.blas) {
@@ -1217,6 +1230,69 @@ hcu_status hcu_bind(hcu_ctx* ctx, void* dev_ptr, size_t bytes, void* stream) {
     std::copy(c.h_info_store.begin(), c.h_info_store.end(), c.h_info_pinned);
     c.h_info = c.h_info_pinned;
   }
+  hcu_status s = upload_structure(c);
+  if (s != HCU_OK) return s;
+  c.bound = true;
+  s = upload_coupling(c);
+  if (s != HCU_OK) return s;
+  HCU_HIP(hipStreamSynchronize(c.stream));
+  return HCU_OK;
+}
+
+hcu_status hcu_move_atoms(hcu_ctx* ctx, const double* pos, int extrapolate, double* coeffs) {
+  hcu_status s = check_ctx(ctx);
+  if (s != HCU_OK) return s;
+  Ctx& c = *ctx;
+  if (!pos) return fail(c, HCU_INVALID_ARG, "null positions");
+  for (int i = 0; i < 3 * c.p.natom; ++i)
+    if (!std::isfinite(pos[i])) return fail(c, HCU_NAN, "non-finite position");
+  // the converged state of the current geometry joins the history
+  if (c.have_results) {
+    c.aimd_pos.insert(c.aimd_pos.begin(), c.pos);
+    c.aimd_D.insert(c.aimd_D.begin(), c.D_out);
+    if (c.aimd_pos.size() > 3) { c.aimd_pos.pop_back(); c.aimd_D.pop_back(); }
+  }
+  const std::vector<double> old = c.pos;
+  c.pos.assign(pos, pos + 3 * c.p.natom);
+  s = build_structure(c);
+  const size_t need = s == HCU_OK ? layout(c, nullptr, false) : 0;
+  if (s != HCU_OK || need > c.ws_bound) {
+    c.pos = old;   // the previous geometry stays in force
+    const std::string why = s != HCU_OK ? c.err : "the moved atoms need " + std::to_string(need) +
+                                                      " workspace bytes, " + std::to_string(c.ws_bound) + " bound";
+    build_structure(c);
+    return fail(c, s != HCU_OK ? s : HCU_OOM, why);
+  }
+  c.ws_bytes = need;
+  layout(c, c.ws);
+  s = upload_structure(c);
+  if (s != HCU_OK) return s;
+  c.have_results = false;
+  c.scf_ready = false;
+  double ab[3] = {0.0, 0.0, 0.0};
+  if (extrapolate && !c.aimd_D.empty()) {
+    aimd_coefficients(c, ab);
+    const std::vector<double>& D0 = c.aimd_D[0];
+    for (size_t i = 0; i < c.D_in.size(); ++i) {
+      double d = D0[i];
+      if (c.aimd_D.size() >= 2) d += ab[0] * (D0[i] - c.aimd_D[1][i]);
+      if (c.aimd_D.size() >= 3) d += ab[1] * (c.aimd_D[1][i] - c.aimd_D[2][i]);
+      c.D_in[i] = d;
+    }
+  }
+  s = upload_coupling(c);
+  if (s != HCU_OK) return s;
+  if (coeffs) { coeffs[0] = ab[0]; coeffs[1] = ab[1]; coeffs[2] = ab[2]; }
+  HCU_HIP(hipStreamSynchronize(c.stream));
+  return HCU_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- structure upload and AIMD
+namespace {
+
+hcu_status upload_structure(Ctx& c) {
   // per-count block lists and Hubbard block indices
   std::vector<int> lists, hb;
   for (int nm = 0; nm <= kMaxNm; ++nm)
@@ -1232,12 +1308,66 @@ hcu_status hcu_bind(hcu_ctx* ctx, void* dev_ptr, size_t bytes, void* stream) {
   HCU_HIP(hipMemcpyAsync(c.d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice, c.stream));
   hcu_status s = device_tables(c);
   if (s != HCU_OK) return s;
-  c.bound = true;
-  s = upload_coupling(c);
-  if (s != HCU_OK) return s;
-  HCU_HIP(hipStreamSynchronize(c.stream));
+  HCU_HIP(hipStreamSynchronize(c.stream));   // lists, hb, tiles are released on return
   return HCU_OK;
 }
+
+// Coefficients of the second-order extrapolation of an atomic trajectory
+// (the scheme the paper adopts for the occupation matrix in AIMD, after the
+// charge-density extrapolation it cites, Sec. II.B): with the new positions
+// R0 and the recorded ones R1, R2, R3 (most recent first),
+//   R0 - R1 ~ a (R1 - R2) + b (R2 - R3)
+// in the least-squares sense over all atoms (minimum-norm solution when the
+// two history steps are parallel); one recorded step earlier only the first
+// term (b = 0).  out = {a, b, order}.
+void aimd_coefficients(const Ctx& c, double* out) {
+  const size_t nh = c.aimd_pos.size();
+  out[0] = out[1] = 0.0;
+  out[2] = nh >= 3 ? 2 : nh >= 2 ? 1 : 0;
+  if (nh < 2) return;
+  const int n = 3 * c.p.natom;
+  auto d = [&](const std::vector<double>& a, const std::vector<double>& b, int i) { return a[i] - b[i]; };
+  double y1 = 0, s11 = 0;
+  double s12 = 0, s22 = 0, y2 = 0;
+  for (int i = 0; i < n; ++i) {
+    const double r = d(c.pos, c.aimd_pos[0], i);
+    const double x1 = d(c.aimd_pos[0], c.aimd_pos[1], i);
+    s11 += x1 * x1;
+    y1 += x1 * r;
+    if (nh >= 3) {
+      const double x2 = d(c.aimd_pos[1], c.aimd_pos[2], i);
+      s12 += x1 * x2;
+      s22 += x2 * x2;
+      y2 += x2 * r;
+    }
+  }
+  if (nh < 3) {
+    out[0] = s11 > 0 ? y1 / s11 : 0.0;
+    return;
+  }
+  // min-norm solution of [[s11, s12], [s12, s22]] [a, b] = [y1, y2]
+  const double tr = s11 + s22, det = s11 * s22 - s12 * s12;
+  if (tr <= 0) return;
+  if (det > 1e-12 * tr * tr) {
+    out[0] = (s22 * y1 - s12 * y2) / det;
+    out[1] = (s11 * y2 - s12 * y1) / det;
+  } else {
+    // rank one: the normal matrix is tr u u^T with u a unit column of it;
+    // the minimum-norm least-squares solution is u (u . y) / tr
+    double u0 = s11, u1 = s12;
+    if (std::fabs(u0) + std::fabs(u1) == 0.0) { u0 = s12; u1 = s22; }
+    const double nu = std::sqrt(u0 * u0 + u1 * u1);
+    u0 /= nu;
+    u1 /= nu;
+    const double t = (u0 * y1 + u1 * y2) / tr;
+    out[0] = t * u0;
+    out[1] = t * u1;
+  }
+}
+
+}  // namespace
+
+extern "C" {
 
 hcu_status hcu_set_hubbard_occupation(hcu_ctx* ctx, const double* D) {
   if (!ctx) return HCU_INVALID_ARG;

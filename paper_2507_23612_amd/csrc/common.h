@@ -158,6 +158,7 @@ struct Ctx {
   int* d_hub_blocks = nullptr;       // block index of each Hubbard atom
   // device layout (byte offsets into the workspace)
   size_t ws_bytes = 0;
+  size_t ws_bound = 0;               // bytes of the bound workspace
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   bool bound = false;
@@ -228,6 +229,8 @@ struct Ctx {
   std::vector<double> D_out;
   hcu_energies en{};
   bool have_results = false;
+  // AIMD history: positions and converged D of the last geometries, most recent first
+  std::vector<std::vector<double>> aimd_pos, aimd_D;
   std::string err;
   // tuning
   int tile_x = 0, tile_yt = 0, ry = 4, tile_z = 0;

@@ -151,6 +151,7 @@ def load_library(path=LIB_PATH):
         "hcu_mlp_guess": (C.c_int, [P, P, C.c_int, C.POINTER(C.c_float)]),
         "hcu_gram_noalloc": (C.c_int, [P, P, C.c_int, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_double, P, P, P]),
         "hcu_hubbard_forces": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "hcu_move_atoms": (C.c_int, [P, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double)]),
         "hcu_hubbard_stress": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     }
     for name, (res, args) in sig.items():
@@ -225,7 +226,7 @@ class Problem:
 class HcuContext:
     """One library context bound to a torch-allocated device workspace."""
 
-    def __init__(self, cfg, precision=None, device="cuda:0"):
+    def __init__(self, cfg, precision=None, device="cuda:0", workspace_margin=0.0):
         import torch
         self.lib = load_library()
         self.torch = torch
@@ -242,11 +243,13 @@ class HcuContext:
         self._check(self.lib.hcu_workspace_size(self.h, C.byref(nb)))
         self.workspace_bytes = nb.value
         self.device = torch.device(device)
-        self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        # a margin lets moved atoms (hcu_move_atoms) grow their supports in place
+        self.bound_bytes = int(self.workspace_bytes * (1.0 + workspace_margin)) // 256 * 256 + 256
+        self.ws = torch.empty(self.bound_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()
         self.ws_ptr = (base + 255) // 256 * 256
         self.stream = torch.cuda.current_stream(self.device)
-        self._check(self.lib.hcu_bind(self.h, C.c_void_p(self.ws_ptr), C.c_size_t(self.workspace_bytes),
+        self._check(self.lib.hcu_bind(self.h, C.c_void_p(self.ws_ptr), C.c_size_t(self.bound_bytes),
                                       C.c_void_p(self.stream.cuda_stream)))
         self.nspin = int(cfg["nspin"])
         self.nk = len(self.prob.kw)
@@ -363,6 +366,16 @@ class HcuContext:
         out = {k: getattr(r, k) for k, _ in hcu_scf_report._fields_}
         out["status"] = st
         return out
+
+    def move_atoms(self, pos, extrapolate=True):
+        """Move the atoms (positions [natom][3] bohr); returns the
+        extrapolation coefficients (a, b, order)."""
+        p = np.ascontiguousarray(np.asarray(pos, np.float64).reshape(-1))
+        if p.size != 3 * len(self.prob.spec):
+            raise HcuError(HCU_INVALID_ARG, "positions must be [natom][3]")
+        out = np.zeros(3)
+        self._check(self.lib.hcu_move_atoms(self.h, _dptr(p), 1 if extrapolate else 0, _dptr(out)))
+        return float(out[0]), float(out[1]), int(out[2])
 
     def _occ_arg(self, occ):
         if occ is None:
