@@ -272,12 +272,18 @@ __global__ void k_couple(const T* __restrict__ P, const BlockDesc* __restrict__ 
 //   part[pdest[slot]][s] = sum_{p in B} Phi[slot][p] Y[s][p]
 //                                           (256-point brick B, as k_proj_brick)
 // One workgroup per (projection brick, 64 states) walks the brick's four
-// scatter bricks: each is updated in registers and written back, and the new
-// values go through a wave-private LDS tile [state][point] (rows padded by
-// 16 bytes) into the projection's operand order, so the block is read and
-// written once for both operations.  NT bounds the brick's slot tiles (all
-// accumulators stay in registers).
+// scatter bricks.  For each, the coupled projections alpha Q of the brick's
+// functions (for the workgroup's 64 states) and the brick's table rows are
+// staged into LDS by all four waves together, a chunk of functions at a
+// time (one batched round trip to memory per chunk, each value fetched once
+// per workgroup), and the waves' matrix-core updates of their 16 states read
+// both operands from LDS.  The updated values are written back and, through
+// a wave-private LDS tile [state][point] (rows padded by 16 bytes) that
+// reuses the staging area, fed into the projection's operand order, so the
+// block is read and written once for both operations.  NT bounds the
+// brick's slot tiles (all projection accumulators stay in registers).
 template <typename T> constexpr int kYsRow = kBrick + 16 / (int)sizeof(T);
+template <typename T> constexpr int kStageFns = sizeof(T) == 8 ? 32 : 64;   // functions staged per chunk
 
 template <typename T, int G, int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_scatter_project(
@@ -287,21 +293,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int64_t* __restrict__ pdest, T* __restrict__ part, int ldp, int64_t nd, int nst) {
   using V = typename Mf<T>::V;
   constexpr int P = kPBrick / kBrick;
-  constexpr int RS = kYsRow<T>;
-  __shared__ __attribute__((aligned(16))) T ys[4][16 * RS];
+  constexpr int RS = kYsRow<T>;                // row of a transposition tile and of a staged function
+  constexpr int CH = kStageFns<T>;
+  constexpr int kYs = 4 * 16 * RS, kSt = 2 * CH * RS;
+  __shared__ __attribute__((aligned(16))) T lds[kYs > kSt ? kYs : kSt];
+  T* const sQ = lds;             // [CH][RS]: alpha Q of the chunk's functions, the workgroup's states
+  T* const sB = lds + CH * RS;   // [CH][RS]: the chunk's rows of the brick's value table
   const unsigned lw = xcd_linear();   // 1-D grid: state tile fastest, then brick
   const int b = lw / nst;
   const int st_ = lw % nst;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int s0 = st_ * 64 + wave * 16;
-  if (s0 >= ncol) return;   // whole wave; no workgroup barrier below
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int swg = st_ * 64;
+  const int s0 = swg + wave * 16;
+  // waves past the last state take part in the staging and the barriers only
+  const bool wave_ok = s0 < ncol;
   const int sa = s0 + (lane & 15);
   const bool sa_ok = sa < ncol;
   const int q = lane >> 4;
   const int njp = pbnj[b];
   const int ntile = (njp + 15) / 16;   // <= NT (host-checked)
   const int64_t jop = pboff[b];
-  T* yw = ys[wave];
+  T* const yw = lds + wave * 16 * RS;
   V pacc[NT];
   for (int t = 0; t < NT; ++t)
     for (int r = 0; r < 4; ++r) pacc[t][r] = T(0);
@@ -309,7 +322,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int sbk = b * P + k;
     if (sbk >= nbrick) break;   // uniform: the last brick of a ragged grid
     const int64_t p0 = (int64_t)sbk * kBrick;
-    // ---- scatter of brick sbk (k_nl_brick's steps)
+    // ---- scatter of brick sbk
     V acc[4];
     for (int pt = 0; pt < 4; ++pt)
       for (int r = 0; r < 4; ++r) {
@@ -318,31 +331,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         acc[pt][r] = (s < ncol && p < nd) ? Y[(int64_t)s * ld + p] : T(0);
       }
     const int64_t jo = boff[sbk];
-    const int nj4 = (bnj[sbk] + 3) & ~3;
+    const int nj4 = (bnj[sbk] + 3) & ~3;   // uniform over the workgroup
     const T* __restrict__ vb = bval + jo * kBrick;
-    int bjl = -1;
-    for (int jj = 0; jj < nj4; jj += 8) {
-      if ((jj & 63) == 0) {
-        const int e = jj + lane;
-        bjl = e < nj4 ? bj[jo + e] : -1;
-      }
-      T a[2], bb[2][4];
-      for (int u = 0; u < 2; ++u) {
-        const int jl = jj + 4 * u + (lane >> 4);
-        a[u] = T(0);
-        for (int pt = 0; pt < 4; ++pt) bb[u][pt] = T(0);
-        if (jj + 4 * u < nj4) {   // wave-uniform
-          const int jg = __shfl(bjl, jl & 63);
-          if (sa_ok && jg >= 0) a[u] = alpha * Qt[(int64_t)jg * ldq + sa];
-          for (int pt = 0; pt < 4; ++pt) bb[u][pt] = vb[(int64_t)jl * kBrick + pt * 16 + (lane & 15)];
+    for (int c0 = 0; c0 < nj4; c0 += CH) {
+      const int nc = min(CH, nj4 - c0);
+      __syncthreads();   // earlier readers of the area (staging or transposition tiles) are done
+      for (int i = 0; i < CH / 4; ++i) {
+        const int fn = wave + 4 * i;   // wave-uniform
+        T qv = T(0), bv = T(0);
+        if (fn < nc) {
+          const int jg = bj[jo + c0 + fn];
+          const int s = swg + lane;
+          if (jg >= 0 && s < ncol) qv = alpha * Qt[(int64_t)jg * ldq + s];
+          bv = vb[(int64_t)(c0 + fn) * kBrick + lane];
         }
+        sQ[fn * RS + lane] = qv;
+        sB[fn * RS + lane] = bv;
       }
-      for (int u = 0; u < 2; ++u) {
-        if (jj + 4 * u >= nj4) break;
-        for (int pt = 0; pt < 4; ++pt) acc[pt] = Mf<T>::mfma(a[u], bb[u][pt], acc[pt]);
-      }
+      __syncthreads();
+      if (wave_ok)
+        for (int f4 = 0; f4 < nc; f4 += 4) {
+          const int fr = (f4 + q) * RS;
+          const T a = sQ[fr + wave * 16 + (lane & 15)];
+          for (int pt = 0; pt < 4; ++pt) acc[pt] = Mf<T>::mfma(a, sB[fr + pt * 16 + (lane & 15)], acc[pt]);
+        }
     }
-    wave_lds_sync();   // the previous piece's reads of yw are done
+    __syncthreads();   // the staging area becomes the transposition tiles
     for (int pt = 0; pt < 4; ++pt)
       for (int r = 0; r < 4; ++r) {
         const int sl = Mf<T>::row(lane, r);
@@ -350,7 +364,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         if (nj4 > 0 && s0 + sl < ncol && p < nd) Y[(int64_t)(s0 + sl) * ld + p] = acc[pt][r];
         yw[sl * RS + pt * 16 + (lane & 15)] = acc[pt][r];
       }
-    if (ntile == 0) continue;
+    if (ntile == 0 || !wave_ok) continue;
     // ---- projection of the updated piece k (wave-private LDS, in order)
     wave_lds_sync();   // every lane's writes of yw are visible
     T bk[16];
