@@ -180,6 +180,7 @@ struct Ctx {
   void* d_jobs = nullptr;            // batched-stencil job table (used when this context leads a batch)
   unsigned long long* d_counters = nullptr;
   void* d_ppart = nullptr;           // projection partial sums [chunk][nproj][ns]
+  std::vector<void*> d_ppart_sk;     // per (spin, k) block (several blocks in one fused launch); [0] = d_ppart
   // Hubbard forces and stress
   double* d_lowC = nullptr;          // Loewdin coefficients [nk][nhub][re 25, im 25]
   void* d_momcsc = nullptr;          // moment values on the supports (nval elements)
@@ -412,6 +413,22 @@ hcu_status build_moment_table(Ctx& c, int ik, int b, T* csc, T* table, hipStream
 // updated Y (the next Chebyshev step's input); usable when scatter_project_ok.
 template <typename T>
 bool scatter_project_ok(const Ctx& c);
+// The fused pass of several blocks in one launch: one record per block,
+// workgroups item0 .. of each job (jobs ordered by item0).
+struct FusedJob {
+  void* Y; int64_t ld; int ncol; int nst;
+  const int64_t* boff; const int* bnj; const int* bj; const void* bval;
+  const void* Qt; int ldq; double alpha; int nbrick;
+  const int64_t* pboff; const int* pbnj; const void* pbval; const int64_t* pdest;
+  void* part; int ldp; int64_t nd;
+  unsigned item0;
+};
+template <typename T>
+FusedJob fused_job_of(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T* Qt, double alpha, void* part,
+                      unsigned item0);
+unsigned fused_job_items(const Ctx& c, int ncol);
+template <typename T>
+void launch_scatter_project_batch(const FusedJob* d_jobs, int njob, unsigned items, int G, int NT, hipStream_t st);
 template <typename T>
 void launch_scatter_project(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T* Qt, double alpha,
                             const double* coup, T* P, T* Q, hipStream_t st, int part = 3);

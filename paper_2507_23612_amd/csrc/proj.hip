@@ -285,12 +285,15 @@ __global__ void k_couple(const T* __restrict__ P, const BlockDesc* __restrict__ 
 template <typename T> constexpr int kYsRow = kBrick + 16 / (int)sizeof(T);
 template <typename T> constexpr int kStageFns = sizeof(T) == 8 ? 32 : 64;   // functions staged per chunk
 
+// body of one workgroup: projection brick b, state tile st_
 template <typename T, int G, int NT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_scatter_project(
-    T* __restrict__ Y, int64_t ld, int ncol, const int64_t* __restrict__ boff, const int* __restrict__ bnj,
-    const int* __restrict__ bj, const T* __restrict__ bval, const T* __restrict__ Qt, int ldq, T alpha, int nbrick,
-    const int64_t* __restrict__ pboff, const int* __restrict__ pbnj, const T* __restrict__ pbval,
-    const int64_t* __restrict__ pdest, T* __restrict__ part, int ldp, int64_t nd, int nst) {
+__device__ __forceinline__ void fused_real(T* __restrict__ Y, int64_t ld, int ncol, const int64_t* __restrict__ boff,
+                                           const int* __restrict__ bnj, const int* __restrict__ bj,
+                                           const T* __restrict__ bval, const T* __restrict__ Qt, int ldq, T alpha,
+                                           int nbrick, const int64_t* __restrict__ pboff,
+                                           const int* __restrict__ pbnj, const T* __restrict__ pbval,
+                                           const int64_t* __restrict__ pdest, T* __restrict__ part, int ldp,
+                                           int64_t nd, int b, int st_) {
   using V = typename Mf<T>::V;
   constexpr int P = kPBrick / kBrick;
   constexpr int RS = kYsRow<T>;                // row of a transposition tile and of a staged function
@@ -299,9 +302,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   __shared__ __attribute__((aligned(16))) T lds[kYs > kSt ? kYs : kSt];
   T* const sQ = lds;             // [CH][RS]: alpha Q of the chunk's functions, the workgroup's states
   T* const sB = lds + CH * RS;   // [CH][RS]: the chunk's rows of the brick's value table
-  const unsigned lw = xcd_linear();   // 1-D grid: state tile fastest, then brick
-  const int b = lw / nst;
-  const int st_ = lw % nst;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int swg = st_ * 64;
@@ -388,23 +388,57 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   }
 }
 
+template <typename T, int G, int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_scatter_project(
+    T* __restrict__ Y, int64_t ld, int ncol, const int64_t* __restrict__ boff, const int* __restrict__ bnj,
+    const int* __restrict__ bj, const T* __restrict__ bval, const T* __restrict__ Qt, int ldq, T alpha, int nbrick,
+    const int64_t* __restrict__ pboff, const int* __restrict__ pbnj, const T* __restrict__ pbval,
+    const int64_t* __restrict__ pdest, T* __restrict__ part, int ldp, int64_t nd, int nst) {
+  const unsigned lw = xcd_linear();   // 1-D grid: state tile fastest, then brick
+  fused_real<T, G, NT>(Y, ld, ncol, boff, bnj, bj, bval, Qt, ldq, alpha, nbrick, pboff, pbnj, pbval, pdest, part,
+                       ldp, nd, lw / nst, lw % nst);
+}
+
+// The job whose workgroups contain lw (jobs ordered by first workgroup).
+__device__ __forceinline__ const FusedJob& fused_job(const FusedJob* __restrict__ jobs, int njob, unsigned lw) {
+  int lo = 0, hi = njob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].item0 <= lw) lo = mid;
+    else hi = mid - 1;
+  }
+  return jobs[lo];
+}
+
+// One launch over the blocks of several (cell, spin, k) problems: the
+// workgroups of job i are item0_i .. item0_{i+1} - 1 (XCD-contiguous).
+template <typename T, int G, int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_scatter_project_batch(
+    const FusedJob* __restrict__ jobs, int njob) {
+  const unsigned lw = xcd_linear();
+  const FusedJob& J = fused_job(jobs, njob, lw);
+  const unsigned local = lw - J.item0;
+  fused_real<T, G, NT>((T*)J.Y, J.ld, J.ncol, J.boff, J.bnj, J.bj, (const T*)J.bval, (const T*)J.Qt, J.ldq,
+                       (T)J.alpha, J.nbrick, J.pboff, J.pbnj, (const T*)J.pbval, J.pdest, (T*)J.part, J.ldp, J.nd,
+                       local / J.nst, local % J.nst);
+}
+
 // Complex (Bloch) blocks in FP32: the same fused pass with the scatter's
 // four real products per step (k_nl_brick_c) and the projection's four
 // accumulators per slot tile (k_proj_brick_c); at most four slot tiles.
 template <typename R, int G, int NT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_scatter_project_c(
-    cplx<R>* __restrict__ Y, int64_t ld, int ncol, const int64_t* __restrict__ boff, const int* __restrict__ bnj,
-    const int* __restrict__ bj, const cplx<R>* __restrict__ bval, const cplx<R>* __restrict__ Qt, int ldq, R alpha,
-    int nbrick, const int64_t* __restrict__ pboff, const int* __restrict__ pbnj, const cplx<R>* __restrict__ pbval,
-    const int64_t* __restrict__ pdest, cplx<R>* __restrict__ part, int ldp, int64_t nd, int nst) {
+__device__ __forceinline__ void fused_cplx(cplx<R>* __restrict__ Y, int64_t ld, int ncol,
+                                           const int64_t* __restrict__ boff, const int* __restrict__ bnj,
+                                           const int* __restrict__ bj, const cplx<R>* __restrict__ bval,
+                                           const cplx<R>* __restrict__ Qt, int ldq, R alpha, int nbrick,
+                                           const int64_t* __restrict__ pboff, const int* __restrict__ pbnj,
+                                           const cplx<R>* __restrict__ pbval, const int64_t* __restrict__ pdest,
+                                           cplx<R>* __restrict__ part, int ldp, int64_t nd, int b, int st_) {
   using V = typename Mf<R>::V;
   using C = cplx<R>;
   constexpr int P = kPBrick / kBrick;
   constexpr int RS = kYsRow<C>;
   __shared__ __attribute__((aligned(16))) unsigned char ys_raw[4 * 16 * RS * sizeof(C)];
-  const unsigned lw = xcd_linear();
-  const int b = lw / nst;
-  const int st_ = lw % nst;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int s0 = st_ * 64 + wave * 16;
   if (s0 >= ncol) return;   // whole wave; no workgroup barrier below
@@ -494,6 +528,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   }
 }
 
+template <typename R, int G, int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_scatter_project_c(
+    cplx<R>* __restrict__ Y, int64_t ld, int ncol, const int64_t* __restrict__ boff, const int* __restrict__ bnj,
+    const int* __restrict__ bj, const cplx<R>* __restrict__ bval, const cplx<R>* __restrict__ Qt, int ldq, R alpha,
+    int nbrick, const int64_t* __restrict__ pboff, const int* __restrict__ pbnj, const cplx<R>* __restrict__ pbval,
+    const int64_t* __restrict__ pdest, cplx<R>* __restrict__ part, int ldp, int64_t nd, int nst) {
+  const unsigned lw = xcd_linear();
+  fused_cplx<R, G, NT>(Y, ld, ncol, boff, bnj, bj, bval, Qt, ldq, alpha, nbrick, pboff, pbnj, pbval, pdest, part,
+                       ldp, nd, lw / nst, lw % nst);
+}
+
+template <typename R, int G, int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_scatter_project_c_batch(
+    const FusedJob* __restrict__ jobs, int njob) {
+  using C = cplx<R>;
+  const unsigned lw = xcd_linear();
+  const FusedJob& J = fused_job(jobs, njob, lw);
+  const unsigned local = lw - J.item0;
+  fused_cplx<R, G, NT>((C*)J.Y, J.ld, J.ncol, J.boff, J.bnj, J.bj, (const C*)J.bval, (const C*)J.Qt, J.ldq,
+                       (R)J.alpha, J.nbrick, J.pboff, J.pbnj, (const C*)J.pbval, J.pdest, (C*)J.part, J.ldp, J.nd,
+                       local / J.nst, local % J.nst);
+}
+
 template <typename T>
 bool scatter_project_ok(const Ctx& c) {
   if (c.nproj == 0 || c.pboff.empty()) return false;
@@ -566,6 +623,48 @@ template void launch_scatter_project<cplx<double>>(const Ctx&, int, cplx<double>
 template void launch_scatter_project<cplx<float>>(const Ctx&, int, cplx<float>*, int64_t, int, const cplx<float>*,
                                                   double, const double*, cplx<float>*, cplx<float>*, hipStream_t,
                                                   int);
+
+// The job record of the fused pass of one block (the block's data, the
+// projection partials of that block, its first workgroup).
+template <typename T>
+FusedJob fused_job_of(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T* Qt, double alpha, void* part,
+                      unsigned item0) {
+  FusedJob j{};
+  j.Y = Y; j.ld = ld; j.ncol = ncol; j.nst = (ncol + 63) / 64;
+  j.boff = c.d_boff; j.bnj = c.d_bnj; j.bj = c.d_bj; j.bval = c.d_bval[ik];
+  j.Qt = Qt; j.ldq = c.p.ns; j.alpha = alpha; j.nbrick = (int)c.boff.size() - 1;
+  j.pboff = c.d_pboff; j.pbnj = c.d_pbnj; j.pbval = c.d_pbval[ik]; j.pdest = c.d_pdest;
+  j.part = part; j.ldp = c.p.ns; j.nd = c.nd;
+  j.item0 = item0;
+  return j;
+}
+
+unsigned fused_job_items(const Ctx& c, int ncol) {
+  return (unsigned)((c.pboff.size() - 1) * (size_t)((ncol + 63) / 64));
+}
+
+template <typename T>
+void launch_scatter_project_batch(const FusedJob* d_jobs, int njob, unsigned items, int G, int NT, hipStream_t st) {
+  if constexpr (sizeof(T) == sizeof(typename real_of<T>::type)) {
+    if (G == 2) {
+      if (NT <= 4) launch_k(k_scatter_project_batch<T, 2, 4>, items, 256, 0, st, d_jobs, njob);
+      else launch_k(k_scatter_project_batch<T, 2, 8>, items, 256, 0, st, d_jobs, njob);
+    } else {
+      if (NT <= 4) launch_k(k_scatter_project_batch<T, 4, 4>, items, 256, 0, st, d_jobs, njob);
+      else launch_k(k_scatter_project_batch<T, 4, 8>, items, 256, 0, st, d_jobs, njob);
+    }
+  } else if constexpr (std::is_same<T, cplx<float>>::value) {
+    launch_k(k_scatter_project_c_batch<float, 2, 4>, items, 256, 0, st, d_jobs, njob);
+  }
+}
+
+#define INST_FUSED_JOB(T)                                                                                    \
+  template FusedJob fused_job_of<T>(const Ctx&, int, T*, int64_t, int, const T*, double, void*, unsigned);  \
+  template void launch_scatter_project_batch<T>(const FusedJob*, int, unsigned, int, int, hipStream_t);
+INST_FUSED_JOB(double)
+INST_FUSED_JOB(float)
+INST_FUSED_JOB(cplx<double>)
+INST_FUSED_JOB(cplx<float>)
 
 size_t project_partial_elems(const Ctx& c) {
   if (c.pboff.empty()) return 0;
