@@ -110,6 +110,10 @@ typedef struct hcu_problem {
   int    precision;             /* hcu_precision                             */
   int    lowdin;                /* 1: Loewdin-orthonormalise Hubbard orbitals
                                    per atom (O^-1/2, O = Phi^H Phi dV)       */
+  int    hxc;                   /* 1: density-dependent Hamiltonian (Sec.
+                                   II.B): V = V_loc + V_H[rho] + V_x[rho],
+                                   the SCF mixes the density and D together
+                                   (nspin = 1 only); 0: fixed V_loc          */
 } hcu_problem;
 
 typedef struct hcu_scf_opts {
@@ -122,6 +126,10 @@ typedef struct hcu_scf_opts {
   double tol_f;                 /* ... and |F_n - F_{n-1}| / natom < tol_f   */
   int    fixed_iterations;      /* > 0: run exactly this many, no test       */
   int    verbose;               /* 1: one line per iteration on stderr       */
+  double kerker_k0;             /* hxc: Kerker wave number k0 (bohr^-1, >= 0)
+                                   of the density preconditioner             */
+  double tol_rho;               /* hxc: ... and sqrt(dV sum (rho_out -
+                                   rho_in)^2) / N_e < tol_rho (> 0)          */
 } hcu_scf_opts;
 
 typedef struct hcu_scf_report {
@@ -134,15 +142,20 @@ typedef struct hcu_scf_report {
   double seconds;               /* wall time of the SCF loop                 */
   double filter_seconds;        /* of which: filters + H Y of Rayleigh-Ritz  */
   double hx_columns;            /* number of single-column H applications    */
+  double residual_rho;          /* hxc: last density residual (else 0)       */
 } hcu_scf_report;
 
 typedef struct hcu_energies {
-  double F;                     /* e_band - dc + E_U - kT S                  */
+  double F;                     /* e_band - dc + E_U - kT S (+ e_hxc)        */
   double e_band;                /* g_s sum_k w_k sum_j f_j lambda_j          */
   double dc;                    /* sum Tr(M(D_in) D_out) over spins, atoms   */
   double E_U;                   /* sum_sigma sum_I U/2 Tr(D - D^2)           */
   double ts;                    /* kT S                                      */
   double mu;                    /* Fermi level                               */
+  double E_H;                   /* hxc: Hartree energy of rho_out (else 0)   */
+  double E_x;                   /* hxc: LDA exchange energy of rho_out       */
+  double e_hxc;                 /* hxc: -int rho_out (V_H + V_x)[rho_in] +
+                                   E_H + E_x, included in F                  */
 } hcu_energies;
 
 /* Accumulated device time per kernel family, recorded only while profiling
@@ -246,8 +259,9 @@ hcu_status hcu_set_start(hcu_ctx* ctx, int spin, int ik, const void* X0, const v
 
 /* Y = H[D] X for ncol states (device pointers, column-major, leading
  * dimension ld >= nd, context precision; X and Y must not overlap).
- * Includes kinetic stencil of order 2 n0 with Bloch wrap, V_loc, KB and
- * Hubbard terms (Sec. II.A potential; Sec. II.B implementation).
+ * Includes kinetic stencil of order 2 n0 with Bloch wrap, V_loc (with hxc:
+ * V_loc + V_H + V_x of the current input density), KB and Hubbard terms
+ * (Sec. II.A potential; Sec. II.B implementation).
  * Errors: HCU_INVALID_ARG (spin/ik out of range, ncol < 1 or > ns, ld < nd). */
 hcu_status hcu_apply_h(hcu_ctx* ctx, int spin, int ik, const void* X, void* Y,
                        int ncol, int64_t ld);
@@ -282,9 +296,24 @@ hcu_status hcu_rotate(hcu_ctx* ctx, const void* Y, const double* C, void* X, int
 
 /* Full SCF loop (Sec. II.B): per iteration, filter + Rayleigh-Ritz for every
  * (spin, k) (first iteration: first_passes), Fermi level, occupations, D_out,
- * E_U, free energy, Pulay mixing of D.  Errors: HCU_NOT_CONVERGED when
- * max_iter is reached without meeting the tolerances (results stay valid),
- * HCU_NOT_SPD, HCU_NAN. */
+ * E_U, free energy, Pulay mixing of D.
+ * With hxc the Hamiltonian depends on the input density rho_in as well:
+ *   -Delta_h V_H = 4 pi (rho_in - <rho_in>) with the kinetic term's
+ *   finite-difference Laplacian (solved exactly by FFT with the stencil's
+ *   symbol), V_x = -(3 rho_in / pi)^(1/3) (LDA exchange);
+ *   F = e_band - dc + E_U - kT S - int rho_out (V_H + V_x)[rho_in]
+ *       + E_H[rho_out] + E_x[rho_out];
+ * the mixing is one Pulay step on the density (history pulay_history <= 8)
+ * whose coefficients, fitted to the density residuals, mix D as well; the
+ * density's residual step is preconditioned with the Kerker operator
+ * (-Delta_h)(-Delta_h + k0^2)^-1 and the new density keeps N_e electrons.
+ * rho_in is uniform (N_e / Omega) after hcu_bind and carries over from one
+ * SCF to the next (and across hcu_move_atoms), like D_in.  Convergence then
+ * also needs the density residual below tol_rho.  The FFT plans are created
+ * in hcu_bind and allocate their own work areas.
+ * Errors: HCU_NOT_CONVERGED when max_iter is reached without meeting the
+ * tolerances (results stay valid), HCU_NOT_SPD, HCU_NAN, HCU_INVALID_ARG
+ * (bad options; with hxc also pulay_history > 8, kerker_k0 < 0, tol_rho <= 0). */
 hcu_status hcu_scf(hcu_ctx* ctx, const hcu_scf_opts* opts, hcu_scf_report* rep);
 
 /* Step-wise SCF for callers that drive the loop themselves.  hcu_scf_begin
@@ -300,6 +329,7 @@ typedef struct hcu_scf_step_info {
   double E_U;
   double residual;             /* |D_out - D_in|_F of this iteration        */
   double dF;                   /* |F - F_prev| / natom (inf on the first)   */
+  double residual_rho;         /* hxc: density residual (else 0)            */
 } hcu_scf_step_info;
 hcu_status hcu_scf_begin(hcu_ctx* ctx, const hcu_scf_opts* opts);
 hcu_status hcu_scf_step(hcu_ctx* ctx, hcu_scf_step_info* info);
@@ -368,13 +398,20 @@ hcu_status hcu_get_orbitals(hcu_ctx* ctx, int spin, int ik, void* dst, int on_de
 /* Density rho[sigma][nd] (host, double): total for nspin = 1, spin densities
  * for nspin = 2; rho = (2/nspin) sum_k w_k sum_j f_j |x_j|^2. */
 hcu_status hcu_get_density(hcu_ctx* ctx, double* rho);
+/* The local potential the next H application uses, host double [nd]:
+ * V_loc, or with hxc V_loc + V_H[rho_in] + V_x[rho_in] of the current input
+ * density rho_in (written to rho_in, host double [nd], when rho_in is not
+ * NULL).  Errors: HCU_NOT_BOUND, HCU_INVALID_ARG (NULL V; rho_in without
+ * hxc). */
+hcu_status hcu_get_potential(hcu_ctx* ctx, double* V, double* rho_in);
 
 /* ------------------------------------------------------------ save / resume
  * Snapshot of the SCF state in a caller-owned host buffer: input occupation
  * matrices and the Pulay history (Sec. II.B mixing), iteration counter and
  * convergence bookkeeping, filter bounds per (spin, k), last eigenvalues,
- * occupations and energies, and the orbital blocks.  A context of the same
- * problem (same shape, precision and real/complex type) that loads it
+ * occupations and energies, and the orbital blocks; with hxc also the
+ * input density and the density mixing window.  A context of the same
+ * problem (same shape, precision, real/complex type and hxc flag) that loads it
  * continues with hcu_scf_step exactly as the saved one would have.
  * Errors: HCU_NOT_BOUND, HCU_INVALID_ARG (buffer too small, foreign or
  * corrupt state, shape mismatch). */

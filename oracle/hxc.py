@@ -95,7 +95,9 @@ def kerker(r, L, n, n0, k0):
 
 def scf_hxc(cfg, max_iter=None, verbose=False):
     """Self-consistent loop with the density-dependent potential (nspin = 1).
-    Returns eigenvalues, occupations, mu, D, density, energies, iterations."""
+    Returns eigenvalues, occupations, mu, D, density, energies, iterations of
+    the last iteration; rho_next / V_next are the input density and potential
+    that its mixing step produced (absent once converged)."""
     assert cfg["nspin"] == 1, "the density-dependent model is spin-unpolarised"
     kpts = np.asarray(cfg["kpts"])
     kw = np.asarray(cfg["kw"])
@@ -190,6 +192,7 @@ def scf_hxc(cfg, max_iter=None, verbose=False):
         rho_in = rho_in + (cfg["nelec"] / omega - np.mean(rho_in))   # the step keeps N_e exactly
         D_in = vec_to_d(xd_bar + beta * fd_bar, D_in)
         V = veff(rho_in)
+        out["rho_next"], out["V_next"] = rho_in, V      # the input of the next iteration
         for ik in range(len(kpts)):
             H[ik] = Hamiltonian(cfg, kpts[ik], D_in[0], atoms_k[ik], V)
     out["converged"] = converged

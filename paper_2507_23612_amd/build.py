@@ -1,7 +1,7 @@
 """Build the HIP library libhcu.so for gfx950 (in-tree).
 
 Each .hip source is compiled to an object in parallel, then linked against
-rocSOLVER/rocBLAS.  Usage: python -m paper_2507_23612_amd.build
+rocSOLVER/rocBLAS and hipFFT.  Usage: python -m paper_2507_23612_amd.build
 """
 from __future__ import annotations
 
@@ -26,7 +26,7 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"),
 ]
 SOURCES = ["setup.hip", "stencil.hip", "nonlocal.hip", "proj.hip", "gemm.hip", "scf_kernels.hip", "mlp.hip", "state.hip",
-           "noalloc.hip", "forces.hip", "api.hip"]
+           "noalloc.hip", "forces.hip", "hxc.hip", "api.hip"]
 
 
 def _compile(src):
@@ -45,7 +45,7 @@ def build(verbose=False):
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
-           "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+           "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-lhipfft", "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

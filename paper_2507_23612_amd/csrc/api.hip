@@ -112,6 +112,17 @@ size_t layout(Ctx& c, char* base, bool assign = true) {
   b.take(c.d_fproj, es * 13 * (size_t)ns * c.nproj);
   b.take(c.d_fsum, sizeof(double) * 650 * (size_t)nh);
   b.take(c.d_focc, sizeof(double) * (size_t)nsk * ns);
+  if (c.hxc) {
+    const size_t nc = hxc_spectrum_elems(c);
+    b.take(c.d_Vloc, sizeof(double) * c.nd);
+    b.take(c.d_rho_in, sizeof(double) * c.nd);
+    b.take(c.d_hx, sizeof(double) * c.nd * kHxcWindow);
+    b.take(c.d_hf, sizeof(double) * c.nd * kHxcWindow);
+    b.take(c.d_hbar, sizeof(double) * c.nd * 2);
+    b.take(c.d_hspec, sizeof(double) * nc * 4);
+    b.take(c.d_hsym, sizeof(double) * (c.p.n[0] / 2 + 1 + c.p.n[1] + c.p.n[2]));
+    b.take(c.d_hpart, sizeof(double) * hxc_partial_elems());
+  }
   // ---- position dependent
   b.take(c.d_supp, sizeof(int) * c.supp.size());
   b.take(c.d_boff, sizeof(int64_t) * c.boff.size());
@@ -826,6 +837,9 @@ hcu_status check_kset(Ctx& c) {
 }
 
 template <typename T>
+hcu_status density_t(Ctx& c, double* rho);
+
+template <typename T>
 hcu_status occupations_t(Ctx& c) {
   if (check_kset(c) != HCU_OK) return HCU_INVALID_ARG;
   const int nsk = c.p.nspin * c.p.nk;
@@ -860,6 +874,13 @@ hcu_status occupations_t(Ctx& c) {
   c.en.E_U = sc[3];
   c.en.ts = sc[4];
   c.en.F = sc[5];
+  c.en.E_H = c.en.E_x = c.en.e_hxc = 0.0;
+  if (c.hxc) {
+    hcu_status s = density_t<T>(c, nullptr);
+    if (s == HCU_OK) s = hxc_energies(c);
+    if (s != HCU_OK) return s;
+    c.en.F += c.en.e_hxc;
+  }
   c.have_results = true;
   if (!std::isfinite(c.en.F)) return fail(c, HCU_NAN, "non-finite free energy");
   return HCU_OK;
@@ -940,6 +961,26 @@ struct Pulay {
     for (size_t i = 0; i < n; ++i) {
       double xb = x[i], fb = f[i];
       for (int j = 0; j < m; ++j) { xb -= dX[j][i] * g[j]; fb -= dF[j][i] * g[j]; }
+      out[i] = xb + beta * fb;
+    }
+    return out;
+  }
+  // The same update with coefficients g fitted elsewhere (the density's,
+  // with the density-dependent Hamiltonian): g[j] multiplies the j-th
+  // difference of consecutive window entries, oldest first.
+  std::vector<double> step_with(const std::vector<double>& x, const std::vector<double>& f,
+                                const std::vector<double>& g) {
+    xs.push_back(x);
+    fs.push_back(f);
+    if ((int)xs.size() > h + 1) { xs.erase(xs.begin()); fs.erase(fs.begin()); }
+    const int m = (int)xs.size() - 1;
+    std::vector<double> out(x.size());
+    for (size_t i = 0; i < x.size(); ++i) {
+      double xb = x[i], fb = f[i];
+      for (int j = 0; j < m && j < (int)g.size(); ++j) {
+        xb -= (xs[j + 1][i] - xs[j][i]) * g[j];
+        fb -= (fs[j + 1][i] - fs[j][i]) * g[j];
+      }
       out[i] = xb + beta * fb;
     }
     return out;
@@ -1081,11 +1122,17 @@ hcu_status scf_post(Ctx& c, hcu_scf_step_info* info) {
   res = std::sqrt(res);
   const int natom = std::max(c.p.natom, 1);
   const double dF = c.scf_have_old ? std::fabs(c.en.F - c.scf_F_old) / natom : INFINITY;
-  if (o.verbose)
-    std::fprintf(stderr, "[hcu scf] it=%d F=%.12f E_U=%.6e res=%.3e dF=%.3e\n", c.scf_iter, c.en.F, c.en.E_U, res, dF);
+  const double res_rho = c.hxc ? c.hxc_res : 0.0;
+  if (o.verbose) {
+    if (c.hxc)
+      std::fprintf(stderr, "[hcu scf] it=%d F=%.12f E_U=%.6e res=%.3e res_rho=%.3e dF=%.3e\n", c.scf_iter, c.en.F,
+                   c.en.E_U, res, res_rho, dF);
+    else
+      std::fprintf(stderr, "[hcu scf] it=%d F=%.12f E_U=%.6e res=%.3e dF=%.3e\n", c.scf_iter, c.en.F, c.en.E_U, res, dF);
+  }
   c.scf_F_old = c.en.F;
   c.scf_have_old = true;
-  const bool conv = res < o.tol_d && dF < o.tol_f;
+  const bool conv = res < o.tol_d && dF < o.tol_f && (!c.hxc || res_rho < o.tol_rho);
   if (info) {
     info->iteration = c.scf_iter;
     info->converged = conv ? 1 : 0;
@@ -1093,13 +1140,23 @@ hcu_status scf_post(Ctx& c, hcu_scf_step_info* info) {
     info->E_U = c.en.E_U;
     info->residual = res;
     info->dF = dF;
+    info->residual_rho = res_rho;
   }
   ++c.scf_iter;
   if (!conv) {
     Pulay mix{o.pulay_history, o.pulay_beta, c.mix_x, c.mix_f};
     std::vector<double> x = d_to_vec(c, c.D_in), xo = d_to_vec(c, c.D_out), f(x.size());
     for (size_t i = 0; i < x.size(); ++i) f[i] = xo[i] - x[i];
-    std::vector<double> xn = mix.step(x, f);
+    std::vector<double> xn;
+    if (c.hxc) {
+      // one Pulay step on the density; its coefficients mix D too
+      std::vector<double> gamma;
+      s = hxc_mix(c, o.pulay_history, o.pulay_beta, o.kerker_k0, gamma);
+      if (s != HCU_OK) return s;
+      xn = mix.step_with(x, f, gamma);
+    } else {
+      xn = mix.step(x, f);
+    }
     vec_to_d(c, xn, c.D_in);
     s = upload_coupling(c);
     if (s != HCU_OK) return s;
@@ -1153,6 +1210,8 @@ hcu_status hcu_create(const hcu_problem* p, hcu_ctx** out) {
   if (!(p->kT > 0)) return bad("kT must be positive");
   if (p->degree < 1) return bad("degree must be >= 1");
   if (p->precision != HCU_FP64 && p->precision != HCU_MIXED) return bad("unknown precision");
+  if (p->hxc != 0 && p->hxc != 1) return bad("hxc must be 0 or 1");
+  if (p->hxc && p->nspin != 1) return bad("the density-dependent Hamiltonian is spin-unpolarised (nspin = 1)");
   const double gs = p->nspin == 1 ? 2.0 : 1.0;
   if (!(p->nelec > 0) || p->nelec >= gs * p->ns * p->nspin) return bad("nelec must be in (0, states available)");
   c->kpts.assign(p->kpts, p->kpts + 3 * p->nk);
@@ -1179,6 +1238,7 @@ hcu_status hcu_create(const hcu_problem* p, hcu_ctx** out) {
   for (int a = 0; a < 3; ++a) c->h[a] = p->L[a] / p->n[a];
   c->dv = c->h[0] * c->h[1] * c->h[2];
   c->mixed = p->precision == HCU_MIXED;
+  c->hxc = p->hxc == 1;
   c->any_complex = false;
   for (int k = 0; k < p->nk; ++k)
     if (k_complex(*c, k)) c->any_complex = true;
@@ -1245,6 +1305,7 @@ void hcu_destroy(hcu_ctx* ctx) {
   for (hipStream_t st : ctx->rr_streams) (void)hipStreamDestroy(st);
   for (hipEvent_t e : ctx->rr_events) (void)hipEventDestroy(e);
   if (ctx->h_info_pinned) (void)hipHostFree(ctx->h_info_pinned);
+  hxc_destroy(*ctx);
   delete ctx;
 }
 
@@ -1370,6 +1431,8 @@ hcu_status upload_structure(Ctx& c) {
   const std::vector<int2> tiles = gram_tiles(c.p.ns, c.any_complex);
   HCU_HIP(hipMemcpyAsync(c.d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice, c.stream));
   hcu_status s = device_tables(c);
+  if (s != HCU_OK) return s;
+  s = hxc_after_structure(c);   // V_loc + V_H + V_x of the input density
   if (s != HCU_OK) return s;
   HCU_HIP(hipStreamSynchronize(c.stream));   // lists, hb, tiles are released on return
   return HCU_OK;
@@ -1568,6 +1631,10 @@ hcu_status hcu_scf_begin(hcu_ctx* ctx, const hcu_scf_opts* o) {
   if (!o) return fail(c, HCU_INVALID_ARG, "null options");
   if (o->max_iter < 1 || o->first_passes < 1 || o->lanczos_steps < 1 || o->pulay_history < 1)
     return fail(c, HCU_INVALID_ARG, "bad SCF options");
+  if (c.hxc && (o->pulay_history + 1 > kHxcWindow || !(o->kerker_k0 >= 0) || !std::isfinite(o->kerker_k0) ||
+                !(o->tol_rho > 0)))
+    return fail(c, HCU_INVALID_ARG, "bad SCF options for the density-dependent Hamiltonian (pulay_history <= 8, "
+                                    "kerker_k0 >= 0, tol_rho > 0)");
   s = check_kset(c);
   if (s != HCU_OK) return s;
   c.scf_opts = *o;
@@ -1575,6 +1642,7 @@ hcu_status hcu_scf_begin(hcu_ctx* ctx, const hcu_scf_opts* o) {
   c.scf_have_old = false;
   c.mix_x.clear();
   c.mix_f.clear();
+  c.hxc_slots.clear();
   c.scf_filter_ms = 0;
   c.scf_hx_cols = 0;
   for (int sp = 0; sp < c.p.nspin; ++sp)
@@ -1628,6 +1696,7 @@ hcu_status hcu_scf(hcu_ctx* ctx, const hcu_scf_opts* o, hcu_scf_report* rep) {
     s = hcu_scf_step(ctx, &si);
     if (s != HCU_OK) return s;
     rep->residual = si.residual;
+    rep->residual_rho = si.residual_rho;
     if (o->fixed_iterations > 0) {
       if (it + 1 >= o->fixed_iterations) { final_status = HCU_OK; ++it; break; }
     } else if (si.converged) {
@@ -1708,6 +1777,18 @@ hcu_status hcu_get_density(hcu_ctx* ctx, double* rho) {
   if (!rho) return fail(c, HCU_INVALID_ARG, "null rho");
   if (!c.have_results) return fail(c, HCU_INVALID_ARG, "no occupations yet");
   return DISPATCH(c, density_t, c, rho);
+}
+
+hcu_status hcu_get_potential(hcu_ctx* ctx, double* V, double* rho_in) {
+  hcu_status s = check_ctx(ctx);
+  if (s != HCU_OK) return s;
+  Ctx& c = *ctx;
+  if (!V) return fail(c, HCU_INVALID_ARG, "null V");
+  if (rho_in && !c.hxc) return fail(c, HCU_INVALID_ARG, "no input density without the density-dependent Hamiltonian");
+  HCU_HIP(hipMemcpyAsync(V, c.d_V, sizeof(double) * c.nd, hipMemcpyDeviceToHost, c.stream));
+  if (rho_in) HCU_HIP(hipMemcpyAsync(rho_in, c.d_rho_in, sizeof(double) * c.nd, hipMemcpyDeviceToHost, c.stream));
+  HCU_HIP(hipStreamSynchronize(c.stream));
+  return HCU_OK;
 }
 
 }  // extern "C"
@@ -1812,6 +1893,7 @@ hcu_status hcu_batch_scf(hcu_batch* b, const hcu_scf_opts* o, hcu_scf_report* re
       if (s != HCU_OK) return batch_fail(b, s, c.err);
       reps[i].iterations = it + 1;
       reps[i].residual = si.residual;
+      reps[i].residual_rho = si.residual_rho;
       reps[i].F = c.en.F;
       reps[i].E_U = c.en.E_U;
       reps[i].e_band = c.en.e_band;

@@ -63,6 +63,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // each XCD receives a contiguous range of logical indices, so neighbouring
 // logical workgroups (that share halo rows or table tiles) share an L2.
 constexpr int kNumXcd = 8;
+constexpr int kHxcWindow = 9;   // density mixing window: Pulay history of at most 8
 __device__ inline unsigned xcd_linear() {
   const unsigned nwg = gridDim.x * gridDim.y * gridDim.z;
   const unsigned w = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
@@ -230,6 +231,20 @@ struct Ctx {
   std::vector<double> D_out;
   hcu_energies en{};
   bool have_results = false;
+  // density-dependent Hamiltonian (problem flag hxc): d_V holds V_loc + V_H + V_x
+  bool hxc = false;
+  bool hxc_have_rho = false;         // d_rho_in holds an input density
+  double* d_Vloc = nullptr;          // V_loc alone
+  double* d_rho_in = nullptr;        // input density of the current iteration
+  double* d_hx = nullptr;            // mixing window: input densities [kHxcWindow][nd]
+  double* d_hf = nullptr;            // mixing window: residuals [kHxcWindow][nd]
+  double* d_hbar = nullptr;          // two grid vectors of the mixing step
+  double* d_hspec = nullptr;         // two half spectra [2][n3][n2][n1/2+1] complex
+  double* d_hsym = nullptr;          // -Delta_h symbol per axis [n1/2+1 | n2 | n3]
+  double* d_hpart = nullptr;         // reduction partials
+  std::vector<int> hxc_slots;        // window slots in use, oldest first
+  double hxc_res = 0;                // density residual of the last energies
+  void* hxc_plan[2] = {nullptr, nullptr};   // FFT plans: real to complex, complex to real
   // AIMD history: positions and converged D of the last geometries, most recent first
   std::vector<std::vector<double>> aimd_pos, aimd_D;
   std::string err;
@@ -331,6 +346,16 @@ inline bool k_complex(const Ctx& c, int ik) {
 hcu_status build_structure(Ctx& c);          // host: supports, blocks, csr
 hcu_status device_tables(Ctx& c);            // device: V_loc, csc/csr values, Loewdin
 void fill_stencil_coef(const Ctx& c, int ik, StencilCoef& sc);
+
+// hxc.hip: the density-dependent potential and the mixing of the density
+size_t hxc_spectrum_elems(const Ctx& c);
+size_t hxc_partial_elems();
+hcu_status hxc_after_structure(Ctx& c);     // symbol tables, FFT plans, potential
+hcu_status hxc_reset_density(Ctx& c);       // uniform rho_in, empty window, potential
+hcu_status hxc_refresh_potential(Ctx& c);   // V from rho_in
+hcu_status hxc_energies(Ctx& c);            // of the output density in d_rho
+hcu_status hxc_mix(Ctx& c, int hist, double beta, double k0, std::vector<double>& gamma);
+void hxc_destroy(Ctx& c);
 
 // stencil.hip: out = alpha*(H_loc y - c y) - beta*yprev
 template <typename T>

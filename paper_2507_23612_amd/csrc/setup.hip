@@ -625,7 +625,10 @@ hcu_status device_tables(Ctx& c) {
   }
   AtomV* d_av = (AtomV*)c.d_red;
   HCU_HIP(hipMemcpyAsync(d_av, av.data(), av.size() * sizeof(AtomV), hipMemcpyHostToDevice, st));
-  k_vloc<<<(c.nd + 255) / 256, 256, 0, st>>>(c.d_V, c.mixed ? c.d_Vf : nullptr, d_av, c.p.natom, c.p.n[0],
+  // with the density-dependent Hamiltonian V_loc is kept apart; the total
+  // potential is assembled from it afterwards
+  k_vloc<<<(c.nd + 255) / 256, 256, 0, st>>>(c.hxc ? c.d_Vloc : c.d_V, (c.mixed && !c.hxc) ? c.d_Vf : nullptr, d_av,
+                                             c.p.natom, c.p.n[0],
                                              c.p.n[1], c.p.n[2], c.h[0], c.h[1], c.h[2], c.p.L[0], c.p.L[1],
                                              c.p.L[2]);
   HCU_HIP(hipGetLastError());

@@ -2,7 +2,8 @@
 // interruption): input occupation matrices and the mixing history, the
 // iteration counter and convergence bookkeeping, the filter bounds of every
 // (spin, k) block, the last eigenvalues/occupations/energies and the
-// orbital blocks themselves.  A restored context continues the SCF exactly
+// orbital blocks themselves; with the density-dependent Hamiltonian also
+// the input density and the density mixing window.  A restored context continues the SCF exactly
 // as the saved one would have (the next step filters the restored blocks
 // with the restored bounds and mixes with the restored history).
 #include "common.h"
@@ -13,7 +14,7 @@ using namespace hcu;
 
 namespace {
 constexpr char kMagic[8] = {'H', 'C', 'U', 'S', 'T', 'A', 'T', 'E'};
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 
 struct StateHeader {
   char magic[8];
@@ -21,6 +22,7 @@ struct StateHeader {
   int32_t nd, ns, nspin, nk, nhub, mixed, complex_, elem;
   int32_t scf_iter, scf_ready, have_old, have_results;
   int32_t n_hist, vec_len;
+  int32_t hxc, n_rho_hist;
   double F_old;
   hcu_scf_opts opts;
   hcu_energies en;
@@ -32,8 +34,9 @@ size_t state_bytes(const Ctx& c, size_t* hist_len) {
   const size_t vl = nh ? c.mix_x[0].size() : 0;
   if (hist_len) *hist_len = vl;
   const size_t es = (c.mixed ? 4 : 8) * (c.any_complex ? 2 : 1);
+  const size_t hx = c.hxc ? (size_t)c.nd * (2 + 2 * c.hxc_slots.size()) + (c.mixed ? (c.nd + 1) / 2 : 0) : 0;
   return sizeof(StateHeader) + sizeof(double) * (2 * c.D_in.size() + c.bounds.size() + 2 * (size_t)nsk * c.p.ns +
-                                                 2 * nh * vl) +
+                                                 2 * nh * vl + hx) +
          (size_t)nsk * es * c.nd * c.p.ns;
 }
 
@@ -85,6 +88,8 @@ hcu_status hcu_save_state(hcu_ctx* ctx, void* host, size_t bytes) {
   h.have_results = c.have_results ? 1 : 0;
   h.n_hist = (int)c.mix_x.size();
   h.vec_len = (int)vl;
+  h.hxc = c.hxc ? 1 : 0;
+  h.n_rho_hist = c.hxc ? (int)c.hxc_slots.size() : 0;
   h.F_old = c.scf_F_old;
   h.opts = c.scf_opts;
   h.en = c.en;
@@ -106,6 +111,24 @@ hcu_status hcu_save_state(hcu_ctx* ctx, void* host, size_t bytes) {
   for (int sk = 0; sk < nsk; ++sk) {
     HCU_HIP(hipMemcpyAsync(p, c.d_X[sk], blk, hipMemcpyDeviceToHost, c.stream));
     p += blk;
+  }
+  if (c.hxc) {
+    // the potential as it stands (recomputing it from rho_in would round differently)
+    const size_t vb = sizeof(double) * c.nd;
+    HCU_HIP(hipMemcpyAsync(p, c.d_V, vb, hipMemcpyDeviceToHost, c.stream));
+    p += vb;
+    if (c.mixed) {
+      HCU_HIP(hipMemcpyAsync(p, c.d_Vf, sizeof(float) * c.nd, hipMemcpyDeviceToHost, c.stream));
+      p += sizeof(double) * ((c.nd + 1) / 2);
+    }
+    HCU_HIP(hipMemcpyAsync(p, c.d_rho_in, vb, hipMemcpyDeviceToHost, c.stream));
+    p += vb;
+    for (int slot : c.hxc_slots) {
+      HCU_HIP(hipMemcpyAsync(p, c.d_hx + (size_t)slot * c.nd, vb, hipMemcpyDeviceToHost, c.stream));
+      p += vb;
+      HCU_HIP(hipMemcpyAsync(p, c.d_hf + (size_t)slot * c.nd, vb, hipMemcpyDeviceToHost, c.stream));
+      p += vb;
+    }
   }
   HCU_HIP(hipStreamSynchronize(c.stream));
   return HCU_OK;
@@ -132,13 +155,21 @@ hcu_status hcu_load_state(hcu_ctx* ctx, const void* host, size_t bytes) {
     c.err = "saved state belongs to a problem of another shape or precision";
     return HCU_INVALID_ARG;
   }
-  if (h.n_hist < 0 || h.vec_len < 0 || h.n_hist > 1024) {
+  if (h.hxc != (c.hxc ? 1 : 0)) {
+    c.err = "saved state belongs to a problem with another Hamiltonian (hxc flag)";
+    return HCU_INVALID_ARG;
+  }
+  if (h.n_hist < 0 || h.vec_len < 0 || h.n_hist > 1024 || h.n_rho_hist < 0 || h.n_rho_hist > kHxcWindow ||
+      (!c.hxc && h.n_rho_hist != 0)) {
     c.err = "corrupt saved state";
     return HCU_INVALID_ARG;
   }
   const size_t need = sizeof(StateHeader) +
                       sizeof(double) * (2 * c.D_in.size() + c.bounds.size() + 2 * (size_t)nsk * c.p.ns +
-                                        2 * (size_t)h.n_hist * h.vec_len) +
+                                        2 * (size_t)h.n_hist * h.vec_len +
+                                        (c.hxc ? (size_t)c.nd * (2 + 2 * (size_t)h.n_rho_hist) +
+                                                     (c.mixed ? (c.nd + 1) / 2 : 0)
+                                               : 0)) +
                       (size_t)nsk * h.elem * c.nd * c.p.ns;
   if (bytes < need) {
     c.err = "saved state truncated";
@@ -161,6 +192,26 @@ hcu_status hcu_load_state(hcu_ctx* ctx, const void* host, size_t bytes) {
   for (int sk = 0; sk < nsk; ++sk) {
     HCU_HIP(hipMemcpyAsync(c.d_X[sk], p, blk, hipMemcpyHostToDevice, c.stream));
     p += blk;
+  }
+  if (c.hxc) {
+    const size_t vb = sizeof(double) * c.nd;
+    HCU_HIP(hipMemcpyAsync(c.d_V, p, vb, hipMemcpyHostToDevice, c.stream));
+    p += vb;
+    if (c.mixed) {
+      HCU_HIP(hipMemcpyAsync(c.d_Vf, p, sizeof(float) * c.nd, hipMemcpyHostToDevice, c.stream));
+      p += sizeof(double) * ((c.nd + 1) / 2);
+    }
+    HCU_HIP(hipMemcpyAsync(c.d_rho_in, p, vb, hipMemcpyHostToDevice, c.stream));
+    p += vb;
+    c.hxc_slots.clear();
+    for (int i = 0; i < h.n_rho_hist; ++i) {
+      HCU_HIP(hipMemcpyAsync(c.d_hx + (size_t)i * c.nd, p, vb, hipMemcpyHostToDevice, c.stream));
+      p += vb;
+      HCU_HIP(hipMemcpyAsync(c.d_hf + (size_t)i * c.nd, p, vb, hipMemcpyHostToDevice, c.stream));
+      p += vb;
+      c.hxc_slots.push_back(i);
+    }
+    c.hxc_have_rho = true;
   }
   HCU_HIP(hipMemcpyAsync(c.d_lam, c.lam.data(), sizeof(double) * c.lam.size(), hipMemcpyHostToDevice, c.stream));
   HCU_HIP(hipMemcpyAsync(c.d_occ, c.occ.data(), sizeof(double) * c.occ.size(), hipMemcpyHostToDevice, c.stream));

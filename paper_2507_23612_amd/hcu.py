@@ -33,24 +33,25 @@ class hcu_problem(C.Structure):
                 ("kpts", C.POINTER(C.c_double)), ("kw", C.POINTER(C.c_double)), ("natom", C.c_int),
                 ("atom_species", C.POINTER(C.c_int)), ("pos", C.POINTER(C.c_double)), ("nspecies", C.c_int),
                 ("species", C.POINTER(hcu_species)), ("ns", C.c_int), ("nelec", C.c_double), ("kT", C.c_double),
-                ("degree", C.c_int), ("precision", C.c_int), ("lowdin", C.c_int)]
+                ("degree", C.c_int), ("precision", C.c_int), ("lowdin", C.c_int), ("hxc", C.c_int)]
 
 
 class hcu_scf_opts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("first_passes", C.c_int), ("lanczos_steps", C.c_int),
                 ("pulay_history", C.c_int), ("pulay_beta", C.c_double), ("tol_d", C.c_double),
-                ("tol_f", C.c_double), ("fixed_iterations", C.c_int), ("verbose", C.c_int)]
+                ("tol_f", C.c_double), ("fixed_iterations", C.c_int), ("verbose", C.c_int),
+                ("kerker_k0", C.c_double), ("tol_rho", C.c_double)]
 
 
 class hcu_scf_report(C.Structure):
     _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("F", C.c_double), ("E_U", C.c_double),
                 ("e_band", C.c_double), ("residual", C.c_double), ("seconds", C.c_double),
-                ("filter_seconds", C.c_double), ("hx_columns", C.c_double)]
+                ("filter_seconds", C.c_double), ("hx_columns", C.c_double), ("residual_rho", C.c_double)]
 
 
 class hcu_scf_step_info(C.Structure):
     _fields_ = [("iteration", C.c_int), ("converged", C.c_int), ("F", C.c_double), ("E_U", C.c_double),
-                ("residual", C.c_double), ("dF", C.c_double)]
+                ("residual", C.c_double), ("dF", C.c_double), ("residual_rho", C.c_double)]
 
 
 class hcu_sizes(C.Structure):
@@ -61,7 +62,8 @@ class hcu_sizes(C.Structure):
 
 class hcu_energies(C.Structure):
     _fields_ = [("F", C.c_double), ("e_band", C.c_double), ("dc", C.c_double), ("E_U", C.c_double),
-                ("ts", C.c_double), ("mu", C.c_double)]
+                ("ts", C.c_double), ("mu", C.c_double), ("E_H", C.c_double), ("E_x", C.c_double),
+                ("e_hxc", C.c_double)]
 
 
 class hcu_kernel_times(C.Structure):
@@ -123,6 +125,7 @@ def load_library(path=LIB_PATH):
         "hcu_get_energies": (C.c_int, [P, C.POINTER(hcu_energies)]),
         "hcu_get_orbitals": (C.c_int, [P, C.c_int, C.c_int, P, C.c_int]),
         "hcu_get_density": (C.c_int, [P, C.POINTER(C.c_double)]),
+        "hcu_get_potential": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "hcu_batch_create": (C.c_int, [C.POINTER(P), C.c_int, C.POINTER(P)]),
         "hcu_batch_destroy": (None, [P]),
         "hcu_batch_last_error": (C.c_char_p, [P]),
@@ -220,6 +223,7 @@ class Problem:
         prec = precision or cfg.get("precision", "fp64")
         p.precision = HCU_MIXED if prec == "mixed" else HCU_FP64
         p.lowdin = 1 if cfg.get("lowdin", True) else 0
+        p.hxc = 1 if cfg.get("hxc", False) else 0
         self.p = p
 
 
@@ -356,9 +360,9 @@ class HcuContext:
         self._check(self.lib.hcu_update_occupations(self.h))
 
     def scf(self, max_iter=100, first_passes=4, lanczos_steps=10, pulay_history=7, pulay_beta=0.3, tol_d=1e-7,
-            tol_f=1e-7, fixed_iterations=0, verbose=False, raise_on_nonconv=True):
+            tol_f=1e-7, fixed_iterations=0, verbose=False, raise_on_nonconv=True, kerker_k0=0.8, tol_rho=1e-6):
         o = hcu_scf_opts(max_iter, first_passes, lanczos_steps, pulay_history, pulay_beta, tol_d, tol_f,
-                         fixed_iterations, 1 if verbose else 0)
+                         fixed_iterations, 1 if verbose else 0, kerker_k0, tol_rho)
         r = hcu_scf_report()
         st = self.lib.hcu_scf(self.h, C.byref(o), C.byref(r))
         if st != HCU_OK and not (st == HCU_NOT_CONVERGED and not raise_on_nonconv):
@@ -423,9 +427,9 @@ class HcuContext:
         return {k: getattr(t, k) for k, _ in hcu_kernel_times._fields_}
 
     def scf_begin(self, max_iter=100, first_passes=4, lanczos_steps=10, pulay_history=7, pulay_beta=0.3,
-                  tol_d=1e-7, tol_f=1e-7, verbose=False):
+                  tol_d=1e-7, tol_f=1e-7, verbose=False, kerker_k0=0.8, tol_rho=1e-6):
         self._scf_opts = hcu_scf_opts(max_iter, first_passes, lanczos_steps, pulay_history, pulay_beta, tol_d,
-                                      tol_f, 0, 1 if verbose else 0)
+                                      tol_f, 0, 1 if verbose else 0, kerker_k0, tol_rho)
         self._check(self.lib.hcu_scf_begin(self.h, C.byref(self._scf_opts)))
 
     def scf_step(self):
@@ -452,6 +456,14 @@ class HcuContext:
         e = hcu_energies()
         self._check(self.lib.hcu_get_energies(self.h, C.byref(e)))
         return {k: getattr(e, k) for k, _ in hcu_energies._fields_}
+
+    def get_potential(self):
+        """(V, rho_in): the local potential of the next H application and,
+        with the density-dependent Hamiltonian, the input density (else None)."""
+        V = np.zeros(self.nd)
+        rho = np.zeros(self.nd) if self.prob.p.hxc else None
+        self._check(self.lib.hcu_get_potential(self.h, _dptr(V), _dptr(rho) if rho is not None else None))
+        return V, rho
 
     def get_orbitals(self, spin=0, ik=0):
         X = self.torch.empty((self.ns, self.nd), dtype=self.dtype, device=self.device)
@@ -532,9 +544,9 @@ class HcuBatch:
         self._check(self.lib.hcu_batch_chfsi_pass(self.h))
 
     def scf(self, max_iter=100, first_passes=4, lanczos_steps=10, pulay_history=7, pulay_beta=0.3, tol_d=1e-7,
-            tol_f=1e-7, fixed_iterations=0, verbose=False, raise_on_nonconv=True):
+            tol_f=1e-7, fixed_iterations=0, verbose=False, raise_on_nonconv=True, kerker_k0=0.8, tol_rho=1e-6):
         o = hcu_scf_opts(max_iter, first_passes, lanczos_steps, pulay_history, pulay_beta, tol_d, tol_f,
-                         fixed_iterations, 1 if verbose else 0)
+                         fixed_iterations, 1 if verbose else 0, kerker_k0, tol_rho)
         reps = (hcu_scf_report * len(self.ctxs))()
         st = self.lib.hcu_batch_scf(self.h, C.byref(o), reps)
         if st != HCU_OK and not (st == HCU_NOT_CONVERGED and not raise_on_nonconv):

@@ -45,6 +45,8 @@ def test_create_validates_on_host():
     cases.append(bad)
     bad = dict(cfg); bad["ns"] = 4      # 4 states cannot hold 16 electrons
     cases.append(bad)
+    bad = workloads.with_kpoints(cfg); bad["hxc"] = True   # the density-dependent model is unpolarised
+    cases.append(bad)
     for b in cases:
         prob = hcu.Problem(b)
         h = ctypes.c_void_p()
@@ -63,6 +65,17 @@ def test_create_validates_on_host():
     assert lib.hcu_state_size(h, ctypes.byref(n)) == hcu.HCU_NOT_BOUND
     assert lib.hcu_save_state(h, None, 0) == hcu.HCU_INVALID_ARG
     assert lib.hcu_descriptor(h, None, None) == hcu.HCU_INVALID_ARG
+    assert lib.hcu_get_potential(h, None, None) == hcu.HCU_NOT_BOUND
+    lib.hcu_destroy(h)
+    # the density-dependent Hamiltonian adds its grid vectors and spectra
+    hx = dict(cfg); hx["hxc"] = True
+    prob = hcu.Problem(hx)
+    h = ctypes.c_void_p()
+    assert lib.hcu_create(ctypes.byref(prob.p), ctypes.byref(h)) == hcu.HCU_OK
+    m = ctypes.c_size_t()
+    assert lib.hcu_workspace_size(h, ctypes.byref(m)) == hcu.HCU_OK
+    nd = int(np.prod(cfg["n"]))
+    assert m.value >= n.value + 8 * nd * 22
     lib.hcu_destroy(h)
 
 

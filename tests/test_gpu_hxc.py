@@ -1,0 +1,189 @@
+"""Density-dependent Hamiltonian and density + D mixing through the C ABI
+against the oracle (Sec. II.B): Hartree potential by FFT with the stencil's
+symbol, LDA exchange, Kerker-preconditioned Pulay on the density whose
+coefficients also mix D.
+
+Both sides start from the same seeded blocks, the isolated-atom D and the
+uniform density, and take the same algorithmic steps, so FP64 iterations
+agree to rounding: first iterations to 1e-9 relative (potential, density),
+converged SCF to 1e-8 Ha/atom in F and 1e-8 Ha in the eigenvalues.
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _cfg(name, kind=None):
+    cfg = workloads.make_config(name)
+    cfg["hxc"] = True
+    if kind == "kpair":
+        k = np.array([0.18, -0.18, 0.28])
+        cfg["kpts"] = np.array([k, -k])
+        cfg["kw"] = np.array([0.5, 0.5])
+    return cfg
+
+
+def _opts(cfg):
+    return dict(first_passes=cfg["first_passes"], lanczos_steps=cfg["lanczos_steps"],
+                pulay_history=cfg["pulay_history"], pulay_beta=cfg["pulay_beta"], tol_d=cfg["scf_tol_d"],
+                tol_f=cfg["scf_tol_f"], kerker_k0=0.8, tol_rho=1e-6)
+
+
+def _ctx(cfg, precision=None):
+    from paper_2507_23612_amd import hcu
+    ctx = hcu.HcuContext(cfg, precision)
+    ctx.set_hubbard_occupation(hcu.initial_occupation(ctx, cfg))
+    for ik in range(len(cfg["kw"])):
+        X0, v0 = hcu.start_inputs(ctx, cfg, 0, ik)
+        ctx.set_start(0, ik, X0, v0)
+    return ctx
+
+
+def test_potential_at_bind_is_uniform_density():
+    _torch()
+    from oracle import hxc
+    from oracle.atoms import local_potential
+    cfg = _cfg("tiny")
+    print("[gpu] hxc potential at bind", flush=True)
+    ctx = _ctx(cfg)
+    V, rho = ctx.get_potential()
+    ctx.close()
+    omega = float(np.prod(cfg["L"]))
+    np.testing.assert_allclose(rho, cfg["nelec"] / omega, rtol=1e-15)
+    Vo = local_potential(cfg) + hxc.exchange_potential(np.full(rho.size, cfg["nelec"] / omega))
+    assert np.max(np.abs(V - Vo)) < 1e-12 * np.max(np.abs(Vo))
+
+
+@pytest.mark.parametrize("iters", [1, 3])
+def test_first_iterations_match_oracle(iters):
+    """After 1 iteration (Kerker step only) and 3 (Pulay with two
+    differences): energies of the last iteration and the mixed input density
+    and potential of the next."""
+    _torch()
+    from oracle import hxc
+    cfg = _cfg("tiny")
+    print(f"[gpu] hxc first {iters} iterations tiny", flush=True)
+    ctx = _ctx(cfg)
+    ctx.scf_begin(max_iter=iters, **_opts(cfg))
+    for _ in range(iters):
+        info = ctx.scf_step()
+    e = ctx.get_energies()
+    lam = ctx.get_eigenvalues()
+    V, rho_in = ctx.get_potential()
+    rho_out = ctx.get_density()[0]
+    ctx.close()
+    ref = hxc.scf_hxc(cfg, max_iter=iters)
+    natom = len(cfg["atom_species"])
+    print(f"[gpu] F gpu {e['F']:.14f} oracle {ref['F']:.14f}; E_H {e['E_H']:.10f} {ref['E_H']:.10f}; "
+          f"E_x {e['E_x']:.10f} {ref['E_x']:.10f}; res_rho {info['residual_rho']:.3e}", flush=True)
+    assert abs(e["F"] - ref["F"]) / natom < 1e-10
+    assert abs(e["E_H"] - ref["E_H"]) < 1e-10 * max(1.0, abs(ref["E_H"]))
+    assert abs(e["E_x"] - ref["E_x"]) < 1e-10 * abs(ref["E_x"])
+    assert abs(e["e_hxc"] - ref["e_hxc"]) < 1e-10 * max(1.0, abs(ref["e_hxc"]))
+    np.testing.assert_allclose(lam[0], ref["eigs"][0], atol=1e-10)
+    assert np.max(np.abs(rho_out - ref["rho"])) < 1e-10 * np.max(ref["rho"])
+    assert np.max(np.abs(rho_in - ref["rho_next"])) < 1e-9 * np.max(ref["rho_next"])
+    assert np.max(np.abs(V - ref["V_next"])) < 1e-9 * np.max(np.abs(ref["V_next"]))
+    dv = float(np.prod(np.asarray(cfg["L"]) / np.asarray(cfg["n"])))
+    assert abs(rho_in.sum() * dv - cfg["nelec"]) < 1e-10
+
+
+@pytest.mark.parametrize("name,kind", [("tiny", None), ("tiny", "kpair"), ("c1", None)])
+def test_scf_matches_oracle(name, kind):
+    _torch()
+    from oracle import hxc
+    cfg = _cfg(name, kind)
+    print(f"[gpu] hxc SCF {name} {kind}", flush=True)
+    ctx = _ctx(cfg)
+    rep = ctx.scf(verbose=True, **_opts(cfg))
+    e = ctx.get_energies()
+    lam = ctx.get_eigenvalues()
+    Dg = ctx.get_hubbard_occupation()[0]
+    rho = ctx.get_density()[0]
+    V, _ = ctx.get_potential()
+    ctx.close()
+    ref = hxc.scf_hxc(cfg)
+    natom = len(cfg["atom_species"])
+    print(f"[gpu] hxc {name} {kind}: F gpu {e['F']:.12f} oracle {ref['F']:.12f}, iterations {rep['iterations']} "
+          f"vs {ref['iterations']}, res_rho {rep['residual_rho']:.2e}", flush=True)
+    assert rep["converged"] and ref["converged"]
+    assert abs(e["F"] - ref["F"]) / natom < 1e-8
+    assert abs(e["E_H"] - ref["E_H"]) < 1e-7 and abs(e["E_x"] - ref["E_x"]) < 1e-7
+    nocc = int(cfg["nelec"] / 2)
+    np.testing.assert_allclose(lam[0][:, :nocc + 4], ref["eigs"][0][:, :nocc + 4], atol=1e-8)
+    for h in range(len(Dg)):
+        np.testing.assert_allclose(Dg[h], np.real(ref["D"][0][h]), atol=1e-6)
+    np.testing.assert_allclose(rho, ref["rho"], atol=1e-6 * ref["rho"].max())
+    np.testing.assert_allclose(V, ref["V"], atol=1e-6 * np.abs(ref["V"]).max())
+
+
+def test_scf_mixed_c1_energy_error():
+    """FP32 blocks (the Hartree solve, exchange and mixing stay FP64): free
+    energy within 1e-5 Ha/atom of the oracle's FP64 SCF."""
+    _torch()
+    from oracle import hxc
+    cfg = _cfg("c1")
+    print("[gpu] hxc SCF c1 mixed", flush=True)
+    ctx = _ctx(cfg, "mixed")
+    o = _opts(cfg)
+    o.update(tol_d=1e-5, tol_f=1e-6, tol_rho=1e-5)
+    rep = ctx.scf(**o)
+    e = ctx.get_energies()
+    lam = ctx.get_eigenvalues()
+    ctx.close()
+    ref = hxc.scf_hxc(cfg)
+    natom = len(cfg["atom_species"])
+    dF = abs(e["F"] - ref["F"]) / natom
+    nocc = int(cfg["nelec"] / 2)
+    dl = np.max(np.abs(lam[0, 0, :nocc] - ref["eigs"][0, 0, :nocc]))
+    print(f"[gpu] hxc c1 mixed: |dF|/atom {dF:.2e}, max |d eig| {dl:.2e}, iterations {rep['iterations']}", flush=True)
+    assert rep["converged"]
+    assert dF < 1e-5 and dl < 1e-4
+
+
+def test_save_resume_continues_exactly():
+    """A state saved after 3 iterations and loaded into a fresh context
+    continues the SCF exactly as the uninterrupted one (density window and
+    input density included)."""
+    _torch()
+    cfg = _cfg("tiny")
+    print("[gpu] hxc save/resume", flush=True)
+    a = _ctx(cfg)
+    a.scf_begin(**_opts(cfg))
+    for _ in range(3):
+        a.scf_step()
+    blob = a.save_state()
+    steps_a = [a.scf_step() for _ in range(3)]
+    Va, ra = a.get_potential()
+    a.close()
+    b = _ctx(cfg)
+    b.load_state(blob)
+    steps_b = [b.scf_step() for _ in range(3)]
+    Vb, rb = b.get_potential()
+    b.close()
+    for sa, sb in zip(steps_a, steps_b):
+        assert sa["F"] == sb["F"] and sa["residual_rho"] == sb["residual_rho"]
+    assert np.array_equal(Va, Vb) and np.array_equal(ra, rb)
+
+
+def test_bad_options_rejected():
+    _torch()
+    from paper_2507_23612_amd import hcu
+    cfg = _cfg("tiny")
+    ctx = _ctx(cfg)
+    for bad in (dict(pulay_history=9), dict(kerker_k0=-1.0), dict(tol_rho=0.0)):
+        o = _opts(cfg)
+        o.update(bad)
+        with pytest.raises(hcu.HcuError):
+            ctx.scf_begin(**o)
+    ctx.close()
