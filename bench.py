@@ -256,6 +256,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-scf", action="store_true", help="skip the SCF wall-time run")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision (c3) figure of the default run")
+    ap.add_argument("--no-hxc", action="store_true",
+                    help="skip the density-dependent Hamiltonian figure (Hartree + exchange + density mixing)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (calibrates hardware byte counters)")
     ap.add_argument("--tile", default=None,
@@ -292,6 +294,8 @@ def main():
         print(json.dumps(bench_scf_compare(args)), flush=True)
         return
     out = measure(args, args.config, args.precision, hcu, torch, top=True)
+    if not args.no_hxc:
+        out["hxc"] = measure_hxc(args, args.config, args.precision, out["stencil_tuning"], hcu, torch)
     if args.config == "c2" and args.precision in (None, "fp64") and not args.no_mixed:
         # the mixed-precision half of the metric, on its own workload (c3)
         mixed = measure(args, "c3", "mixed", hcu, torch, top=False)
@@ -327,6 +331,57 @@ def fused_roofline(cfg, prec, sizes, kt, config, tile, complex_):
             "avg_launch_ms": round(ms, 4), "algorithmic_bytes_per_launch": int(nbytes),
             "algorithmic_flops_per_launch": int(flops), "achieved_tflops": round(tf, 2),
             "mfma_peak_tflops": peak_tf, "mfma_frac": round(tf / peak_tf, 4)}
+
+
+def measure_hxc(args, config, precision, tuning, hcu, torch):
+    """SCF iterations of the same workload with the density-dependent
+    Hamiltonian (V = V_loc + V_H[rho_in] + V_x[rho_in], the density mixed by
+    the Kerker-preconditioned Pulay step, its coefficients mixing D): time
+    per iteration and the share of the density, Hartree/exchange energies and
+    mixing step (stream time of those phases, host solve included)."""
+    cfg = make_workload(config)
+    cfg["hxc"] = True
+    prec = precision or cfg["precision"]
+    nd, ns = int(np.prod(cfg["n"])), int(cfg["ns"])
+    ctx = hcu.HcuContext(cfg, prec)
+    ctx.set_tuning(tuning["tile_x"], tuning["tile_yt"], tuning["ry"], tuning["tile_z"])
+    ctx.set_hubbard_occupation(hcu.initial_occupation(ctx, cfg))
+    for sp in range(ctx.nspin):
+        for ik in range(ctx.nk):
+            X0, v0 = hcu.start_inputs(ctx, cfg, sp, ik)
+            ctx.set_start(sp, ik, X0, v0)
+            del X0, v0
+    ctx.scf_begin(first_passes=1)
+    for _ in range(args.warmup):
+        ctx.scf_step()
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info = ctx.scf_step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    kt = ctx.get_kernel_times()
+    ctx.set_profiling(False)
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    m = int(cfg["degree"])
+    elem = 4 if prec == "mixed" else 8
+    hx_ms = kt["hxc_ms"] / args.steps
+    # algorithmic bytes of the density-dependent phases per iteration: the
+    # density reads the orbital block once; the grid passes (sums, FFTs,
+    # window, combination, Kerker step, assembly) are ~(30 + 3 m) grid
+    # vectors of doubles with a full mixing window of m = 7 differences
+    hx_bytes = ns * nd * elem + (30 + 3 * 7) * nd * 8
+    return {"ms_per_step": round(dt * 1e3, 3),
+            "value": round(nd * ns * (m + 1) / dt / 1e9, 3), "unit": "Gpts·states/s",
+            "hxc_ms_per_step": round(hx_ms, 3), "hxc_share": round(hx_ms / (dt * 1e3), 4),
+            "hxc_algorithmic_bytes": int(hx_bytes),
+            "hxc_achieved_GBs": round(hx_bytes / (hx_ms * 1e-3) / 1e9, 1) if hx_ms > 0 else None,
+            "residual_rho_last": info["residual_rho"],
+            "note": "density + FFT Hartree (stencil symbol) + LDA exchange + Kerker-preconditioned Pulay step on "
+                    "the density; stream time of those phases per SCF iteration"}
 
 
 def measure(args, config, precision, hcu, torch, top):

@@ -175,6 +175,9 @@ typedef struct hcu_kernel_times {
   double scatter_ms;  long long scatter_launches;  /* projector scatter (KB + Hubbard)   */
   double fused_ms;    long long fused_launches;    /* of scatter: the fused scatter +
                                                       projection kernel alone           */
+  double hxc_ms;      long long hxc_launches;      /* hxc: density, Hartree and exchange
+                                                      energies, density mixing step
+                                                      (stream time, host solve included) */
 } hcu_kernel_times;
 
 typedef struct hcu_ctx hcu_ctx;

@@ -876,8 +876,12 @@ hcu_status occupations_t(Ctx& c) {
   c.en.F = sc[5];
   c.en.E_H = c.en.E_x = c.en.e_hxc = 0.0;
   if (c.hxc) {
-    hcu_status s = density_t<T>(c, nullptr);
-    if (s == HCU_OK) s = hxc_energies(c);
+    hcu_status s;
+    {
+      ProfScope ps(c, PK_HXC, true);
+      s = density_t<T>(c, nullptr);
+      if (s == HCU_OK) s = hxc_energies(c);
+    }
     if (s != HCU_OK) return s;
     c.en.F += c.en.e_hxc;
   }
@@ -1151,7 +1155,10 @@ hcu_status scf_post(Ctx& c, hcu_scf_step_info* info) {
     if (c.hxc) {
       // one Pulay step on the density; its coefficients mix D too
       std::vector<double> gamma;
-      s = hxc_mix(c, o.pulay_history, o.pulay_beta, o.kerker_k0, gamma);
+      {
+        ProfScope ps(c, PK_HXC, true);
+        s = hxc_mix(c, o.pulay_history, o.pulay_beta, o.kerker_k0, gamma);
+      }
       if (s != HCU_OK) return s;
       xn = mix.step_with(x, f, gamma);
     } else {
@@ -1288,6 +1295,7 @@ hcu_status hcu_get_kernel_times(hcu_ctx* ctx, hcu_kernel_times* t) {
   t->project_ms = ctx->prof_ms[PK_PROJECT]; t->project_launches = ctx->prof_count[PK_PROJECT];
   t->gram_ms = ctx->prof_ms[PK_GRAM]; t->gram_launches = ctx->prof_count[PK_GRAM];
   t->eig_ms = ctx->prof_ms[PK_EIG]; t->eig_launches = ctx->prof_count[PK_EIG];
+  t->hxc_ms = ctx->prof_ms[PK_HXC]; t->hxc_launches = ctx->prof_count[PK_HXC];
   t->rotate_ms = ctx->prof_ms[PK_ROTATE]; t->rotate_launches = ctx->prof_count[PK_ROTATE];
   t->scatter_ms = ctx->prof_ms[PK_SCATTER] + ctx->prof_ms[PK_FUSED];
   t->scatter_launches = ctx->prof_count[PK_SCATTER];

@@ -268,7 +268,7 @@ struct Ctx {
 };
 
 enum ProfKind { PK_STENCIL = 0, PK_PROJECT = 1, PK_GRAM = 2, PK_EIG = 3, PK_ROTATE = 4, PK_SCATTER = 5,
-                PK_FUSED = 6 };
+                PK_FUSED = 6, PK_HXC = 7 };
 
 // Scoped timing of the launches queued inside it (no-op unless profiling).
 // Per-phase GPU time.  A marker event recorded between two kernels on a

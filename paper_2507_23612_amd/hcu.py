@@ -73,7 +73,8 @@ class hcu_kernel_times(C.Structure):
                 ("eig_ms", C.c_double), ("eig_launches", C.c_longlong),
                 ("rotate_ms", C.c_double), ("rotate_launches", C.c_longlong),
                 ("scatter_ms", C.c_double), ("scatter_launches", C.c_longlong),
-                ("fused_ms", C.c_double), ("fused_launches", C.c_longlong)]
+                ("fused_ms", C.c_double), ("fused_launches", C.c_longlong),
+                ("hxc_ms", C.c_double), ("hxc_launches", C.c_longlong)]
 
 
 class hcu_tuning(C.Structure):

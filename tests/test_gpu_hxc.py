@@ -187,3 +187,30 @@ def test_bad_options_rejected():
         with pytest.raises(hcu.HcuError):
             ctx.scf_begin(**o)
     ctx.close()
+
+
+def test_hartree_full_size_c2_property():
+    """At the benchmark's full size (48 atoms, 72x72x96, 256 FP64 states),
+    after one SCF iteration: the Hartree part of the potential solves the
+    finite-difference Poisson equation, -Delta_h V_H = 4 pi (rho_in - <rho_in>),
+    on every grid point (V_H = V - V_loc - V_x(rho_in), the Laplacian applied
+    directly on the CPU), and rho_in holds N_e electrons."""
+    _torch()
+    from oracle import fd, hxc
+    from oracle.atoms import local_potential
+    cfg = _cfg("c2")
+    print("[gpu] hxc full size c2: one iteration", flush=True)
+    ctx = _ctx(cfg)
+    ctx.scf_begin(first_passes=1, **{k: v for k, v in _opts(cfg).items() if k != "first_passes"})
+    ctx.scf_step()
+    V, rho = ctx.get_potential()
+    ctx.close()
+    n = np.asarray(cfg["n"])
+    dv = float(np.prod(np.asarray(cfg["L"]) / n))
+    assert abs(rho.sum() * dv - cfg["nelec"]) < 1e-9 * cfg["nelec"]
+    vh = V - local_potential(cfg) - hxc.exchange_potential(rho)
+    lhs = -fd.apply_laplacian(vh.reshape(n[2], n[1], n[0]), cfg["L"], n, cfg["n0"]).ravel()
+    rhs = 4 * np.pi * (rho - rho.mean())
+    err = np.max(np.abs(lhs - rhs)) / np.max(np.abs(rhs))
+    print(f"[gpu] c2 Poisson residual {err:.2e}, max |V_H| {np.max(np.abs(vh)):.3e}", flush=True)
+    assert err < 1e-9
