@@ -69,9 +69,9 @@ def stencil_bytes(cfg, elem):
 def measured_traffic(kernel, config, prec, tile, sources):
     """HBM bytes per launch of `kernel` from the committed counter summaries
     profiles/<kernel>_<config>_<prec>*.md (FETCH_SIZE and WRITE_SIZE runs,
-    calibrated on a plain copy; one file per tile shape), or None if there is
-    none for this tile shape or the kernel's sources changed since it was
-    taken."""
+    calibrated on a plain copy; one file per stencil tile shape, "any" for
+    kernels that do not depend on it), or None if there is none for this
+    tile shape or the kernel's sources changed since it was taken."""
     import glob
     from paper_2507_23612_amd.tracesum import kernel_source_digest
     digest = kernel_source_digest(sources)
@@ -83,7 +83,7 @@ def measured_traffic(kernel, config, prec, tile, sources):
                     k, _, v = line[len("- record "):].partition(":")
                     rec[k.strip()] = v.strip()
         try:
-            if rec.get("source_sha256") == digest and rec.get("tile") == tile:
+            if rec.get("source_sha256") == digest and rec.get("tile") in (tile, "any"):
                 return int(float(rec["traffic_bytes_per_launch"]))
         except (KeyError, ValueError):
             continue

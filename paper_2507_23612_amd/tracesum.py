@@ -3,7 +3,7 @@
     python -m paper_2507_23612_amd.tracesum <dir-with-*_kernel_trace.csv> [top]
     python -m paper_2507_23612_amd.tracesum --counter <dir> <kernel substring> <counter>
     python -m paper_2507_23612_amd.tracesum --record <trace dir> <FETCH_SIZE dir> <WRITE_SIZE dir> \
-        <kernel substring> <tile> <title> <command file> [source files, comma-separated]
+        <kernel substring> <tile> <title> <command file> [source files, comma-separated] [counter dir]
 
 Prints, per (kernel, grid, workgroup) group: launches, total, average, min
 and max duration in ms, sorted by total time.  Grouping by launch shape
@@ -101,10 +101,41 @@ def _calibration(path, counter):
     return first, 1048576.0 / first
 
 
-def record(trace_dir, fetch_dir, write_dir, kernel_sub, tile, title, cmds, digest):
+def sq_lines(sq_dir, kernel_sub, avg_ms):
+    """Per-launch averages of the instruction-counter pass (full-block
+    launches) and the matrix-core busy fraction derived from them.
+    GRBM_GUI_ACTIVE is summed over the 8 XCDs, so one XCD's active cycles
+    are a eighth of it; SQ_VALU_MFMA_BUSY_CYCLES is summed over the 1024
+    SIMDs (256 CUs x 4)."""
+    names = set()
+    for f in glob.glob(os.path.join(sq_dir, "*_counter_collection.csv")):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if kernel_sub in r["Kernel_Name"]:
+                    names.add(r["Counter_Name"])
+    vals = {}
+    for n in sorted(names):
+        _, v = _largest_grid(counters(sq_dir, kernel_sub, n))
+        vals[n] = sum(v) / len(v)
+    out = ["", "## Instruction counters (full-block launches, per launch)", ""]
+    out += [f"- {n}: {v:.4g}" for n, v in vals.items()]
+    if "GRBM_GUI_ACTIVE" in vals and "SQ_VALU_MFMA_BUSY_CYCLES" in vals:
+        gui = vals["GRBM_GUI_ACTIVE"] / 8.0
+        busy = vals["SQ_VALU_MFMA_BUSY_CYCLES"] / (gui * 1024.0)
+        out += [f"- GPU active per XCD: {gui:.0f} cycles ({gui / 2.4e6:.4f} ms at 2.4 GHz; "
+                f"trace average {avg_ms:.4f} ms)",
+                f"- matrix-core busy fraction: SQ_VALU_MFMA_BUSY_CYCLES / (active cycles x 1024 SIMDs) = {busy:.3f}"]
+    if "SQ_WAVE_CYCLES" in vals and "SQ_WAIT_INST_ANY" in vals and vals["SQ_WAVE_CYCLES"] > 0:
+        out.append(f"- waves waiting on any instruction dependency: SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES = "
+                   f"{vals['SQ_WAIT_INST_ANY'] / vals['SQ_WAVE_CYCLES']:.3f}")
+    return out
+
+
+def record(trace_dir, fetch_dir, write_dir, kernel_sub, tile, title, cmds, digest, sq_dir=None):
     """Markdown summary of one kernel: trace statistics, per-launch
-    FETCH_SIZE / WRITE_SIZE scaled by the copy calibration, and the record
-    lines bench.py reads (traffic per launch, tile, source digest)."""
+    FETCH_SIZE / WRITE_SIZE scaled by the copy calibration, optionally the
+    instruction-counter pass, and the record lines bench.py reads (traffic
+    per launch, tile, source digest)."""
     grid, durs = _avg_ms_largest_grid(trace_dir, kernel_sub)
     fg, fv = _largest_grid(counters(fetch_dir, kernel_sub, "FETCH_SIZE"))
     wg, wv = _largest_grid(counters(write_dir, kernel_sub, "WRITE_SIZE"))
@@ -124,8 +155,10 @@ def record(trace_dir, fetch_dir, write_dir, kernel_sub, tile, title, cmds, diges
             f"- calibration (1 GiB device copy): FETCH_SIZE reads {cf_raw:.1f} KiB -> factor {cf:.3f}; "
             f"WRITE_SIZE reads {cw_raw:.1f} KiB -> factor {cw:.3f}",
             f"- HBM traffic per launch: {fetch * cf / 1024:.1f} MiB fetched + {write * cw / 1024:.1f} MiB written "
-            f"= {traffic / 2**20:.1f} MiB", "",
-            "Record read by bench.py (applies while the kernel sources hash to the digest):", "",
+            f"= {traffic / 2**20:.1f} MiB"]
+    if sq_dir:
+        out += sq_lines(sq_dir, kernel_sub, sum(durs) / len(durs))
+    out += ["", "Record read by bench.py (applies while the kernel sources hash to the digest):", "",
             f"- record kernel: {kernel_sub}",
             f"- record tile: {tile}",
             f"- record traffic_bytes_per_launch: {traffic:.0f}",
@@ -139,8 +172,9 @@ if __name__ == "__main__":
         with open(sys.argv[8]) as fh:
             cmds = [ln.rstrip("\n") for ln in fh if ln.strip()]
         srcs = tuple(sys.argv[9].split(",")) if len(sys.argv) > 9 else ("stencil.hip",)
+        sq = sys.argv[10] if len(sys.argv) > 10 else None
         print(record(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6], sys.argv[7], cmds,
-                     kernel_source_digest(srcs)))
+                     kernel_source_digest(srcs), sq))
         sys.exit(0)
     if len(sys.argv) > 2 and sys.argv[1] == "--counter":
         # --counter <dir> <kernel substring> <counter name>
