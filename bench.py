@@ -448,10 +448,13 @@ def measure(args, config, precision, hcu, torch, top):
            "data": "synthetic",
            "config": {"workload": f"{config}: {WORKLOADS.get(config, config)}",
                       "precision": prec, "nd": nd, "ns": ns, "degree": m},
-           "roofline": roofline, "roofline_fused": fused, "kernel_ms_per_step": breakdown,
+           "roofline": roofline, "roofline_second": fused, "kernel_ms_per_step": breakdown,
            "stencil_tuning": tuning}
+    # "roofline" describes the kernel that takes the most time per step
+    if fused and kt["fused_ms"] > kt["stencil_ms"]:
+        out["roofline"], out["roofline_second"] = fused, roofline
     if not top:
-        out = {k: out[k] for k in ("value", "unit", "ms_per_step", "dtype", "config", "roofline", "roofline_fused",
+        out = {k: out[k] for k in ("value", "unit", "ms_per_step", "dtype", "config", "roofline", "roofline_second",
                                    "kernel_ms_per_step", "stencil_tuning")}
     # forces and stress of the state reached (one call each, outside the timed region)
     ctx.update_occupations()
