@@ -26,7 +26,7 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"),
 ]
 SOURCES = ["setup.hip", "stencil.hip", "nonlocal.hip", "proj.hip", "gemm.hip", "scf_kernels.hip", "mlp.hip", "state.hip",
-           "noalloc.hip", "forces.hip", "hxc.hip", "api.hip"]
+           "noalloc.hip", "forces.hip", "hxc.hip", "eig.hip", "api.hip"]
 
 
 def _compile(src):

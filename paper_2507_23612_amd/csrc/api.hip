@@ -257,12 +257,34 @@ hcu_status generalized_eig(Ctx& c, int n, bool cp, double* lam) {
     if (r == rocblas_status_success)
       r = rocblas_dtrsm(c.blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
                         rocblas_diagonal_non_unit, n, n, &one, c.d_S, n, c.d_Hs, n);
-    if (r == rocblas_status_success)
-      r = rocsolver_dsyevd(c.blas, rocblas_evect_original, rocblas_fill_upper, n, c.d_Hs, n, lam, c.d_E,
-                           c.d_info + 1);
-    if (r == rocblas_status_success)
-      r = rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
-                        rocblas_diagonal_non_unit, n, n, &one, c.d_S, n, c.d_Hs, n);
+    if (sytrd_small_ok(n) && c.part_elems >= (size_t)n * n) {
+      // tridiagonal form in one workgroup (eig.hip), then the library's
+      // tridiagonal divide and conquer and back-transformation; the
+      // eigenvectors are formed in the Gram partials (free after the Gram
+      // reduction), the tridiagonal in d_E (off-diagonal, then tau)
+      double* Z = c.d_part;
+      double* e = c.d_E;
+      double* tau = c.d_E + n;
+      if (r == rocblas_status_success) launch_sytrd_small(c.d_Hs, n, n, lam, e, tau, c.stream);
+      if (r == rocblas_status_success)
+        r = rocsolver_dstedc(c.blas, rocblas_evect_tridiagonal, n, lam, e, Z, n, c.d_info + 1);
+      if (r == rocblas_status_success)
+        r = rocsolver_dormtr(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none, n, n, c.d_Hs, n,
+                             tau, Z, n);
+      if (r == rocblas_status_success)
+        r = rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                          rocblas_diagonal_non_unit, n, n, &one, c.d_S, n, Z, n);
+      if (r == rocblas_status_success &&
+          hipMemcpyAsync(c.d_Hs, Z, sizeof(double) * n * n, hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
+        r = rocblas_status_internal_error;
+    } else {
+      if (r == rocblas_status_success)
+        r = rocsolver_dsyevd(c.blas, rocblas_evect_original, rocblas_fill_upper, n, c.d_Hs, n, lam, c.d_E,
+                             c.d_info + 1);
+      if (r == rocblas_status_success)
+        r = rocblas_dtrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                          rocblas_diagonal_non_unit, n, n, &one, c.d_S, n, c.d_Hs, n);
+    }
   }
   if (r != rocblas_status_success) return fail(c, HCU_DEVICE, "rocSOLVER/rocBLAS call failed in the eigensolve");
   return HCU_OK;
