@@ -226,7 +226,7 @@ __device__ inline double wave_sum_lane63(double x) {
 __global__ __launch_bounds__(kRgThreads) void k_sytrd_reg(double* __restrict__ A, int n, int lda,
                                                           double* __restrict__ d, double* __restrict__ e,
                                                           double* __restrict__ taus) {
-  __shared__ double v[kRgMaxN], w[kRgMaxN], vn[kRgMaxN], p[kRgMaxN], pc[kRgMaxN], colbuf[kRgMaxN];
+  __shared__ double v[kRgMaxN], w[kRgMaxN], vn[kRgMaxN], pc[kRgMaxN], colbuf[kRgMaxN];
   __shared__ double part[kRgWaves * kRgChunks * 64];
   __shared__ double red[kRgWaves];
   __shared__ double sc[4];
@@ -298,42 +298,61 @@ __global__ __launch_bounds__(kRgThreads) void k_sytrd_reg(double* __restrict__ A
       accr[k] = 0.0;
     }
 #pragma unroll
-    for (int j = 0; j < kRgCols; ++j) {
-      const int c = wv + kRgWaves * j;
-      if (c < m) {   // wave-uniform
-        const double vc = v[c], wc = w[c], vnc = vn[c];
-        double col = 0.0;
+    // columns in pairs (two independent reduction chains in flight); the
+    // second column of a pair may lie beyond m, where v, w and vn read as
+    // zero: its update subtracts zeros and it adds nothing to accr (its pc
+    // entry is not read)
+    for (int jp = 0; jp < kRgCols; jp += 2) {
+      if (wv + kRgWaves * jp < m) {   // wave-uniform
+        double col[2];
 #pragma unroll
-        for (int k = 0; k < rg_nch(j); ++k) {
-          const int r = 64 * k + lane;
-          const double x = a[rg_off(j) + k] - (vr[k] * wc + wr[k] * vc);
-          if (r <= c) a[rg_off(j) + k] = x;
-          if (r < c) {
-            col += x * vnr[k];
-            accr[k] += x * vnc;
-          } else if (r == c) {
-            col += x * vnc;
+        for (int u = 0; u < 2; ++u) {
+          const int j = jp + u;
+          const int c = wv + kRgWaves * j;
+          const double vc = v[c], wc = w[c], vnc = vn[c];
+          col[u] = 0.0;
+#pragma unroll
+          for (int k = 0; k < rg_nch(j); ++k) {
+            const int r = 64 * k + lane;
+            const double x = a[rg_off(j) + k] - (vr[k] * wc + wr[k] * vc);
+            if (k < rg_nch(j) - 1) {
+              // rows of the earlier chunks all lie above the diagonal
+              a[rg_off(j) + k] = x;
+              col[u] += x * vnr[k];
+              accr[k] += x * vnc;
+            } else {
+              // the last chunk holds the diagonal (vnr = vnc there)
+              if (r <= c) {
+                a[rg_off(j) + k] = x;
+                col[u] += x * vnr[k];
+              }
+              if (r < c) accr[k] += x * vnc;
+            }
+            if (c == m - 1 && r <= c) colbuf[r] = x;
           }
-          if (c == m - 1 && r <= c) colbuf[r] = x;
         }
-        col = wave_sum_lane63(col);
-        if (lane == 63) pc[c] = col;
+        const double s0 = wave_sum_lane63(col[0]);
+        const double s1 = wave_sum_lane63(col[1]);
+        if (lane == 63) {
+          pc[wv + kRgWaves * jp] = s0;
+          pc[wv + kRgWaves * (jp + 1)] = s1;
+        }
       }
     }
 #pragma unroll
     for (int k = 0; k < kRgChunks; ++k) part[(wv * kRgChunks + k) * 64 + lane] = accr[k];
     __syncthreads();
+    // ---- p = A_new v' (thread t holds p_t), then
+    //      w = tau p - (tau^2 / 2)(p . v') v' for the reflector just formed
+    //      (v' = vn, length m), then v <- v'
+    double pt = 0.0;
     if (t < m) {
       const int k = t >> 6, l = t & 63;
-      double s = pc[t];
-      for (int ww = 0; ww < kRgWaves; ++ww) s += part[(ww * kRgChunks + k) * 64 + l];
-      p[t] = s;
+      pt = pc[t];
+      for (int ww = 0; ww < kRgWaves; ++ww) pt += part[(ww * kRgChunks + k) * 64 + l];
     }
     if (t == 0) { e[q - 1] = beta; taus[q - 1] = tau; }
-    __syncthreads();
-    // ---- w = tau p - (tau^2 / 2)(p . v') v' for the reflector just formed
-    //      (v' = vn, length m), then v <- v'
-    const double wi = t < m ? tau * p[t] : 0.0;
+    const double wi = t < m ? tau * pt : 0.0;
     const double dotp = wave_sum_lane63(t < m ? wi * vn[t] : 0.0);
     if (lane == 63) red[wv] = dotp;
     __syncthreads();
