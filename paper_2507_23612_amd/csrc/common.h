@@ -72,6 +72,31 @@ __device__ inline unsigned xcd_linear() {
   return x * q + (x < r ? x : r) + i;
 }
 
+// Point order of the 64-point bricks of the projector tables.  Linear: brick
+// b holds the points 64 b .. 64 b + 63 (the last one cut at the grid end).
+// Blocks: brick b is a block of 2^lx x 2^ly x 2^lz grid points (lx >= 2,
+// lx + ly + lz = 6) in x-fastest block order, local index
+// i = dx + 2^lx (dy + 2^ly dz); a compact block meets the atoms' spherical
+// supports more densely than a 64-point run of one grid row.  Local indices
+// 4k .. 4k+3 are consecutive in memory in both orders.  Projection brick b
+// is made of the bricks 4b .. 4b+3 in either order.
+struct BrickGeo {
+  int cube = 0;                 // 1: blocks
+  int lx = 6, ly = 0, lz = 0;   // log2 of the block edges
+  int n1 = 0, nbx = 1, nby = 1;
+  int64_t n12 = 0;
+  int64_t nbrick = 0;           // bricks of the grid
+  __host__ __device__ int64_t base(int64_t b) const {
+    if (!cube) return b * 64;
+    const int64_t bx = b % nbx, t = b / nbx, by = t % nby, bz = t / nby;
+    return (bx << lx) + (int64_t)n1 * (by << ly) + n12 * (bz << lz);
+  }
+  __host__ __device__ int64_t off(int i) const {
+    if (!cube) return i;
+    return (i & ((1 << lx) - 1)) + (int64_t)n1 * ((i >> lx) & ((1 << ly) - 1)) + n12 * (i >> (lx + ly));
+  }
+};
+
 // ---------------------------------------------------------------- context
 struct BlockDesc {            // one projector block: the KB channels or the Hubbard manifold of one atom
   int atom;
@@ -126,7 +151,8 @@ struct Ctx {
   std::vector<int> csr_ptr, csr_col;
   std::vector<int64_t> csr_src;      // csc position of each csr entry
   int coup_size = 0;
-  // Bricks of 64 consecutive grid points.  Brick b has bnj[b] functions,
+  BrickGeo geo;                      // point order of the bricks
+  // Bricks of 64 grid points (geo).  Brick b has bnj[b] functions,
   // listed in bj[boff[b] .. boff[b+1]) (padded to a multiple of 4 with -1),
   // and a dense value tile [slot][64 points].
   std::vector<int64_t> boff;         // nbrick + 1, in slots
@@ -445,6 +471,7 @@ bool scatter_project_ok(const Ctx& c);
 // The fused pass of several blocks in one launch: one record per block,
 // workgroups item0 .. of each job (jobs ordered by item0).
 struct FusedJob {
+  BrickGeo geo;
   void* Y; int64_t ld; int ncol; int nst;
   const int64_t* boff; const int* bnj; const int* bj; const void* bval;
   const void* Qt; int ldq; double alpha; int nbrick;

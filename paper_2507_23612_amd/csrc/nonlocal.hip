@@ -30,7 +30,8 @@ template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_nl_brick(T* __restrict__ Y, int64_t ld, int ncol,
                                                   const int64_t* __restrict__ boff, const int* __restrict__ bnj,
                                                   const int* __restrict__ bj, const T* __restrict__ bval,
-                                                  const T* __restrict__ Qt, int ldq, T alpha, int64_t nd, int nst) {
+                                                  const T* __restrict__ Qt, int ldq, T alpha, int64_t nd, int nst,
+                                                  const BrickGeo geo) {
   using V = typename Mf<T>::V;
   // 1-D grid, logical order: state tile fastest, then brick; XCD-contiguous
   // so the state tiles of a brick share its table tile in one L2
@@ -44,13 +45,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   const int s0 = st_ * 64 + wave * 16;
   const int sa = s0 + (lane & 15);
   const bool sa_ok = sa < ncol;
-  const int64_t p0 = (int64_t)b * kBrick;
+  const int64_t p0 = geo.base(b);   // local index pt*16 + lane%16 at p0 + geo.off(...)
   const T* __restrict__ vb = bval + jo * kBrick;
   V acc[4];
   for (int pt = 0; pt < 4; ++pt)
     for (int q = 0; q < 4; ++q) {
       const int s = s0 + Mf<T>::row(lane, q);
-      const int64_t p = p0 + pt * 16 + (lane & 15);
+      const int64_t p = p0 + geo.off(pt * 16 + (lane & 15));
       acc[pt][q] = (s < ncol && p < nd) ? Y[(int64_t)s * ld + p] : T(0);
     }
   // The brick's function indices are read 64 at a time (one per lane) and
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   for (int pt = 0; pt < 4; ++pt)
     for (int q = 0; q < 4; ++q) {
       const int s = s0 + Mf<T>::row(lane, q);
-      const int64_t p = p0 + pt * 16 + (lane & 15);
+      const int64_t p = p0 + geo.off(pt * 16 + (lane & 15));
       if (s < ncol && p < nd) Y[(int64_t)s * ld + p] = acc[pt][q];
     }
 }
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(256) void k_nl_brick_c(cplx<R>* __restrict__ Y, int
                                                     const int64_t* __restrict__ boff, const int* __restrict__ bnj,
                                                     const int* __restrict__ bj, const cplx<R>* __restrict__ bval,
                                                     const cplx<R>* __restrict__ Qt, int ldq, R alpha, int64_t nd,
-                                                    int nst) {
+                                                    int nst, const BrickGeo geo) {
   using V = typename Mf<R>::V;
   const unsigned lw = xcd_linear();
   const int b = lw / nst;
@@ -106,13 +107,13 @@ __global__ __launch_bounds__(256) void k_nl_brick_c(cplx<R>* __restrict__ Y, int
   const int s0 = st_ * 64 + wave * 16;
   const int sa = s0 + (lane & 15);
   const bool sa_ok = sa < ncol;
-  const int64_t p0 = (int64_t)b * kBrick;
+  const int64_t p0 = geo.base(b);   // local index pt*16 + lane%16 at p0 + geo.off(...)
   const cplx<R>* __restrict__ vb = bval + jo * kBrick;
   V ar[4], ai[4];
   for (int pt = 0; pt < 4; ++pt)
     for (int q = 0; q < 4; ++q) {
       const int s = s0 + Mf<R>::row(lane, q);
-      const int64_t p = p0 + pt * 16 + (lane & 15);
+      const int64_t p = p0 + geo.off(pt * 16 + (lane & 15));
       const cplx<R> y = (s < ncol && p < nd) ? Y[(int64_t)s * ld + p] : cplx<R>();
       ar[pt][q] = y.re;
       ai[pt][q] = y.im;
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(256) void k_nl_brick_c(cplx<R>* __restrict__ Y, int
   for (int pt = 0; pt < 4; ++pt)
     for (int q = 0; q < 4; ++q) {
       const int s = s0 + Mf<R>::row(lane, q);
-      const int64_t p = p0 + pt * 16 + (lane & 15);
+      const int64_t p = p0 + geo.off(pt * 16 + (lane & 15));
       if (s < ncol && p < nd) Y[(int64_t)s * ld + p] = cplx<R>(ar[pt][q], ai[pt][q]);
     }
 }
@@ -152,7 +153,7 @@ void launch_nl_scatter(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T
     const int nbrick = (int)c.boff.size() - 1;
     const int nst = (ncol + 63) / 64;
     launch_k(k_nl_brick<T>, (unsigned)nbrick * nst, 256, 0, st, Y, ld, ncol, c.d_boff, c.d_bnj, c.d_bj,
-             (const T*)c.d_bval[ik], Qt, c.p.ns, (T)alpha, c.nd, nst);
+             (const T*)c.d_bval[ik], Qt, c.p.ns, (T)alpha, c.nd, nst, c.geo);
     return;
   }
   else {
@@ -160,7 +161,7 @@ void launch_nl_scatter(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T
     const int nbrick = (int)c.boff.size() - 1;
     const int nst = (ncol + 63) / 64;
     launch_k(k_nl_brick_c<R>, (unsigned)nbrick * nst, 256, 0, st, Y, ld, ncol, c.d_boff, c.d_bnj, c.d_bj,
-             (const T*)c.d_bval[ik], Qt, c.p.ns, (R)alpha, c.nd, nst);
+             (const T*)c.d_bval[ik], Qt, c.p.ns, (R)alpha, c.nd, nst, c.geo);
     return;
   }
 }

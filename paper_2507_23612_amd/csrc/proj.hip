@@ -76,11 +76,31 @@ __device__ __forceinline__ void load_piece(const T* __restrict__ row, int stride
   }
 }
 
+// the 16 step operands of the state row Ys on piece sbk (a 64-point brick):
+// local indices 4G i + G q .. + G-1 (consecutive in memory), zeros outside
+// the grid
+template <typename T, int G>
+__device__ __forceinline__ void load_rows(const T* __restrict__ Ys, const BrickGeo& geo, int64_t sbk, int q,
+                                          int64_t nd, bool vec, T* out) {
+  if (!geo.cube) {
+    const int64_t pb = sbk * 64;
+    load_piece<T, G>(Ys + pb, 4 * G, G * q, nd - pb, vec, out);
+    return;
+  }
+  if (sbk >= geo.nbrick) {
+    for (int i = 0; i < 16; ++i) out[i] = T();
+    return;
+  }
+  const int64_t base = geo.base(sbk);
+  for (int i = 0; i < 16 / G; ++i) ld_group<T, G>(Ys + base + geo.off(4 * G * i + G * q), vec, out + G * i);
+}
+
 template <typename T, int G>
 __global__ __launch_bounds__(256) void k_proj_brick(const T* __restrict__ Y, int64_t ld, int ncol,
                                                     const int64_t* __restrict__ pboff, const int* __restrict__ pbnj,
                                                     const T* __restrict__ pbval, const int64_t* __restrict__ pdest,
-                                                    T* __restrict__ part, int ldp, int64_t nd, int nst, int vec) {
+                                                    T* __restrict__ part, int ldp, int64_t nd, int nst, int vec,
+                                                    const BrickGeo geo) {
   using V = typename Mf<T>::V;
   constexpr int P = kPBrick / 64;
   const unsigned lw = xcd_linear();   // 1-D grid: state tile fastest, then brick
@@ -95,7 +115,6 @@ __global__ __launch_bounds__(256) void k_proj_brick(const T* __restrict__ Y, int
   if (s0 >= ncol) return;
   const int sb = s0 + (lane & 15);
   const int q = lane >> 4;
-  const int64_t p0 = (int64_t)b * kPBrick;
   // rows of padding states repeat the last state (results never stored)
   const T* __restrict__ Ys = Y + (int64_t)min(sb, ncol - 1) * ld;
   const bool vec_ok = vec != 0;
@@ -111,9 +130,8 @@ __global__ __launch_bounds__(256) void k_proj_brick(const T* __restrict__ Y, int
       for (int t = 0; t < 4; ++t)
         for (int r = 0; r < 4; ++r) acc[t][r] = T(0);
       for (int piece = 0; piece < P; ++piece) {
-        const int64_t pb = p0 + piece * 64;
         T bk[16];
-        load_piece<T, G>(Ys + pb, 4 * G, G * q, nd - pb, vec_ok, bk);
+        load_rows<T, G>(Ys, geo, (int64_t)b * P + piece, q, nd, vec_ok, bk);
         for (int t = 0; t < 4; ++t) {
           if (jg + t >= ntile) break;   // wave-uniform
           T a[16];
@@ -139,9 +157,8 @@ __global__ __launch_bounds__(256) void k_proj_brick(const T* __restrict__ Y, int
         for (int h = 0; h < 2; ++h)
           for (int r = 0; r < 4; ++r) acc[t][h][r] = T(0);
       for (int piece = 0; piece < P; ++piece) {
-        const int64_t pb = p0 + piece * 64;
         T bk[16], a0[16], a1[16];
-        load_piece<T, G>(Ys + pb, 4 * G, G * q, nd - pb, vec_ok, bk);
+        load_rows<T, G>(Ys, geo, (int64_t)b * P + piece, q, nd, vec_ok, bk);
         load_piece<T, G>(trow(jg, piece), 64 * G, 0, 64, true, a0);
         if (two) {
           load_piece<T, G>(trow(jg + 1, piece), 64 * G, 0, 64, true, a1);
@@ -171,7 +188,8 @@ __global__ __launch_bounds__(256) void k_proj_brick_c(const cplx<R>* __restrict_
                                                       const int* __restrict__ pbnj,
                                                       const cplx<R>* __restrict__ pbval,
                                                       const int64_t* __restrict__ pdest, cplx<R>* __restrict__ part,
-                                                      int ldp, int64_t nd, int nst, int vec) {
+                                                      int ldp, int64_t nd, int nst, int vec,
+                                                      const BrickGeo geo) {
   using V = typename Mf<R>::V;
   constexpr int P = kPBrick / 64;
   const unsigned lw = xcd_linear();
@@ -186,7 +204,6 @@ __global__ __launch_bounds__(256) void k_proj_brick_c(const cplx<R>* __restrict_
   if (s0 >= ncol) return;
   const int sb = s0 + (lane & 15);
   const int q = lane >> 4;
-  const int64_t p0 = (int64_t)b * kPBrick;
   const cplx<R>* __restrict__ Ys = Y + (int64_t)min(sb, ncol - 1) * ld;
   const bool vec_ok = vec != 0;
   // one slot tile per sweep with four independent accumulators
@@ -195,9 +212,8 @@ __global__ __launch_bounds__(256) void k_proj_brick_c(const cplx<R>* __restrict_
     V c0, c1, c2, c3;
     for (int r = 0; r < 4; ++r) c0[r] = c1[r] = c2[r] = c3[r] = R(0);
     for (int piece = 0; piece < P; ++piece) {
-      const int64_t pb = p0 + piece * 64;
       cplx<R> y[16], f[16];
-      load_piece<cplx<R>, G>(Ys + pb, 4 * G, G * q, nd - pb, vec_ok, y);
+      load_rows<cplx<R>, G>(Ys, geo, (int64_t)b * P + piece, q, nd, vec_ok, y);
       load_piece<cplx<R>, G>(pbval + (((jo / 16 + jt) * P + piece) * (16 / G)) * (64 * G) + lane * G, 64 * G, 0, 64,
                              true, f);
       for (int kk = 0; kk < 16; ++kk) {
@@ -287,7 +303,8 @@ template <typename T> constexpr int kStageFns = sizeof(T) == 8 ? 32 : 64;   // f
 
 // body of one workgroup: projection brick b, state tile st_
 template <typename T, int G, int NT>
-__device__ __forceinline__ void fused_real(T* __restrict__ Y, int64_t ld, int ncol, const int64_t* __restrict__ boff,
+__device__ __forceinline__ void fused_real(const BrickGeo& geo, T* __restrict__ Y, int64_t ld, int ncol,
+                                           const int64_t* __restrict__ boff,
                                            const int* __restrict__ bnj, const int* __restrict__ bj,
                                            const T* __restrict__ bval, const T* __restrict__ Qt, int ldq, T alpha,
                                            int nbrick, const int64_t* __restrict__ pboff,
@@ -321,13 +338,13 @@ __device__ __forceinline__ void fused_real(T* __restrict__ Y, int64_t ld, int nc
   for (int k = 0; k < P; ++k) {
     const int sbk = b * P + k;
     if (sbk >= nbrick) break;   // uniform: the last brick of a ragged grid
-    const int64_t p0 = (int64_t)sbk * kBrick;
+    const int64_t p0 = geo.base(sbk);   // local index pt*16 + lane%16 at p0 + geo.off(...)
     // ---- scatter of brick sbk
     V acc[4];
     for (int pt = 0; pt < 4; ++pt)
       for (int r = 0; r < 4; ++r) {
         const int s = s0 + Mf<T>::row(lane, r);
-        const int64_t p = p0 + pt * 16 + (lane & 15);
+        const int64_t p = p0 + geo.off(pt * 16 + (lane & 15));
         acc[pt][r] = (s < ncol && p < nd) ? Y[(int64_t)s * ld + p] : T(0);
       }
     const int64_t jo = boff[sbk];
@@ -360,7 +377,7 @@ __device__ __forceinline__ void fused_real(T* __restrict__ Y, int64_t ld, int nc
     for (int pt = 0; pt < 4; ++pt)
       for (int r = 0; r < 4; ++r) {
         const int sl = Mf<T>::row(lane, r);
-        const int64_t p = p0 + pt * 16 + (lane & 15);
+        const int64_t p = p0 + geo.off(pt * 16 + (lane & 15));
         if (nj4 > 0 && s0 + sl < ncol && p < nd) Y[(int64_t)(s0 + sl) * ld + p] = acc[pt][r];
         yw[sl * RS + pt * 16 + (lane & 15)] = acc[pt][r];
       }
@@ -393,9 +410,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     T* __restrict__ Y, int64_t ld, int ncol, const int64_t* __restrict__ boff, const int* __restrict__ bnj,
     const int* __restrict__ bj, const T* __restrict__ bval, const T* __restrict__ Qt, int ldq, T alpha, int nbrick,
     const int64_t* __restrict__ pboff, const int* __restrict__ pbnj, const T* __restrict__ pbval,
-    const int64_t* __restrict__ pdest, T* __restrict__ part, int ldp, int64_t nd, int nst) {
+    const int64_t* __restrict__ pdest, T* __restrict__ part, int ldp, int64_t nd, int nst, const BrickGeo geo) {
   const unsigned lw = xcd_linear();   // 1-D grid: state tile fastest, then brick
-  fused_real<T, G, NT>(Y, ld, ncol, boff, bnj, bj, bval, Qt, ldq, alpha, nbrick, pboff, pbnj, pbval, pdest, part,
+  fused_real<T, G, NT>(geo, Y, ld, ncol, boff, bnj, bj, bval, Qt, ldq, alpha, nbrick, pboff, pbnj, pbval, pdest, part,
                        ldp, nd, lw / nst, lw % nst);
 }
 
@@ -418,7 +435,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const unsigned lw = xcd_linear();
   const FusedJob& J = fused_job(jobs, njob, lw);
   const unsigned local = lw - J.item0;
-  fused_real<T, G, NT>((T*)J.Y, J.ld, J.ncol, J.boff, J.bnj, J.bj, (const T*)J.bval, (const T*)J.Qt, J.ldq,
+  fused_real<T, G, NT>(J.geo, (T*)J.Y, J.ld, J.ncol, J.boff, J.bnj, J.bj, (const T*)J.bval, (const T*)J.Qt, J.ldq,
                        (T)J.alpha, J.nbrick, J.pboff, J.pbnj, (const T*)J.pbval, J.pdest, (T*)J.part, J.ldp, J.nd,
                        local / J.nst, local % J.nst);
 }
@@ -427,7 +444,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // four real products per step (k_nl_brick_c) and the projection's four
 // accumulators per slot tile (k_proj_brick_c); at most four slot tiles.
 template <typename R, int G, int NT>
-__device__ __forceinline__ void fused_cplx(cplx<R>* __restrict__ Y, int64_t ld, int ncol,
+__device__ __forceinline__ void fused_cplx(const BrickGeo& geo, cplx<R>* __restrict__ Y, int64_t ld, int ncol,
                                            const int64_t* __restrict__ boff, const int* __restrict__ bnj,
                                            const int* __restrict__ bj, const cplx<R>* __restrict__ bval,
                                            const cplx<R>* __restrict__ Qt, int ldq, R alpha, int nbrick,
@@ -457,13 +474,13 @@ __device__ __forceinline__ void fused_cplx(cplx<R>* __restrict__ Y, int64_t ld, 
   for (int k = 0; k < P; ++k) {
     const int sbk = b * P + k;
     if (sbk >= nbrick) break;   // uniform: the last brick of a ragged grid
-    const int64_t p0 = (int64_t)sbk * kBrick;
+    const int64_t p0 = geo.base(sbk);   // local index pt*16 + lane%16 at p0 + geo.off(...)
     // ---- scatter of brick sbk (k_nl_brick_c's steps)
     V ar[4], ai[4];
     for (int pt = 0; pt < 4; ++pt)
       for (int r = 0; r < 4; ++r) {
         const int s = s0 + Mf<R>::row(lane, r);
-        const int64_t p = p0 + pt * 16 + (lane & 15);
+        const int64_t p = p0 + geo.off(pt * 16 + (lane & 15));
         const C y = (s < ncol && p < nd) ? Y[(int64_t)s * ld + p] : C();
         ar[pt][r] = y.re;
         ai[pt][r] = y.im;
@@ -493,7 +510,7 @@ __device__ __forceinline__ void fused_cplx(cplx<R>* __restrict__ Y, int64_t ld, 
     for (int pt = 0; pt < 4; ++pt)
       for (int r = 0; r < 4; ++r) {
         const int sl = Mf<R>::row(lane, r);
-        const int64_t p = p0 + pt * 16 + (lane & 15);
+        const int64_t p = p0 + geo.off(pt * 16 + (lane & 15));
         const C v(ar[pt][r], ai[pt][r]);
         if (nj4 > 0 && s0 + sl < ncol && p < nd) Y[(int64_t)(s0 + sl) * ld + p] = v;
         yw[sl * RS + pt * 16 + (lane & 15)] = v;
@@ -533,9 +550,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     cplx<R>* __restrict__ Y, int64_t ld, int ncol, const int64_t* __restrict__ boff, const int* __restrict__ bnj,
     const int* __restrict__ bj, const cplx<R>* __restrict__ bval, const cplx<R>* __restrict__ Qt, int ldq, R alpha,
     int nbrick, const int64_t* __restrict__ pboff, const int* __restrict__ pbnj, const cplx<R>* __restrict__ pbval,
-    const int64_t* __restrict__ pdest, cplx<R>* __restrict__ part, int ldp, int64_t nd, int nst) {
+    const int64_t* __restrict__ pdest, cplx<R>* __restrict__ part, int ldp, int64_t nd, int nst,
+    const BrickGeo geo) {
   const unsigned lw = xcd_linear();
-  fused_cplx<R, G, NT>(Y, ld, ncol, boff, bnj, bj, bval, Qt, ldq, alpha, nbrick, pboff, pbnj, pbval, pdest, part,
+  fused_cplx<R, G, NT>(geo, Y, ld, ncol, boff, bnj, bj, bval, Qt, ldq, alpha, nbrick, pboff, pbnj, pbval, pdest, part,
                        ldp, nd, lw / nst, lw % nst);
 }
 
@@ -546,7 +564,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const unsigned lw = xcd_linear();
   const FusedJob& J = fused_job(jobs, njob, lw);
   const unsigned local = lw - J.item0;
-  fused_cplx<R, G, NT>((C*)J.Y, J.ld, J.ncol, J.boff, J.bnj, J.bj, (const C*)J.bval, (const C*)J.Qt, J.ldq,
+  fused_cplx<R, G, NT>(J.geo, (C*)J.Y, J.ld, J.ncol, J.boff, J.bnj, J.bj, (const C*)J.bval, (const C*)J.Qt, J.ldq,
                        (R)J.alpha, J.nbrick, J.pboff, J.pbnj, (const C*)J.pbval, J.pdest, (C*)J.part, J.ldp, J.nd,
                        local / J.nst, local % J.nst);
 }
@@ -573,7 +591,7 @@ void launch_scatter_project(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, co
       constexpr int G = decltype(g)::value, NT = decltype(nt)::value;
       launch_k(k_scatter_project<T, G, NT>, (unsigned)npb * nst, 256, 0, st, Y, ld, ncol, c.d_boff, c.d_bnj, c.d_bj,
                (const T*)c.d_bval[ik], Qt, c.p.ns, (T)alpha, nbrick, c.d_pboff, c.d_pbnj, (const T*)c.d_pbval[ik],
-               c.d_pdest, part, c.p.ns, c.nd, nst);
+               c.d_pdest, part, c.p.ns, c.nd, nst, c.geo);
     };
     using I2 = std::integral_constant<int, 2>;
     using I4 = std::integral_constant<int, 4>;
@@ -599,7 +617,7 @@ void launch_scatter_project(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, co
     if (part_sel & 1)
       launch_k(k_scatter_project_c<float, 2, 4>, (unsigned)npb * nst, 256, 0, st, Y, ld, ncol, c.d_boff, c.d_bnj,
                c.d_bj, (const T*)c.d_bval[ik], Qt, c.p.ns, (float)alpha, nbrick, c.d_pboff, c.d_pbnj,
-               (const T*)c.d_pbval[ik], c.d_pdest, part, c.p.ns, c.nd, nst);
+               (const T*)c.d_pbval[ik], c.d_pdest, part, c.p.ns, c.nd, nst, c.geo);
     if (part_sel & 2) {
       dim3 g2((ncol + 63) / 64, c.nproj);
       launch_k(k_slot_sum<T>, g2, 1024, 0, st, part, c.p.ns, ncol, c.d_jrow, P, c.nproj, c.dv);
@@ -630,6 +648,7 @@ template <typename T>
 FusedJob fused_job_of(const Ctx& c, int ik, T* Y, int64_t ld, int ncol, const T* Qt, double alpha, void* part,
                       unsigned item0) {
   FusedJob j{};
+  j.geo = c.geo;
   j.Y = Y; j.ld = ld; j.ncol = ncol; j.nst = (ncol + 63) / 64;
   j.boff = c.d_boff; j.bnj = c.d_bnj; j.bj = c.d_bj; j.bval = c.d_bval[ik];
   j.Qt = Qt; j.ldq = c.p.ns; j.alpha = alpha; j.nbrick = (int)c.boff.size() - 1;
@@ -686,10 +705,10 @@ void launch_project_table(const Ctx& c, const T* table, const T* Y, int ncol, in
     constexpr int G = decltype(g)::value;
     if constexpr (sizeof(T) == sizeof(typename real_of<T>::type))
       launch_k(k_proj_brick<T, G>, (unsigned)npb * nst, 256, 0, st, Y, ld, ncol, c.d_pboff, c.d_pbnj, table,
-               c.d_pdest, part, c.p.ns, c.nd, nst, vec);
+               c.d_pdest, part, c.p.ns, c.nd, nst, vec, c.geo);
     else
       launch_k(k_proj_brick_c<typename real_of<T>::type, G>, (unsigned)npb * nst, 256, 0, st, Y, ld, ncol,
-               c.d_pboff, c.d_pbnj, table, c.d_pdest, part, c.p.ns, c.nd, nst, vec);
+               c.d_pboff, c.d_pbnj, table, c.d_pdest, part, c.p.ns, c.nd, nst, vec, c.geo);
   };
   if (c.pgroup == 4) run(std::integral_constant<int, 4>());
   else run(std::integral_constant<int, 2>());

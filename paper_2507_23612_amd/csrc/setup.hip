@@ -200,17 +200,37 @@ hcu_status build_structure(Ctx& c) {
     std::sort(row.begin(), row.end());
     for (int t = a; t < e; ++t) { c.csr_col[t] = row[t - a].first; c.csr_src[t] = row[t - a].second; }
   }
-  // bricks of 64 consecutive points: the functions touching each brick,
-  // padded to a multiple of 4 (the MFMA depth)
-  const int nbrick = (c.nd + kBrick - 1) / kBrick;
+  // bricks of 64 points (4x4x4 blocks when the grid allows, else runs of
+  // 64 consecutive points): the functions touching each brick, padded to a
+  // multiple of 4 (the MFMA depth)
+  BrickGeo& geo = c.geo;
+  geo = BrickGeo{};
+  {
+    const int n1 = c.p.n[0], n2 = c.p.n[1], n3 = c.p.n[2];
+    // 8 x 8 x 1 blocks: 64-byte runs of FP64 values per state row (4 x 4 x 4
+    // cubes, denser still, leave 32-byte runs and were slower: the fused
+    // scatter + projection 0.99 -> 1.28 ms on c2, 4.45 -> 6.5 ms on c3)
+    (void)n3;
+    if (n1 % 8 == 0 && n2 % 8 == 0) { geo.cube = 1; geo.lx = 3; geo.ly = 3; geo.lz = 0; }
+    geo.n1 = n1;
+    geo.n12 = (int64_t)n1 * n2;
+    geo.nbx = n1 >> geo.lx;
+    geo.nby = geo.cube ? n2 >> geo.ly : 1;
+  }
+  const int nbrick = geo.cube ? c.nd / kBrick : (c.nd + kBrick - 1) / kBrick;
+  geo.nbrick = nbrick;
+  auto brick_point = [&](int b, int i) -> int64_t { return geo.base(b) + geo.off(i); };   // >= nd: outside
   c.boff.assign(nbrick + 1, 0);
   c.bnj.assign(nbrick, 0);
   c.bj.clear();
   std::vector<int> js;
   for (int b = 0; b < nbrick; ++b) {
-    const int p0 = b * kBrick, p1 = std::min(c.nd, p0 + kBrick);
     js.clear();
-    for (int t = c.csr_ptr[p0]; t < c.csr_ptr[p1]; ++t) js.push_back(c.csr_col[t]);
+    for (int i = 0; i < kBrick; ++i) {
+      const int64_t p = brick_point(b, i);
+      if (p >= c.nd) continue;
+      for (int t = c.csr_ptr[p]; t < c.csr_ptr[p + 1]; ++t) js.push_back(c.csr_col[t]);
+    }
     std::sort(js.begin(), js.end());
     js.erase(std::unique(js.begin(), js.end()), js.end());
     const int nj = (int)js.size();
@@ -223,20 +243,23 @@ hcu_status build_structure(Ctx& c) {
   for (int b = 0; b < nbrick; ++b) {
     const int* bjb = c.bj.data() + c.boff[b];
     const int nj = c.bnj[b];
-    const int p0 = b * kBrick, p1 = std::min(c.nd, p0 + kBrick);
-    for (int p = p0; p < p1; ++p)
+    for (int i = 0; i < kBrick; ++i) {
+      const int64_t p = brick_point(b, i);
+      if (p >= c.nd) continue;
       for (int t = c.csr_ptr[p]; t < c.csr_ptr[p + 1]; ++t) {
         const int jl = (int)(std::lower_bound(bjb, bjb + nj, c.csr_col[t]) - bjb);
-        c.bsrc[(c.boff[b] + jl) * kBrick + (p - p0)] = c.csr_src[t];
+        c.bsrc[(c.boff[b] + jl) * kBrick + i] = c.csr_src[t];
       }
+    }
   }
-  // projection bricks: the function list of each brick
+  // projection bricks (bricks 4b .. 4b+3): the function list of each brick
   // is padded to a multiple of 16 (one matrix-core tile), and the value tile
   // is stored in operand order [tile][64-point piece][step group i][lane][G]:
   // at steps G i .. G i + G-1 lane l of a wave holds row 16 tile + l%16 at
-  // the G consecutive points from piece*64 + 4G i + G (l/16), which is also
-  // the order in which the lane reads its state row.  G = 2 (16-byte groups
-  // in FP64 and complex FP32) unless every block is real FP32 (G = 4).
+  // the G local indices from 4G i + G (l/16) of the piece (consecutive in
+  // memory), which is also the order in which the lane reads its state row.
+  // G = 2 (16-byte groups in FP64 and complex FP32) unless every block is
+  // real FP32 (G = 4).
   c.pgroup = (c.mixed && !c.any_complex) ? 4 : 2;
   const int G = c.pgroup;
   c.pboff.assign(1, 0);
@@ -246,12 +269,17 @@ hcu_status build_structure(Ctx& c) {
   c.pdest.clear();
   c.jrow.assign(c.nproj + 1, 0);
   {
-    const int npb = (c.nd + kPBrick - 1) / kPBrick;
+    constexpr int P = kPBrick / kBrick;
+    const int npb = (nbrick + P - 1) / P;
     std::vector<int> pbj;   // padded slots, -1 for padding
     for (int b = 0; b < npb; ++b) {
-      const int p0 = b * kPBrick, p1 = std::min(c.nd, p0 + kPBrick);
       js.clear();
-      for (int t = c.csr_ptr[p0]; t < c.csr_ptr[p1]; ++t) js.push_back(c.csr_col[t]);
+      for (int piece = 0; piece < P && P * b + piece < nbrick; ++piece)
+        for (int i = 0; i < kBrick; ++i) {
+          const int64_t p = brick_point(P * b + piece, i);
+          if (p >= c.nd) continue;
+          for (int t = c.csr_ptr[p]; t < c.csr_ptr[p + 1]; ++t) js.push_back(c.csr_col[t]);
+        }
       std::sort(js.begin(), js.end());
       js.erase(std::unique(js.begin(), js.end()), js.end());
       const int nj = (int)js.size();
@@ -273,18 +301,19 @@ hcu_status build_structure(Ctx& c) {
     for (int b = 0; b < npb; ++b) {
       const int* jb = pbj.data() + c.pboff[b];
       const int nj = c.pbnj[b];
-      const int p0 = b * kPBrick, p1 = std::min(c.nd, p0 + kPBrick);
       const int64_t tile0 = c.pboff[b] / 16;
-      for (int p = p0; p < p1; ++p) {
-        const int pl = p - p0, piece = pl / 64, r = pl % 64;
-        const int i = r / (4 * G), q = (r % (4 * G)) / G, h = r % G;
-        for (int t = c.csr_ptr[p]; t < c.csr_ptr[p + 1]; ++t) {
-          const int jl = (int)(std::lower_bound(jb, jb + nj, c.csr_col[t]) - jb);
-          const int64_t lane = q * 16 + jl % 16;
-          const int64_t flat = ((((tile0 + jl / 16) * (kPBrick / 64) + piece) * (16 / G) + i) * 64 + lane) * G + h;
-          c.pbsrc[flat] = c.csr_src[t];
+      for (int piece = 0; piece < P && P * b + piece < nbrick; ++piece)
+        for (int r = 0; r < kBrick; ++r) {
+          const int64_t p = brick_point(P * b + piece, r);
+          if (p >= c.nd) continue;
+          const int i = r / (4 * G), q = (r % (4 * G)) / G, h = r % G;
+          for (int t = c.csr_ptr[p]; t < c.csr_ptr[p + 1]; ++t) {
+            const int jl = (int)(std::lower_bound(jb, jb + nj, c.csr_col[t]) - jb);
+            const int64_t lane = q * 16 + jl % 16;
+            const int64_t flat = ((((tile0 + jl / 16) * P + piece) * (16 / G) + i) * 64 + lane) * G + h;
+            c.pbsrc[flat] = c.csr_src[t];
+          }
         }
-      }
     }
   }
   return HCU_OK;

@@ -86,17 +86,22 @@ def test_cheb_filter_c2_fp64_fused_sampled_columns():
     assert err < 1e-11
 
 
-def test_cheb_filter_c3_mixed_fused_sampled_columns():
-    """108-atom cell, 108x108x96, 640 states (ten 64-state tiles), FP32
-    blocks: the fused kernel's eight-slot-tile variant (more than 64
-    functions touch some 256-point brick)."""
+@pytest.mark.parametrize("layout", ["runs", "blocks"])
+def test_cheb_filter_c3_mixed_fused_sampled_columns(layout):
+    """108-atom cell, 640 states (ten 64-state tiles), FP32 blocks, the
+    fused kernel's eight-slot-tile variant (more than 64 functions touch
+    some 256-point brick).  runs: grid 108x108x96 (108 is not a multiple of
+    8), bricks of 64 consecutive points; blocks: grid 112x112x96, bricks of
+    8x8x1 points (FP32 groups of four consecutive points)."""
     cfg = workloads.make_config("c3")
+    if layout == "blocks":
+        cfg["n"] = np.array([112, 112, 96], np.int32)
     nd = int(np.prod(cfg["n"]))
-    print("[gpu] filter c3 mixed full block (640 states), oracle on 4 columns", flush=True)
+    print(f"[gpu] filter c3 mixed full block (640 states, {layout}), oracle on 4 columns", flush=True)
     X = np.random.default_rng(32).random((cfg["ns"], nd), dtype=np.float32) - np.float32(0.5)
     cols = [3, 200, 411, 637]
     err, sizes = _run(cfg, "mixed", X, cols, 42)
-    print(f"[gpu] filter c3 mixed: rel err {err:.2e}, most functions per 256-point brick "
+    print(f"[gpu] filter c3 mixed ({layout}): rel err {err:.2e}, most functions per 256-point brick "
           f"{sizes['max_brick_functions']}", flush=True)
     assert sizes["max_brick_functions"] > 64      # the NT = 8 instantiation ran
     assert err < FP32_BAR
