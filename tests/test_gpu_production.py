@@ -151,3 +151,43 @@ def test_apply_h_lowdin_off_matches_oracle():
           f"(lowdin on differs by {np.max(np.abs(other - want)) / np.max(np.abs(want)):.2e})", flush=True)
     assert np.max(np.abs(other - want)) > 1e-6 * np.max(np.abs(want))
     assert err < 1e-12
+
+
+def test_scf_c2_matches_stored_oracle_scf():
+    """The full-size SCF (48 atoms, 72x72x96, 256 FP64 states, degree 16)
+    against the oracle's converged SCF of the same seeded inputs, stored by
+    tests/golden/make_scf_reference.py (oracle only): free energy within
+    1e-8 Ha/atom, E_U, the occupied and lowest empty Ritz values within
+    1e-8 Ha, D within 1e-6."""
+    import json
+    import os
+    torch = _torch()
+    from paper_2507_23612_amd import hcu
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "scf_reference_c2.json")
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle SCF for c2")
+    with open(path) as fh:
+        ref = json.load(fh)
+    cfg = workloads.make_config("c2")
+    print("[gpu] SCF c2 against the stored oracle SCF", flush=True)
+    ctx = hcu.HcuContext(cfg)
+    ctx.set_hubbard_occupation(hcu.initial_occupation(ctx, cfg))
+    X0, v0 = hcu.start_inputs(ctx, cfg)
+    ctx.set_start(0, 0, X0, v0)
+    del X0, v0
+    rep = ctx.scf()
+    e = ctx.get_energies()
+    lam = ctx.get_eigenvalues()[0, 0]
+    Dg = ctx.get_hubbard_occupation()[0]
+    ctx.close()
+    torch.cuda.empty_cache()
+    natom = ref["natom"]
+    print(f"[gpu] SCF c2: F gpu {e['F']:.12f} oracle {ref['F']:.12f}, iterations {rep['iterations']} vs "
+          f"{ref['iterations']}", flush=True)
+    assert rep["converged"] and ref["converged"]
+    assert abs(e["F"] - ref["F"]) / natom < 1e-8
+    assert abs(e["E_U"] - ref["E_U"]) < 1e-7
+    nocc = int(cfg["nelec"] / 2)
+    np.testing.assert_allclose(lam[:nocc + 8], np.asarray(ref["eigenvalues"])[:nocc + 8], atol=1e-8)
+    for h in range(len(ref["D"])):
+        np.testing.assert_allclose(Dg[h], np.asarray(ref["D"][h]), atol=1e-6)
