@@ -89,20 +89,41 @@ def generate(seeds, group=8, tol_d=1e-6, tol_f=1e-7, log=print):
     return np.concatenate(Xs).astype(np.float32), np.concatenate(Ts).astype(np.float32), cells
 
 
-def train(X, T, epochs=200, batch=256, lr=2e-3, seed=7, log=print):
+def standardised_error(m, X, T, chunk):
+    """Per-output mean squared error of the network's FP32 predictions in
+    the units of its own output scaling (the training loss's units); X is
+    fed in chunks of at most the network's batch capacity."""
+    import torch
+    _, _, out_mean, out_sd = m.get_scaling()
+    err = np.zeros(T.shape[1])
+    for r0 in range(0, X.shape[0], chunk):
+        Y = m.forward(torch.from_numpy(np.ascontiguousarray(X[r0:r0 + chunk])).cuda()).cpu().numpy()
+        err += (((Y - T[r0:r0 + chunk]) / out_sd) ** 2).sum(0)
+    return err / X.shape[0]
+
+
+def train(X, T, epochs=200, batch=256, lr=2e-3, seed=7, val_frac=0.1, log=print):
     """Train a fresh MLP (seeded initial parameters and batch order, both
-    drawn on the host) and return it with its loss history."""
+    drawn on the host) and return it with its loss history.  The last
+    val_frac of the rows (the last cells) is held back as a validation
+    split: the parameters of the epoch with the lowest validation loss are
+    kept (early stopping; longer training fits noise in the occupation
+    entries that the radial descriptor cannot predict)."""
     import torch
     import workloads
     from paper_2507_23612_amd import hcu
+    n_all = X.shape[0]
+    nv = int(round(n_all * val_frac)) // 8 * 8 if val_frac > 0 else 0   # whole cells (8 sites each)
+    Xt, Tt, Xv, Tv = X[:n_all - nv], T[:n_all - nv], X[n_all - nv:], T[n_all - nv:]
     m = hcu.HcuMlp(DIMS, max(batch, 64))
     m.set_params(workloads.mlp_init_params(seed, DIMS))
-    Xd = torch.from_numpy(X).cuda()
-    Td = torch.from_numpy(T).cuda()
+    Xd = torch.from_numpy(np.ascontiguousarray(Xt)).cuda()
+    Td = torch.from_numpy(np.ascontiguousarray(Tt)).cuda()
     m.fit_scaling(Xd, Td)
     rng = np.random.default_rng(seed)
-    n = X.shape[0]
-    hist = []
+    n = Xt.shape[0]
+    hist, vhist = [], []
+    best = (np.inf, None, -1)
     for ep in range(epochs):
         perm = rng.permutation(n).astype(np.int32)
         tot, cnt = 0.0, 0
@@ -111,8 +132,19 @@ def train(X, T, epochs=200, batch=256, lr=2e-3, seed=7, log=print):
             tot += m.train_step(Xd, Td, idx, lr=lr)
             cnt += 1
         hist.append(tot / max(cnt, 1))
+        if nv:
+            vl = float(standardised_error(m, Xv, Tv, max(batch, 64)).mean())
+            vhist.append(vl)
+            if vl < best[0]:
+                best = (vl, m.get_params(), ep)
         if log and (ep % 50 == 0 or ep == epochs - 1):
-            log(f"[mlguess] epoch {ep} loss {hist[-1]:.4e}", flush=True)
+            log(f"[mlguess] epoch {ep} loss {hist[-1]:.4e}" + (f" validation {vhist[-1]:.4e}" if nv else ""),
+                flush=True)
+    if nv:
+        m.set_params(best[1])
+        log(f"[mlguess] kept epoch {best[2]} (validation loss {best[0]:.4e})", flush=True)
+    m.train_info = {"validation_rows": nv, "best_epoch": best[2], "best_validation_loss": best[0],
+                    "validation_history": vhist}
     return m, hist
 
 
@@ -135,12 +167,15 @@ def compare(m, seeds, group=8, tol_d=1e-6, tol_f=1e-7, bf16=True, log=print):
         rl, tl = _scf_group(learned, tol_d, tol_f)
         for i, seed in enumerate(chunk):
             natom = len(cfgs[i]["atom_species"])
-            shells_true = base[i].site_targets()[:, 15:]
+            targets = base[i].site_targets()
+            shells_true = targets[:, 15:]
             out.append({"seed": int(seed), "it_atomic": int(rb[i]["iterations"]),
                         "it_learned": int(rl[i]["iterations"]),
                         "conv_atomic": bool(rb[i]["converged"]), "conv_learned": bool(rl[i]["converged"]),
                         "F_atomic": rb[i]["F"], "F_learned": rl[i]["F"],
                         "dF_per_atom": abs(rb[i]["F"] - rl[i]["F"]) / natom,
+                        "pred": np.asarray(pred[i], np.float64).tolist(),
+                        "target": np.asarray(targets, np.float64).tolist(),
                         "shell_rel_err": float(np.abs(pred[i][:, 15:] - shells_true).max()
                                                / np.abs(shells_true).max())})
         out[-1]["group_seconds_atomic"] = tb
@@ -168,6 +203,22 @@ def load_model(path, max_batch=64):
     return m
 
 
+def fit_summary(rows):
+    """Held-out fit of the BF16 predictions: R^2 per output group (against
+    the held-out variance of each output, averaged over the group) and the
+    rms error of the occupation-matrix entries."""
+    P = np.concatenate([np.asarray(r["pred"]) for r in rows])
+    T = np.concatenate([np.asarray(r["target"]) for r in rows])
+    r2 = 1.0 - ((P - T) ** 2).mean(0) / T.var(0)
+    diag = [0, 5, 9, 12, 14]                   # (m, m) entries of the row-major upper triangle of a 5x5 D
+    pooled = 1.0 - ((P[:, :15] - T[:, :15]) ** 2).sum() / (T[:, :15].var(0).sum() * P.shape[0])
+    return {"r2_D_mean": float(r2[:15].mean()), "r2_shells_mean": float(r2[15:].mean()),
+            "r2_D_diagonal_mean": float(r2[diag].mean()), "r2_D_pooled": float(pooled),
+            "r2_D": [float(v) for v in r2[:15]],
+            "rms_err_D": float(np.sqrt(((P[:, :15] - T[:, :15]) ** 2).mean())),
+            "rms_D_about_mean": float(np.sqrt(T[:, :15].var(0).mean()))}
+
+
 def summarise(rows):
     ia = np.array([r["it_atomic"] for r in rows], float)
     il = np.array([r["it_learned"] for r in rows], float)
@@ -189,6 +240,8 @@ def main():
     ap.add_argument("--seed0", type=int, default=TRAIN_SEED0, help="first training cell seed")
     ap.add_argument("--heldout", type=int, default=200, help="held-out cells (seeds 3000..)")
     ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--val-frac", type=float, default=0.1,
+                    help="fraction of the training cells held back for early stopping (0: none)")
     ap.add_argument("--gen-only", action="store_true", help="generate and save training data, then stop")
     ap.add_argument("--data", default=None,
                     help="comma-separated npz files with X, T from earlier runs (skips generation)")
@@ -215,14 +268,20 @@ def main():
             print(json.dumps({"data": gen}), flush=True)
             return
     t1 = time.perf_counter()
-    m, hist = train(X, T, epochs=args.epochs)
+    m, hist = train(X, T, epochs=args.epochs, val_frac=args.val_frac)
     t_train = time.perf_counter() - t1
     if args.save_model:
         save_model(m, args.save_model)
     rows = compare(m, list(range(HELDOUT_SEED0, HELDOUT_SEED0 + args.heldout))) if args.heldout > 0 else []
+    info = getattr(m, "train_info", {})
     res = {"data": gen, "train": {"samples": int(X.shape[0]), "epochs": args.epochs, "seconds": t_train,
-                                   "loss_first": hist[0], "loss_last": hist[-1]},
-           "heldout": summarise(rows) if rows else None, "rows": rows}
+                                   "loss_first": hist[0], "loss_last": hist[-1],
+                                   "validation_rows": info.get("validation_rows"),
+                                   "best_epoch": info.get("best_epoch"),
+                                   "best_validation_loss": info.get("best_validation_loss")},
+           "heldout": summarise(rows) if rows else None,
+           "heldout_fit": fit_summary(rows) if rows else None,
+           "rows": [{k: v for k, v in r.items() if k not in ("pred", "target")} for r in rows]}
     print(json.dumps({k: v for k, v in res.items() if k != "rows"}), flush=True)
     if args.out:
         with open(args.out, "w") as fh:

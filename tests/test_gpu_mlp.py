@@ -203,8 +203,15 @@ def test_learned_guess_beats_isolated_atom_start():
     from paper_2507_23612_amd import mlguess
     X, T, cells = mlguess.generate(list(range(1000, 1024)), group=8)
     assert X.shape == (24 * 8, 64) and T.shape == (24 * 8, 30)
-    m, hist = mlguess.train(X, T, epochs=150, batch=64)
+    m, hist = mlguess.train(X, T, epochs=150, batch=64, val_frac=0.0)
     assert hist[-1] < hist[0] / 2
+    # early stopping keeps the parameters of the best validation epoch
+    me, _ = mlguess.train(X, T, epochs=40, batch=64, val_frac=0.25)
+    info = me.train_info
+    assert info["validation_rows"] == 48 and 0 <= info["best_epoch"] < 40
+    assert info["best_validation_loss"] == min(info["validation_history"])
+    again = float(mlguess.standardised_error(me, X[-48:], T[-48:], 64).mean())
+    assert abs(again - info["best_validation_loss"]) < 1e-6 * info["best_validation_loss"]
     rows = mlguess.compare(m, list(range(3000, 3004)), group=4)
     s = mlguess.summarise(rows)
     print(f"[gpu] learned guess: {s}", flush=True)
