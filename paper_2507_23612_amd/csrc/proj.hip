@@ -335,6 +335,37 @@ __device__ __forceinline__ void fused_real(const BrickGeo& geo, T* __restrict__ 
   V pacc[NT];
   for (int t = 0; t < NT; ++t)
     for (int r = 0; r < 4; ++r) pacc[t][r] = T(0);
+  // FP64: the scatter bricks' table offsets and (padded) function counts,
+  // all P of them at once (clamped to the last brick; bricks past it are
+  // not used), and each brick's first-chunk function indices requested one
+  // brick ahead.  FP32 loads both where they are used: with its 64-function
+  // chunks the carried indices cost more scalar registers than the round
+  // trips they save (c3 measured slower).
+  constexpr bool kIdx = sizeof(T) == 8;
+  int64_t jo_k[P];
+  int nj4_k[P];
+  if constexpr (kIdx)
+    for (int k = 0; k < P; ++k) {
+      const int sbk = min(b * P + k, nbrick - 1);
+      jo_k[k] = boff[sbk];
+      nj4_k[k] = (bnj[sbk] + 3) & ~3;
+    }
+  // Function indices of a brick's first chunk: one per lane by a vector load
+  // (clamped inside the index array, which has a tail past the last brick),
+  // then the wave's own as uniform values.  The next brick's are requested
+  // while the current one is processed, so they arrive with the current
+  // brick's staging loads and are read out after its chunk loop.
+  constexpr int NJ = CH / 4;
+  auto chunk0_idx = [&](int k) -> int {
+    const int nc = min(CH, nj4_k[k]);
+    return bj[jo_k[k] + (lane < nc ? lane : max(nc - 1, 0))];
+  };
+  int jgs[NJ];
+  if constexpr (kIdx) {
+    const int v = chunk0_idx(0);
+    for (int i = 0; i < NJ; ++i) jgs[i] = __builtin_amdgcn_readlane(v, wave + 4 * i);
+  }
+  int bj_next = 0;
   for (int k = 0; k < P; ++k) {
     const int sbk = b * P + k;
     if (sbk >= nbrick) break;   // uniform: the last brick of a ragged grid
@@ -347,23 +378,44 @@ __device__ __forceinline__ void fused_real(const BrickGeo& geo, T* __restrict__ 
         const int64_t p = p0 + geo.off(pt * 16 + (lane & 15));
         acc[pt][r] = (s < ncol && p < nd) ? Y[(int64_t)s * ld + p] : T(0);
       }
-    const int64_t jo = boff[sbk];
-    const int nj4 = (bnj[sbk] + 3) & ~3;   // uniform over the workgroup
+    const int64_t jo = kIdx ? jo_k[k] : boff[sbk];
+    const int nj4 = kIdx ? nj4_k[k] : (bnj[sbk] + 3) & ~3;   // uniform over the workgroup
     const T* __restrict__ vb = bval + jo * kBrick;
+    if (kIdx && k + 1 < P) bj_next = chunk0_idx(k + 1);
     for (int c0 = 0; c0 < nj4; c0 += CH) {
       const int nc = min(CH, nj4 - c0);
+      // Every load of the chunk is issued before the first LDS write, from
+      // clamped in-range addresses, and out-of-range entries are zeroed by
+      // selection: conditional loads become branches, each closed by a wait
+      // for all outstanding loads, which serialises the chunk's round trips.
+      constexpr int NB = (sizeof(T) == 8 && NT > 4) ? 2 : 1;   // load batches (register budget)
+      constexpr int NI = CH / 4 / NB;
+      const int s = swg + lane;
+      const int sc = s < ncol ? s : ncol - 1;
       __syncthreads();   // earlier readers of the area (staging or transposition tiles) are done
-      for (int i = 0; i < CH / 4; ++i) {
-        const int fn = wave + 4 * i;   // wave-uniform
-        T qv = T(0), bv = T(0);
-        if (fn < nc) {
-          const int jg = bj[jo + c0 + fn];
-          const int s = swg + lane;
-          if (jg >= 0 && s < ncol) qv = alpha * Qt[(int64_t)jg * ldq + s];
-          bv = vb[(int64_t)(c0 + fn) * kBrick + lane];
+      for (int h = 0; h < NB; ++h) {
+        int jg[NI];
+        if (kIdx && c0 == 0) {
+          for (int i = 0; i < NI; ++i) jg[i] = jgs[h * NI + i];
+        } else {
+          for (int i = 0; i < NI; ++i) {
+            const int fn = wave + 4 * (h * NI + i);   // wave-uniform
+            jg[i] = bj[jo + c0 + (fn < nc ? fn : nc - 1)];
+          }
         }
-        sQ[fn * RS + lane] = qv;
-        sB[fn * RS + lane] = bv;
+        __builtin_amdgcn_sched_barrier(0);   // the index loads go out together
+        T qraw[NI], braw[NI];
+        for (int i = 0; i < NI; ++i) {
+          const int fn = wave + 4 * (h * NI + i);
+          qraw[i] = Qt[(int64_t)(jg[i] >= 0 ? jg[i] : 0) * ldq + sc];
+          braw[i] = vb[(int64_t)(c0 + (fn < nc ? fn : nc - 1)) * kBrick + lane];
+        }
+        __builtin_amdgcn_sched_barrier(0);   // and the value loads before any use
+        for (int i = 0; i < NI; ++i) {
+          const int fn = wave + 4 * (h * NI + i);
+          sQ[fn * RS + lane] = (fn < nc && jg[i] >= 0 && s < ncol) ? alpha * qraw[i] : T(0);
+          sB[fn * RS + lane] = fn < nc ? braw[i] : T(0);
+        }
       }
       __syncthreads();
       if (wave_ok)
@@ -373,6 +425,8 @@ __device__ __forceinline__ void fused_real(const BrickGeo& geo, T* __restrict__ 
           for (int pt = 0; pt < 4; ++pt) acc[pt] = Mf<T>::mfma(a, sB[fr + pt * 16 + (lane & 15)], acc[pt]);
         }
     }
+    if (kIdx && k + 1 < P)   // the next brick's chunk-0 indices (their load has completed)
+      for (int i = 0; i < NJ; ++i) jgs[i] = __builtin_amdgcn_readlane(bj_next, wave + 4 * i);
     __syncthreads();   // the staging area becomes the transposition tiles
     for (int pt = 0; pt < 4; ++pt)
       for (int r = 0; r < 4; ++r) {
@@ -398,9 +452,14 @@ __device__ __forceinline__ void fused_real(const BrickGeo& geo, T* __restrict__ 
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     if (t >= ntile) break;
+    int64_t dst[4];   // destination rows first (clamped), then the stores
     for (int r = 0; r < 4; ++r) {
       const int j = t * 16 + Mf<T>::row(lane, r);
-      if (j < njp && sa_ok) part[pdest[jop + j] * ldp + sa] = pacc[t][r];
+      dst[r] = pdest[jop + (j < njp ? j : njp - 1)];
+    }
+    for (int r = 0; r < 4; ++r) {
+      const int j = t * 16 + Mf<T>::row(lane, r);
+      if (j < njp && sa_ok) part[dst[r] * ldp + sa] = pacc[t][r];
     }
   }
 }
@@ -476,27 +535,45 @@ __device__ __forceinline__ void fused_cplx(const BrickGeo& geo, cplx<R>* __restr
     if (sbk >= nbrick) break;   // uniform: the last brick of a ragged grid
     const int64_t p0 = geo.base(sbk);   // local index pt*16 + lane%16 at p0 + geo.off(...)
     // ---- scatter of brick sbk (k_nl_brick_c's steps)
+    // Loads from clamped in-range addresses, zeroed by selection afterwards
+    // (a conditional load becomes a branch closed by a wait for every
+    // outstanding load, one round trip per value).
     V ar[4], ai[4];
-    for (int pt = 0; pt < 4; ++pt)
-      for (int r = 0; r < 4; ++r) {
-        const int s = s0 + Mf<R>::row(lane, r);
-        const int64_t p = p0 + geo.off(pt * 16 + (lane & 15));
-        const C y = (s < ncol && p < nd) ? Y[(int64_t)s * ld + p] : C();
-        ar[pt][r] = y.re;
-        ai[pt][r] = y.im;
-      }
+    {
+      C yv[4][4];
+      for (int pt = 0; pt < 4; ++pt)
+        for (int r = 0; r < 4; ++r) {
+          const int s = min(s0 + Mf<R>::row(lane, r), ncol - 1);
+          const int64_t p = min(p0 + geo.off(pt * 16 + (lane & 15)), nd - 1);
+          yv[pt][r] = Y[(int64_t)s * ld + p];
+        }
+      for (int pt = 0; pt < 4; ++pt)
+        for (int r = 0; r < 4; ++r) {
+          const bool in = s0 + Mf<R>::row(lane, r) < ncol && p0 + geo.off(pt * 16 + (lane & 15)) < nd;
+          ar[pt][r] = in ? yv[pt][r].re : R(0);
+          ai[pt][r] = in ? yv[pt][r].im : R(0);
+        }
+    }
     const int64_t jo = boff[sbk];
     const int nj4 = (bnj[sbk] + 3) & ~3;
     const C* __restrict__ vb = bval + jo * kBrick;
-    int bjl = -1;   // function indices 64 at a time, passed between lanes
+    // Function indices 64 at a time, passed between lanes (the index array
+    // has a 64-entry tail, so the unguarded load stays inside it); a step's
+    // Q and table loads go out together and Q is zeroed at its use.
+    const int sac = sa_ok ? sa : ncol - 1;
+    int bjl = -1;
     for (int jj = 0; jj < nj4; jj += 4) {
-      if ((jj & 63) == 0) bjl = jj + lane < nj4 ? bj[jo + jj + lane] : -1;
+      if ((jj & 63) == 0) {
+        const int v = bj[jo + jj + lane];
+        bjl = jj + lane < nj4 ? v : -1;
+      }
       const int jl = jj + (lane >> 4);
       const int jg = __shfl(bjl, jl & 63);
-      const C qv = (sa_ok && jg >= 0) ? Qt[(int64_t)jg * ldq + sa] : C();
-      const R qr = alpha * qv.re, qi = alpha * qv.im;
+      const C qraw = Qt[(int64_t)(jg >= 0 ? jg : 0) * ldq + sac];
       C f[4];
       for (int pt = 0; pt < 4; ++pt) f[pt] = vb[(int64_t)jl * kBrick + pt * 16 + (lane & 15)];
+      const bool qok = sa_ok && jg >= 0;
+      const R qr = qok ? alpha * qraw.re : R(0), qi = qok ? alpha * qraw.im : R(0);
       for (int pt = 0; pt < 4; ++pt) {
         ar[pt] = Mf<R>::mfma(qr, f[pt].re, ar[pt]);
         ai[pt] = Mf<R>::mfma(qr, f[pt].im, ai[pt]);

@@ -239,6 +239,8 @@ hcu_status build_structure(Ctx& c) {
     c.boff[b + 1] = c.boff[b] + njp;
     for (int t = 0; t < njp; ++t) c.bj.push_back(t < nj ? js[t] : -1);
   }
+  // a tail past the last brick: a kernel may read a clamped index there
+  c.bj.insert(c.bj.end(), 64, -1);
   c.bsrc.assign((size_t)c.boff[nbrick] * kBrick, -1);
   for (int b = 0; b < nbrick; ++b) {
     const int* bjb = c.bj.data() + c.boff[b];
