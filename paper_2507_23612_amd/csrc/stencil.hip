@@ -64,25 +64,33 @@ template <typename R> __device__ inline void stv(gptr<cplx<R>> p, int64_t i, cpl
   q[2 * i + 1] = v.im;
 }
 
-template <typename T> struct Ld {
-  // value of the (possibly wrapped) node with wrap counts w (each -1, 0, 1)
-  template <typename RT, typename PT>
-  __device__ static inline T get(PT y, int64_t idx, int wx, int wy, int wz, const KArgs<RT>&) {
+// Bloch factor of a node reached with wrap counts w (each -1, 0, 1) applied
+// to its value: identity for real blocks.
+template <typename T> struct Ph {
+  template <typename RT>
+  __device__ static inline T apply(T v, int wx, int wy, int wz, const KArgs<RT>&) {
     (void)wx; (void)wy; (void)wz;
-    return ldv(y, idx);
+    return v;
   }
 };
-template <typename R> struct Ld<cplx<R>> {
-  template <typename RT, typename PT>
-  __device__ static inline cplx<R> get(PT y, int64_t idx, int wx, int wy, int wz, const KArgs<RT>& a) {
-    cplx<R> v = ldv(y, idx);
-    int w[3] = {wx, wy, wz};
+template <typename R> struct Ph<cplx<R>> {
+  template <typename RT>
+  __device__ static inline cplx<R> apply(cplx<R> v, int wx, int wy, int wz, const KArgs<RT>& a) {
+    // the phase first, then one product (by 1 for an unwrapped node)
+    cplx<R> ph(R(1), R(0));
+    const int w[3] = {wx, wy, wz};
     for (int d = 0; d < 3; ++d) {
-      if (w[d] == 0) continue;
-      cplx<R> ph(a.ph_re[d], w[d] > 0 ? a.ph_im[d] : -a.ph_im[d]);
-      for (int t = 0; t < (w[d] > 0 ? w[d] : -w[d]); ++t) v = v * ph;
+      const cplx<R> f(a.ph_re[d], w[d] > 0 ? a.ph_im[d] : -a.ph_im[d]);
+      for (int t = 0; t < (w[d] > 0 ? w[d] : -w[d]); ++t) ph = ph * f;
     }
-    return v;
+    return v * ph;
+  }
+};
+// value of the (possibly wrapped) node
+template <typename T> struct Ld {
+  template <typename RT, typename PT>
+  __device__ static inline T get(PT y, int64_t idx, int wx, int wy, int wz, const KArgs<RT>& a) {
+    return Ph<T>::apply(ldv(y, idx), wx, wy, wz, a);
   }
 };
 
@@ -145,7 +153,7 @@ __device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T*
   int h_xy[NHS], h_lds[NHS], h_w[NHS];
   for (int k = 0; k < NHS; ++k) {
     const int e = tid + k * nthr;
-    h_lds[k] = -1; h_xy[k] = 0; h_w[k] = 0;
+    h_lds[k] = -1; h_xy[k] = 0; h_w[k] = 4 * 16 + 4;   // unused: node 0, no wrap
     if (e >= nh) continue;
     int row, col, hx, hy, wx, wy;
     if (e < nyh) {
@@ -175,44 +183,46 @@ __device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T*
       q[r][dz + R] = Ld<T>::get(Ys, gx + (int64_t)n1 * gy[r] + plane * gz, wxo, wyo[r], wz, a);
   }
   // stage plane zbeg
-  auto stage = [&](T* buf, const T* hreg) {
+  // Halo values are loaded raw and take their Bloch factor when staged
+  // (hwz: the plane's z wrap count): a product right after the loads would
+  // make the wave wait for them before computing the current plane.
+  auto stage = [&](T* buf, const T* hreg, int hwz) {
     for (int r = 0; r < RY; ++r) {
       const int row = ty * RY + r + R;
       const T v = q[r][R];
       buf[row * SW + tx + R] = v;
       if (xfull) {
-        if (tx < R) buf[row * SW + tx + n1 + R] = Ld<T>::get(&v, 0, 1, 0, 0, a);
-        if (tx >= n1 - R) buf[row * SW + tx - n1 + R] = Ld<T>::get(&v, 0, -1, 0, 0, a);
+        if (tx < R) buf[row * SW + tx + n1 + R] = Ph<T>::apply(v, 1, 0, 0, a);
+        if (tx >= n1 - R) buf[row * SW + tx - n1 + R] = Ph<T>::apply(v, -1, 0, 0, a);
       }
     }
     for (int k = 0; k < NHS; ++k)
-      if (h_lds[k] >= 0) buf[h_lds[k]] = hreg[k];
+      if (h_lds[k] >= 0) buf[h_lds[k]] = Ph<T>::apply(hreg[k], h_w[k] / 16 - 4, h_w[k] % 16 - 4, hwz, a);
   };
   T hreg[NHS];
   {
     int wz;
     const int gz = wrap(zbeg + zsh, n3, wz);
-    for (int k = 0; k < NHS; ++k)
-      if (h_lds[k] >= 0)
-        hreg[k] = Ld<T>::get(Ys, h_xy[k] + plane * gz, h_w[k] / 16 - 4, h_w[k] % 16 - 4, wz, a);
+    // unused slots load node 0 of the plane too (never staged): a guarded
+    // load would end in a wait before the next one issues
+    for (int k = 0; k < NHS; ++k) hreg[k] = ldv(Ys, h_xy[k] + plane * gz);
+    stage(buf0, hreg, wz);
   }
-  stage(buf0, hreg);
   __syncthreads();
 
   int cur = 0;
   for (int z = zbeg; z < zend; ++z) {
     const bool more = z + 1 < zend;
     // prefetch: next plane's halo and queue head, this plane's V and Yprev
+    // (raw values: the queue head takes its Bloch factor when it enters the
+    // queue, the halo when staged)
     T qn[RY];
+    int wzn = 0;
     if (more) {
-      int wz;
-      const int gz = wrap(z + 1 + R + zsh, n3, wz);
-      for (int r = 0; r < RY; ++r)
-        qn[r] = Ld<T>::get(Ys, gx + (int64_t)n1 * gy[r] + plane * gz, wxo, wyo[r], wz, a);
+      const int gz = wrap(z + 1 + R + zsh, n3, wzn);
+      for (int r = 0; r < RY; ++r) qn[r] = ldv(Ys, gx + (int64_t)n1 * gy[r] + plane * gz);
       const int zh = z + 1 + zsh - (z + 1 + zsh >= n3 ? n3 : 0);
-      for (int k = 0; k < NHS; ++k)
-        if (h_lds[k] >= 0)
-          hreg[k] = Ld<T>::get(Ys, h_xy[k] + plane * zh, h_w[k] / 16 - 4, h_w[k] % 16 - 4, 0, a);
+      for (int k = 0; k < NHS; ++k) hreg[k] = ldv(Ys, h_xy[k] + plane * zh);   // unused slots: node 0
     }
     const int64_t zoff = plane * (z + zsh - (z + zsh >= n3 ? n3 : 0));
     RT vv[RY];
@@ -248,9 +258,9 @@ __device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T*
     }
     for (int r = 0; r < RY; ++r) {
       for (int t = 0; t < 2 * R; ++t) q[r][t] = q[r][t + 1];
-      if (more) q[r][2 * R] = qn[r];
+      if (more) q[r][2 * R] = Ph<T>::apply(qn[r], wxo, wyo[r], wzn, a);
     }
-    if (more) stage(cur ? buf0 : buf1, hreg);
+    if (more) stage(cur ? buf0 : buf1, hreg, 0);
     __syncthreads();
     cur ^= 1;
   }
