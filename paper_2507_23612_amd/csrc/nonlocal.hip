@@ -109,22 +109,40 @@ __global__ __launch_bounds__(256) void k_nl_brick_c(cplx<R>* __restrict__ Y, int
   const bool sa_ok = sa < ncol;
   const int64_t p0 = geo.base(b);   // local index pt*16 + lane%16 at p0 + geo.off(...)
   const cplx<R>* __restrict__ vb = bval + jo * kBrick;
+  // Loads from clamped in-range addresses, zeroed by selection afterwards:
+  // a conditional load becomes a branch that waits for every outstanding
+  // load before the next one issues.
   V ar[4], ai[4];
-  for (int pt = 0; pt < 4; ++pt)
-    for (int q = 0; q < 4; ++q) {
-      const int s = s0 + Mf<R>::row(lane, q);
-      const int64_t p = p0 + geo.off(pt * 16 + (lane & 15));
-      const cplx<R> y = (s < ncol && p < nd) ? Y[(int64_t)s * ld + p] : cplx<R>();
-      ar[pt][q] = y.re;
-      ai[pt][q] = y.im;
-    }
-  int bjl = -1;   // function indices 64 at a time, passed between lanes
+  {
+    cplx<R> yv[4][4];
+    for (int pt = 0; pt < 4; ++pt)
+      for (int q = 0; q < 4; ++q) {
+        const int s = min(s0 + Mf<R>::row(lane, q), ncol - 1);
+        const int64_t p = min(p0 + geo.off(pt * 16 + (lane & 15)), nd - 1);
+        yv[pt][q] = Y[(int64_t)s * ld + p];
+      }
+    for (int pt = 0; pt < 4; ++pt)
+      for (int q = 0; q < 4; ++q) {
+        const bool in = s0 + Mf<R>::row(lane, q) < ncol && p0 + geo.off(pt * 16 + (lane & 15)) < nd;
+        ar[pt][q] = in ? yv[pt][q].re : R(0);
+        ai[pt][q] = in ? yv[pt][q].im : R(0);
+      }
+  }
+  // function indices 64 at a time, passed between lanes (the index array has
+  // a 64-entry tail, so the unguarded load stays inside it); Q is zeroed at
+  // its use, so a step's loads go out together
+  const int sac = sa_ok ? sa : ncol - 1;
+  int bjl = -1;
   for (int jj = 0; jj < nj4; jj += 4) {
-    if ((jj & 63) == 0) bjl = jj + lane < nj4 ? bj[jo + jj + lane] : -1;
+    if ((jj & 63) == 0) {
+      const int v = bj[jo + jj + lane];
+      bjl = jj + lane < nj4 ? v : -1;
+    }
     const int jl = jj + (lane >> 4);
     const int jg = __shfl(bjl, jl & 63);
-    const cplx<R> qv = (sa_ok && jg >= 0) ? Qt[(int64_t)jg * ldq + sa] : cplx<R>();
-    const R qr = alpha * qv.re, qi = alpha * qv.im;
+    const cplx<R> qraw = Qt[(int64_t)(jg >= 0 ? jg : 0) * ldq + sac];
+    const bool qok = sa_ok && jg >= 0;
+    const R qr = qok ? alpha * qraw.re : R(0), qi = qok ? alpha * qraw.im : R(0);
     cplx<R> f[4];
     for (int pt = 0; pt < 4; ++pt) f[pt] = vb[(int64_t)jl * kBrick + pt * 16 + (lane & 15)];
     // independent accumulators between dependent matrix-core ops

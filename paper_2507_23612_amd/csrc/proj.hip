@@ -141,9 +141,14 @@ __global__ __launch_bounds__(256) void k_proj_brick(const T* __restrict__ Y, int
       }
       for (int t = 0; t < 4; ++t) {
         if (jg + t >= ntile) break;
+        int64_t dst[4];   // destination rows first (clamped), then the stores
         for (int r = 0; r < 4; ++r) {
           const int j = (jg + t) * 16 + Mf<T>::row(lane, r);
-          if (j < nj && sb < ncol) part[pdest[jo + j] * ldp + sb] = acc[t][r];
+          dst[r] = pdest[jo + (j < nj ? j : nj - 1)];
+        }
+        for (int r = 0; r < 4; ++r) {
+          const int j = (jg + t) * 16 + Mf<T>::row(lane, r);
+          if (j < nj && sb < ncol) part[dst[r] * ldp + sb] = acc[t][r];
         }
       }
     }
@@ -170,11 +175,17 @@ __global__ __launch_bounds__(256) void k_proj_brick(const T* __restrict__ Y, int
           for (int kk = 0; kk < 16; ++kk) acc[0][kk & 1] = Mf<T>::mfma(a0[kk], bk[kk], acc[0][kk & 1]);
         }
       }
-      for (int t = 0; t < (two ? 2 : 1); ++t)
+      for (int t = 0; t < (two ? 2 : 1); ++t) {
+        int64_t dst[4];   // destination rows first (clamped), then the stores
         for (int r = 0; r < 4; ++r) {
           const int j = (jg + t) * 16 + Mf<T>::row(lane, r);
-          if (j < nj && sb < ncol) part[pdest[jo + j] * ldp + sb] = acc[t][0][r] + acc[t][1][r];
+          dst[r] = pdest[jo + (j < nj ? j : nj - 1)];
         }
+        for (int r = 0; r < 4; ++r) {
+          const int j = (jg + t) * 16 + Mf<T>::row(lane, r);
+          if (j < nj && sb < ncol) part[dst[r] * ldp + sb] = acc[t][0][r] + acc[t][1][r];
+        }
+      }
     }
   }
 }
@@ -223,9 +234,14 @@ __global__ __launch_bounds__(256) void k_proj_brick_c(const cplx<R>* __restrict_
         c3 = Mf<R>::mfma(f[kk].im, y[kk].re, c3);
       }
     }
+    int64_t dst[4];   // destination rows first (clamped), then the stores
     for (int r = 0; r < 4; ++r) {
       const int j = jt * 16 + Mf<R>::row(lane, r);
-      if (j < nj && sb < ncol) part[pdest[jo + j] * ldp + sb] = cplx<R>(c0[r] + c1[r], c2[r] - c3[r]);
+      dst[r] = pdest[jo + (j < nj ? j : nj - 1)];
+    }
+    for (int r = 0; r < 4; ++r) {
+      const int j = jt * 16 + Mf<R>::row(lane, r);
+      if (j < nj && sb < ncol) part[dst[r] * ldp + sb] = cplx<R>(c0[r] + c1[r], c2[r] - c3[r]);
     }
   }
 }
@@ -614,10 +630,14 @@ __device__ __forceinline__ void fused_cplx(const BrickGeo& geo, cplx<R>* __restr
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     if (t >= ntile) break;
+    int64_t dst[4];   // destination rows first (clamped), then the stores
     for (int r = 0; r < 4; ++r) {
       const int j = t * 16 + Mf<R>::row(lane, r);
-      if (j < njp && sa_ok)
-        part[pdest[jop + j] * ldp + sa] = C(pc[t][0][r] + pc[t][1][r], pc[t][2][r] - pc[t][3][r]);
+      dst[r] = pdest[jop + (j < njp ? j : njp - 1)];
+    }
+    for (int r = 0; r < 4; ++r) {
+      const int j = t * 16 + Mf<R>::row(lane, r);
+      if (j < njp && sa_ok) part[dst[r] * ldp + sa] = C(pc[t][0][r] + pc[t][1][r], pc[t][2][r] - pc[t][3][r]);
     }
   }
 }
