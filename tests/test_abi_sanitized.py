@@ -100,7 +100,9 @@ def test_host_code_clean_under_asan_and_ubsan():
     if rt is None:
         pytest.skip("sanitizer runtime not found")
     env = dict(os.environ)
-    env["LD_PRELOAD"] = rt
+    # the runtime goes first (it must initialise before anything it
+    # instruments); whatever the environment already preloads stays loaded
+    env["LD_PRELOAD"] = rt + (":" + env["LD_PRELOAD"] if env.get("LD_PRELOAD") else "")
     # the interpreter itself is not instrumented: its allocations are not
     # leak-checked; every other report stops the child
     env["ASAN_OPTIONS"] = "detect_leaks=0:halt_on_error=1:abort_on_error=0:exitcode=86"
