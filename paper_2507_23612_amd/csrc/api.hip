@@ -421,7 +421,7 @@ hcu_status rr_t(Ctx& c, int sk, T* Y, T* HY) {
   }
   launch_convert_c<T>(c.d_Hs, (T*)c.d_Cb, ns, cp ? 1 : 0, c.stream);
   {
-    ProfScope ps(c, PK_ROTATE);
+    ProfScope ps(c, PK_ROTATE, true);   // a library call for real blocks
     launch_rotate<T>(c, Y, nd, (const T*)c.d_Cb, X, ns, c.stream);
   }
   if (c.nproj > 0) launch_rotate_proj<T>(c, (const T*)c.d_PY[sk], (const T*)c.d_Cb, (T*)c.d_PX[sk], ns, c.stream);
