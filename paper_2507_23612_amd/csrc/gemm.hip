@@ -616,6 +616,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 
 template <typename T>
 void launch_rotate_c(const Ctx& c, const T* Y, int64_t ld, const T* Cb, T* X, int ncol, hipStream_t st) {
+  // X_c = Y_c C (no conjugation) as a plain complex GEMM through the vendor
+  // library, as for real blocks; the kernels below without a handle
+  if (c.blas && c.nd <= INT32_MAX && ld <= INT32_MAX) {
+    rocblas_set_stream(c.blas, st);
+    rocblas_status r;
+    if constexpr (std::is_same<T, cplx<float>>::value) {
+      using B = rocblas_float_complex;
+      const B one{1.0f, 0.0f}, zero{0.0f, 0.0f};
+      r = rocblas_cgemm(c.blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)c.nd, ncol, ncol, &one,
+                        reinterpret_cast<const B*>(Y), (rocblas_int)ld, reinterpret_cast<const B*>(Cb), ncol, &zero,
+                        reinterpret_cast<B*>(X), (rocblas_int)ld);
+    } else {
+      using B = rocblas_double_complex;
+      const B one{1.0, 0.0}, zero{0.0, 0.0};
+      r = rocblas_zgemm(c.blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)c.nd, ncol, ncol, &one,
+                        reinterpret_cast<const B*>(Y), (rocblas_int)ld, reinterpret_cast<const B*>(Cb), ncol, &zero,
+                        reinterpret_cast<B*>(X), (rocblas_int)ld);
+    }
+    if (r == rocblas_status_success) return;
+  }
   if constexpr (std::is_same<T, cplx<float>>::value) {
     dim3 grid((ncol + GT - 1) / GT, (unsigned)((c.nd + GT - 1) / GT));
     launch_k(k_rotate_cm<float>, grid, 256, 0, st, Y, ld, Cb, X, ncol, c.nd);
