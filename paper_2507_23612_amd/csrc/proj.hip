@@ -317,8 +317,10 @@ __global__ void k_couple(const T* __restrict__ P, const BlockDesc* __restrict__ 
 template <typename T> constexpr int kYsRow = kBrick + 16 / (int)sizeof(T);
 template <typename T> constexpr int kStageFns = sizeof(T) == 8 ? 32 : 64;   // functions staged per chunk
 
-// body of one workgroup: projection brick b, state tile st_
-template <typename T, int G, int NT>
+// body of one workgroup: projection brick b, state tile st_; DB: FP32 slot
+// tiles' table values double-buffered (off where the register budget has no
+// room: the multi-job kernel)
+template <typename T, int G, int NT, bool DB = true>
 __device__ __forceinline__ void fused_real(const BrickGeo& geo, T* __restrict__ Y, int64_t ld, int ncol,
                                            const int64_t* __restrict__ boff,
                                            const int* __restrict__ bnj, const int* __restrict__ bj,
@@ -456,13 +458,27 @@ __device__ __forceinline__ void fused_real(const BrickGeo& geo, T* __restrict__ 
     wave_lds_sync();   // every lane's writes of yw are visible
     T bk[16];
     load_piece<T, G>(yw + (lane & 15) * RS, 4 * G, G * q, 64, true, bk);
+    auto tab = [&](int t) { return pbval + (((jop / 16 + t) * P + k) * (16 / G)) * (64 * G) + lane * G; };
+    if constexpr (sizeof(T) == 4 && DB) {
+      // FP32: slot tile t+1's table values are requested before tile t's
+      // products (16 more registers, still three waves per SIMD), so the
+      // tiles' round trips to the table overlap instead of adding up
+      T a[2][16];
+      load_piece<T, G>(tab(0), 64 * G, 0, 64, true, a[0]);
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      if (t >= ntile) break;   // wave-uniform
-      T a[16];
-      load_piece<T, G>(pbval + (((jop / 16 + t) * P + k) * (16 / G)) * (64 * G) + lane * G, 64 * G, 0, 64, true,
-                       a);
-      for (int kk = 0; kk < 16; ++kk) pacc[t] = Mf<T>::mfma(a[kk], bk[kk], pacc[t]);
+      for (int t = 0; t < NT; ++t) {
+        if (t >= ntile) break;   // wave-uniform
+        if (t + 1 < ntile) load_piece<T, G>(tab(t + 1), 64 * G, 0, 64, true, a[(t + 1) & 1]);
+        for (int kk = 0; kk < 16; ++kk) pacc[t] = Mf<T>::mfma(a[t & 1][kk], bk[kk], pacc[t]);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if (t >= ntile) break;   // wave-uniform
+        T a[16];
+        load_piece<T, G>(tab(t), 64 * G, 0, 64, true, a);
+        for (int kk = 0; kk < 16; ++kk) pacc[t] = Mf<T>::mfma(a[kk], bk[kk], pacc[t]);
+      }
     }
   }
 #pragma unroll
@@ -510,7 +526,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const unsigned lw = xcd_linear();
   const FusedJob& J = fused_job(jobs, njob, lw);
   const unsigned local = lw - J.item0;
-  fused_real<T, G, NT>(J.geo, (T*)J.Y, J.ld, J.ncol, J.boff, J.bnj, J.bj, (const T*)J.bval, (const T*)J.Qt, J.ldq,
+  fused_real<T, G, NT, false>(J.geo, (T*)J.Y, J.ld, J.ncol, J.boff, J.bnj, J.bj, (const T*)J.bval, (const T*)J.Qt, J.ldq,
                        (T)J.alpha, J.nbrick, J.pboff, J.pbnj, (const T*)J.pbval, J.pdest, (T*)J.part, J.ldp, J.nd,
                        local / J.nst, local % J.nst);
 }
