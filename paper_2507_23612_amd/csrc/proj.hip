@@ -471,6 +471,25 @@ __device__ __forceinline__ void fused_real(const BrickGeo& geo, T* __restrict__ 
         if (t + 1 < ntile) load_piece<T, G>(tab(t + 1), 64 * G, 0, 64, true, a[(t + 1) & 1]);
         for (int kk = 0; kk < 16; ++kk) pacc[t] = Mf<T>::mfma(a[t & 1][kk], bk[kk], pacc[t]);
       }
+    } else if constexpr (DB && NT <= 4) {
+      // FP64: only the first half of each slot tile (steps 0-7) is
+      // double-buffered (16 registers, three waves per SIMD kept): tile t+1's
+      // first half is requested before tile t's products and each tile's
+      // second half at its start, covered by the products of the first half
+      constexpr int HG = 8 / G;   // load groups per half
+      auto half = [&](int t, int h, T* out) {
+        for (int i = 0; i < HG; ++i) ld_group<T, G>(tab(t) + (h * HG + i) * (64 * G), true, out + G * i);
+      };
+      T alo[2][8], ahi[8];
+      half(0, 0, alo[0]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if (t >= ntile) break;   // wave-uniform
+        half(t, 1, ahi);
+        if (t + 1 < ntile) half(t + 1, 0, alo[(t + 1) & 1]);
+        for (int kk = 0; kk < 8; ++kk) pacc[t] = Mf<T>::mfma(alo[t & 1][kk], bk[kk], pacc[t]);
+        for (int kk = 0; kk < 8; ++kk) pacc[t] = Mf<T>::mfma(ahi[kk], bk[8 + kk], pacc[t]);
+      }
     } else {
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
