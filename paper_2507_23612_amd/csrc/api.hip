@@ -87,7 +87,7 @@ size_t layout(Ctx& c, char* base, bool assign = true) {
   b.take(c.d_Cb, es * (size_t)ns * ns);
   b.take(c.d_lam, sizeof(double) * (size_t)nsk * ns);
   b.take(c.d_occ, sizeof(double) * (size_t)nsk * ns);
-  b.take(c.d_E, sizeof(double) * (size_t)ns * 2);
+  b.take(c.d_E, sizeof(double) * (size_t)ns * (c.any_complex ? 4 : 2));   // e, then tau (complex: 2 per entry)
   b.take(c.d_info, sizeof(int) * 4);
   std::vector<Ctx::RRSlot> slots((size_t)std::max(0, std::min(nsk, kRRLanes) - 1));
   for (size_t i = 0; i < slots.size(); ++i) {
@@ -97,7 +97,7 @@ size_t layout(Ctx& c, char* base, bool assign = true) {
     b.take(r.S, sizeof(double) * (size_t)ns * ns * cp);
     b.take(r.Hs, sizeof(double) * (size_t)ns * ns * cp);
     b.take(r.Cb, es * (size_t)ns * ns);
-    b.take(r.E, sizeof(double) * (size_t)ns * 2);
+    b.take(r.E, sizeof(double) * (size_t)ns * (c.any_complex ? 4 : 2));
     b.take(r.info, sizeof(int) * 4);
   }
   if (assign) c.rr_slots = slots;
@@ -242,11 +242,33 @@ hcu_status generalized_eig(Ctx& c, int n, bool cp, double* lam) {
     if (r == rocblas_status_success)
       r = rocblas_ztrsm(c.blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
                         rocblas_diagonal_non_unit, n, n, &one, S, n, A, n);
-    if (r == rocblas_status_success)
-      r = rocsolver_zheevd(c.blas, rocblas_evect_original, rocblas_fill_upper, n, A, n, lam, c.d_E, c.d_info + 1);
-    if (r == rocblas_status_success)
-      r = rocblas_ztrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
-                        rocblas_diagonal_non_unit, n, n, &one, S, n, A, n);
+    if (hetrd_small_ok(n) && c.part_elems >= 2 * (size_t)n * n) {
+      // tridiagonal form in one workgroup (eig.hip), then the library's
+      // divide and conquer into a complex eigenvector matrix (the Gram
+      // partials) and the back-transformation by the reflectors
+      auto* Z = (rocblas_double_complex*)c.d_part;
+      double* e = c.d_E;
+      auto* tau = (rocblas_double_complex*)(c.d_E + n);
+      if (r == rocblas_status_success)
+        launch_hetrd_small((cplx<double>*)c.d_Hs, n, n, lam, e, (cplx<double>*)tau, c.stream);
+      if (r == rocblas_status_success)
+        r = rocsolver_zstedc(c.blas, rocblas_evect_tridiagonal, n, lam, e, Z, n, c.d_info + 1);
+      if (r == rocblas_status_success)
+        r = rocsolver_zunmtr(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none, n, n, A, n, tau,
+                             Z, n);
+      if (r == rocblas_status_success)
+        r = rocblas_ztrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                          rocblas_diagonal_non_unit, n, n, &one, S, n, Z, n);
+      if (r == rocblas_status_success &&
+          hipMemcpyAsync(A, Z, 2 * sizeof(double) * n * n, hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
+        r = rocblas_status_internal_error;
+    } else {
+      if (r == rocblas_status_success)
+        r = rocsolver_zheevd(c.blas, rocblas_evect_original, rocblas_fill_upper, n, A, n, lam, c.d_E, c.d_info + 1);
+      if (r == rocblas_status_success)
+        r = rocblas_ztrsm(c.blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                          rocblas_diagonal_non_unit, n, n, &one, S, n, A, n);
+    }
   } else {
     const double one = 1.0;
     r = rocsolver_dpotrf(c.blas, rocblas_fill_upper, n, c.d_S, n, c.d_info);

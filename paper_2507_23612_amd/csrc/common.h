@@ -376,6 +376,8 @@ void fill_stencil_coef(const Ctx& c, int ik, StencilCoef& sc);
 // eig.hip: Householder tridiagonalization of the Rayleigh-Ritz matrix in one workgroup
 bool sytrd_small_ok(int n);
 void launch_sytrd_small(double* A, int n, int lda, double* d, double* e, double* tau, hipStream_t st);
+bool hetrd_small_ok(int n);
+void launch_hetrd_small(cplx<double>* A, int n, int lda, double* d, double* e, cplx<double>* tau, hipStream_t st);
 
 // hxc.hip: the density-dependent potential and the mixing of the density
 size_t hxc_spectrum_elems(const Ctx& c);

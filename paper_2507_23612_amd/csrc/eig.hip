@@ -369,7 +369,168 @@ __global__ __launch_bounds__(kRgThreads) void k_sytrd_reg(double* __restrict__ A
   if (t == 0) d[0] = colbuf[0] - 2.0 * v[0] * w[0];
 }
 
+// ---------------------------------------------------------------- Hermitian
+// Complex (Bloch) blocks: the same one-workgroup reduction of a Hermitian
+// matrix, H_i = I - tau v v^H with the complex tau of the standard Hermitian
+// reduction, which makes the superdiagonal beta real (beta = -sign(Re alpha)
+// |(alpha, x)|, tau = ((beta - Re alpha) / beta, -Im alpha / beta),
+// v = x / (alpha - beta); tau = 0 when x = 0 and alpha is real):
+//   p = A v,  w = tau p + alpha2 v,  alpha2 = -(tau / 2) (tau p)^H v,
+//   A -= v w^H + w v^H.
+// T is real (d, e); the reflectors stay in A's upper triangle as for real
+// blocks, so the library's divide and conquer (complex eigenvector matrix)
+// and back-transformation apply.
+using zc = cplx<double>;
+
+__device__ inline zc zc_div(zc a, zc b) {   // a / b (b != 0; scaled to avoid overflow)
+  const double s = fabs(b.re) + fabs(b.im);
+  const double br = b.re / s, bi = b.im / s;
+  const double den = br * br + bi * bi;
+  return {(a.re * br + a.im * bi) / (den * s), (a.im * br - a.re * bi) / (den * s)};
+}
+
+__device__ void hd_sweep(zc* __restrict__ A, int lda, int m, bool upd, const zc* v, const zc* w, const zc* vn,
+                         zc* part, zc* p) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nrb = (m + 63) >> 6;
+  const int g = kTdWaves / nrb;
+  const int rb = wv % nrb, cg = wv / nrb;
+  const int r = 64 * rb + lane;
+  zc acc;
+  if (cg < g && r < m) {
+    const zc vr = v[r], wr = w[r];
+    zc* col = A + r;
+    int c = cg;
+    for (; c + (kTdUnroll - 1) * g < m; c += kTdUnroll * g) {
+      zc a[kTdUnroll];
+#pragma unroll
+      for (int u = 0; u < kTdUnroll; ++u) a[u] = col[(int64_t)(c + u * g) * lda];
+#pragma unroll
+      for (int u = 0; u < kTdUnroll; ++u) {
+        const int cc = c + u * g;
+        if (upd) {
+          a[u] = a[u] - (vr * conj_(w[cc]) + wr * conj_(v[cc]));
+          col[(int64_t)cc * lda] = a[u];
+        }
+        acc += a[u] * vn[cc];
+      }
+    }
+    for (; c < m; c += g) {
+      zc a = col[(int64_t)c * lda];
+      if (upd) {
+        a = a - (vr * conj_(w[c]) + wr * conj_(v[c]));
+        col[(int64_t)c * lda] = a;
+      }
+      acc += a * vn[c];
+    }
+  }
+  part[wv * 64 + lane] = acc;
+  __syncthreads();
+  if (threadIdx.x < m) {
+    const int rr = threadIdx.x, b = rr >> 6, l = rr & 63;
+    zc s;
+    for (int k = 0; k < g; ++k) s += part[(k * nrb + b) * 64 + l];
+    p[rr] = s;
+  }
+  __syncthreads();
+}
+
+// Reflector of column c from the values x_r (r < len) held by threads r
+// (alpha = x_{len-1}); writes v (v[len-1] = 1), the scaled entries to
+// A(0:len-2, c), beta to A(len-1, c); tau and beta through sc.
+__device__ void hd_reflector(zc* __restrict__ A, int lda, int c, int len, zc xr, zc* vout, double* red,
+                             double* sc) {
+  const int t = threadIdx.x;
+  const double s2 = td_block_sum(t < len - 1 ? abs2_(xr) : 0.0, red);
+  if (t == len - 1) { sc[4] = xr.re; sc[5] = xr.im; }   // alpha
+  __syncthreads();
+  const zc alpha(sc[4], sc[5]);
+  zc tau, scale(1.0, 0.0);
+  double beta = alpha.re;
+  if (s2 > 0.0 || alpha.im != 0.0) {
+    const double nrm = sqrt(abs2_(alpha) + s2);
+    beta = alpha.re >= 0.0 ? -nrm : nrm;
+    tau = zc((beta - alpha.re) / beta, -alpha.im / beta);
+    scale = zc_div(zc(1.0, 0.0), alpha - zc(beta, 0.0));
+  }
+  const bool refl = tau.re != 0.0 || tau.im != 0.0;
+  if (t < len - 1) {
+    const zc x = refl ? xr * scale : xr;
+    A[t + (int64_t)c * lda] = x;
+    vout[t] = x;
+  } else if (t == len - 1) {
+    A[t + (int64_t)c * lda] = zc(beta, 0.0);
+    vout[t] = zc(1.0, 0.0);
+  }
+  if (t == 0) { sc[0] = tau.re; sc[1] = tau.im; sc[2] = beta; }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kTdThreads) void k_hetrd_small(zc* __restrict__ A, int n, int lda,
+                                                            double* __restrict__ d, double* __restrict__ e,
+                                                            zc* __restrict__ taus) {
+  // (the complex type has constructors: LDS is declared as doubles)
+  __shared__ __attribute__((aligned(16))) double lds_z[2 * (4 * kTdMaxN + kTdThreads)];
+  zc* const v = reinterpret_cast<zc*>(lds_z);
+  zc* const w = v + kTdMaxN;
+  zc* const vn = w + kTdMaxN;
+  zc* const p = vn + kTdMaxN;
+  zc* const part = p + kTdMaxN;
+  __shared__ double red[kTdWaves];
+  __shared__ double sc[8];
+  const int t = threadIdx.x;
+  // the lower triangle from the upper one, conjugated
+  for (int64_t q = t; q < (int64_t)n * n; q += kTdThreads) {
+    const int r = (int)(q % n), c = (int)(q / n);
+    if (r > c) A[r + (int64_t)c * lda] = conj_(A[c + (int64_t)r * lda]);
+  }
+  __syncthreads();
+  if (t == 0) d[n - 1] = A[(n - 1) + (int64_t)(n - 1) * lda].re;
+  if (n == 1) return;
+  {
+    const int len = n - 1;
+    const zc x = t < len ? A[t + (int64_t)(n - 1) * lda] : zc();
+    hd_reflector(A, lda, n - 1, len, x, v, red, sc);
+    hd_sweep(A, lda, len, false, v, v, v, part, p);
+  }
+  for (int i = n - 2; i >= 0; --i) {
+    // v, p = A(0:i,0:i) v and tau of step i are ready
+    const zc tau(sc[0], sc[1]);
+    const double beta = sc[2];
+    const zc wi = t <= i ? tau * p[t] : zc();
+    const zc pr = t <= i ? conj_(wi) * v[t] : zc();   // (tau p)^H v, term t
+    const double dre = td_block_sum(pr.re, red);
+    const double dim = td_block_sum(pr.im, red);
+    const zc a2 = (-0.5) * (tau * zc(dre, dim));
+    if (t <= i) w[t] = wi + a2 * v[t];
+    if (t == 0) { e[i] = beta; taus[i] = tau; }
+    __syncthreads();
+    const bool refl = tau.re != 0.0 || tau.im != 0.0;
+    if (i == 0) {
+      if (t == 0) d[0] = A[0].re - (refl ? 2.0 * (v[0] * conj_(w[0])).re : 0.0);
+      break;
+    }
+    // column i of the updated block (entries r < i) and its diagonal
+    zc xr;
+    if (t < i) {
+      xr = A[t + (int64_t)i * lda];
+      if (refl) xr = xr - (v[t] * conj_(w[i]) + w[t] * conj_(v[i]));
+    }
+    if (t == i) d[i] = A[i + (int64_t)i * lda].re - (refl ? 2.0 * (v[i] * conj_(w[i])).re : 0.0);
+    hd_reflector(A, lda, i, i, xr, vn, red, sc);
+    hd_sweep(A, lda, i, refl, v, w, vn, part, p);
+    if (t < i) v[t] = vn[t];
+    __syncthreads();
+  }
+}
+
 }  // namespace
+
+bool hetrd_small_ok(int n) { return n >= 1 && n <= kTdMaxN; }
+
+void launch_hetrd_small(cplx<double>* A, int n, int lda, double* d, double* e, cplx<double>* tau, hipStream_t st) {
+  launch_k(k_hetrd_small, 1, kTdThreads, 0, st, A, n, lda, d, e, tau);
+}
 
 bool sytrd_small_ok(int n) { return n >= 1 && n <= kTdMaxN; }
 
