@@ -160,7 +160,8 @@ typedef struct hcu_energies {
 
 /* Accumulated device time per kernel family, recorded only while profiling
  * is on: from the begin/end timestamps of the family's own kernel dispatches
- * (the eigensolve, made of library calls, from events around it).  Rayleigh-
+ * (the eigensolve and the rotation, which call the vendor libraries, from
+ * events around them).  Rayleigh-
  * Ritz steps of several blocks run side by side, so their times can add up
  * to more than the wall time.  For real and complex FP32 blocks the
  * projections of a Chebyshev step's output are computed in the scatter pass
@@ -170,8 +171,9 @@ typedef struct hcu_kernel_times {
   double stencil_ms;  long long stencil_launches;  /* stencil + V + Chebyshev step       */
   double project_ms;  long long project_launches;  /* projections onto atom functions    */
   double gram_ms;     long long gram_launches;     /* S, Hs contractions + reduction     */
-  double eig_ms;      long long eig_launches;      /* generalized eigensolve (rocSOLVER) */
-  double rotate_ms;   long long rotate_launches;   /* X = Y C                            */
+  double eig_ms;      long long eig_launches;      /* generalized eigensolve (one-workgroup
+                                                      tridiagonalization + rocSOLVER)   */
+  double rotate_ms;   long long rotate_launches;   /* X = Y C (rocBLAS GEMM)             */
   double scatter_ms;  long long scatter_launches;  /* projector scatter (KB + Hubbard)   */
   double fused_ms;    long long fused_launches;    /* of scatter: the fused scatter +
                                                       projection kernel alone           */
@@ -294,7 +296,8 @@ hcu_status hcu_lanczos_bounds(hcu_ctx* ctx, int spin, int ik, int steps,
 hcu_status hcu_gram(hcu_ctx* ctx, const void* Y, const void* HY, int ncol, int64_t ld, double* S, double* Hs);
 
 /* Subspace rotation X = Y C (device blocks, ld >= nd; C host, ncol x ncol
- * column-major doubles, complex interleaved at k != 0). */
+ * column-major doubles, complex interleaved at k != 0).  A plain GEMM: run
+ * by the vendor library (rocBLAS) on the context's stream. */
 hcu_status hcu_rotate(hcu_ctx* ctx, const void* Y, const double* C, void* X, int ncol, int64_t ld);
 
 /* Full SCF loop (Sec. II.B): per iteration, filter + Rayleigh-Ritz for every
