@@ -66,6 +66,21 @@ def stencil_bytes(cfg, elem):
     return nsk * (3 * elem * nd * ns + elem * nd)
 
 
+def parse_tile(text):
+    """TX,TYt,RY,TZ[,ring] -> (TX, TYt, RY, TZ, halo_ring)."""
+    parts = text.split(",")
+    ring = 1 if len(parts) == 5 and parts[4] == "ring" else 0
+    if len(parts) not in (4, 5) or (len(parts) == 5 and not ring):
+        raise SystemExit(f"--tile: expected TX,TYt,RY,TZ[,ring], got {text!r}")
+    return tuple(int(v) for v in parts[:4]) + (ring,)
+
+
+def tile_name(t):
+    """Tile shape as the counter records name it: TX,TYt,RY,TZ[,ring]."""
+    name = f'{t["tile_x"]},{t["tile_yt"]},{t["ry"]},{t["tile_z"]}'
+    return name + (",ring" if t.get("halo_ring") else "")
+
+
 def measured_traffic(kernel, config, prec, tile, sources):
     """HBM bytes per launch of `kernel` from the committed counter summaries
     profiles/<kernel>_<config>_<prec>*.md (FETCH_SIZE and WRITE_SIZE runs,
@@ -209,7 +224,7 @@ def bench_batch(args):
         if key not in tuned:                      # one autotuning per cell type
             tuned[key] = ctx.autotune()
         t = tuned[key]
-        ctx.set_tuning(t["tile_x"], t["tile_yt"], t["ry"], t["tile_z"])
+        ctx.set_tuning(t["tile_x"], t["tile_yt"], t["ry"], t["tile_z"], t["halo_ring"])
         ctx.lanczos_bounds()
         ctxs.append(ctx)
     work = sum(int(np.prod(c["n"])) * int(c["ns"]) * (int(c["degree"]) + 1) for c in cells)
@@ -262,7 +277,8 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (calibrates hardware byte counters)")
     ap.add_argument("--tile", default=None,
-                    help="stencil tile shape TX,TYt,RY,TZ (skips the autotuner, e.g. for profiling)")
+                    help="stencil tile shape TX,TYt,RY,TZ[,ring] (skips the autotuner, e.g. for profiling; "
+                         "ring: halo rows read with the queue head)")
     ap.add_argument("--scf-compare", action="store_true",
                     help="SCF wall time on held-out 24-atom cells: mixed precision with the learned start against "
                          "FP64 with the isolated-atom start (needs the trained site network)")
@@ -363,7 +379,7 @@ def measure_hxc(args, config, precision, tuning, hcu, torch):
     prec = precision or cfg["precision"]
     nd, ns = int(np.prod(cfg["n"])), int(cfg["ns"])
     ctx = hcu.HcuContext(cfg, prec)
-    ctx.set_tuning(tuning["tile_x"], tuning["tile_yt"], tuning["ry"], tuning["tile_z"])
+    ctx.set_tuning(tuning["tile_x"], tuning["tile_yt"], tuning["ry"], tuning["tile_z"], tuning["halo_ring"])
     ctx.set_hubbard_occupation(hcu.initial_occupation(ctx, cfg))
     for sp in range(ctx.nspin):
         for ik in range(ctx.nk):
@@ -424,9 +440,9 @@ def measure(args, config, precision, hcu, torch, top):
             del X0, v0
     torch.cuda.synchronize()
     if args.tile and top:
-        tx, tyt, ry, tz = (int(v) for v in args.tile.split(","))
-        ctx.set_tuning(tx, tyt, ry, tz)
-        tuning = {"tile_x": tx, "tile_yt": tyt, "ry": ry, "tile_z": tz, "stencil_ms": None}
+        tx, tyt, ry, tz, ring = parse_tile(args.tile)
+        ctx.set_tuning(tx, tyt, ry, tz, ring)
+        tuning = {"tile_x": tx, "tile_yt": tyt, "ry": ry, "tile_z": tz, "halo_ring": ring, "stencil_ms": None}
     else:
         tuning = ctx.autotune()
     ctx.scf_begin(first_passes=1)
@@ -448,7 +464,7 @@ def measure(args, config, precision, hcu, torch, top):
     bytes_launch = stencil_bytes(cfg, elem)
     st_ms = kt["stencil_ms"] / max(kt["stencil_launches"], 1)
     achieved = bytes_launch / (st_ms * 1e-3) / 1e9
-    tile = f'{tuning["tile_x"]},{tuning["tile_yt"]},{tuning["ry"]},{tuning["tile_z"]}'
+    tile = tile_name(tuning)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic("k_stencil", config, prec, tile, ("stencil.hip",)),
@@ -489,7 +505,7 @@ def measure(args, config, precision, hcu, torch, top):
 
     if top and not args.no_scf:
         ctx2 = hcu.HcuContext(cfg, prec)
-        ctx2.set_tuning(tuning["tile_x"], tuning["tile_yt"], tuning["ry"], tuning["tile_z"])
+        ctx2.set_tuning(tuning["tile_x"], tuning["tile_yt"], tuning["ry"], tuning["tile_z"], tuning["halo_ring"])
         ctx2.set_hubbard_occupation(hcu.initial_occupation(ctx2, cfg))
         for sp in range(ctx2.nspin):
             for ik in range(ctx2.nk):

@@ -379,12 +379,18 @@ hcu_status hcu_hubbard_stress(hcu_ctx* ctx, const double* occ, double* stress);
  * launch (autotune output). */
 typedef struct hcu_tuning {
   int tile_x, tile_yt, ry, tile_z;
+  int halo_ring;   /* 1: the y/x halo of a plane is read together with the
+                      tile's own queue head, R planes before the plane is
+                      computed, and held in an LDS ring of R planes (order-12
+                      stencil, at most 4 halo values per thread and 512
+                      threads, LDS within 160 KB) */
   double stencil_ms;
 } hcu_tuning;
-/* Time every admissible tile shape on the full orbital block of (spin 0,
- * k 0) (contents are not changed) and keep the fastest; tile_x = 0 in
+/* Time every admissible tile shape (with and without the halo ring) on the
+ * full orbital block of (spin 0, k 0) (contents are not changed) and keep
+ * the fastest; shapes the device cannot launch are skipped.  tile_x = 0 in
  * hcu_set_tuning restores the built-in choice.  Errors: HCU_INVALID_ARG for
- * a shape the grid does not admit. */
+ * a shape the grid does not admit, HCU_DEVICE if no shape launches. */
 hcu_status hcu_autotune(hcu_ctx* ctx, hcu_tuning* best);
 hcu_status hcu_set_tuning(hcu_ctx* ctx, const hcu_tuning* t);
 

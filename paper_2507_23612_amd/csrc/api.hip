@@ -1121,8 +1121,10 @@ hcu_status autotune_t(Ctx& c, hcu_tuning* best) {
         for (int zd : {1, 2, 4}) {
           const int tz = (n3 + zd - 1) / zd;
           if (zd > 1 && tz < 8) continue;
-          if (!stencil_shape_ok(c, TX, TYt, RY, tz)) continue;
-          cands.push_back(hcu_tuning{TX, TYt, RY, tz, 0.0});
+          for (int ring : {0, 1}) {
+            if (!stencil_shape_ok(c, TX, TYt, RY, tz, ring)) continue;
+            cands.push_back(hcu_tuning{TX, TYt, RY, tz, ring, 0.0});
+          }
         }
       }
     }
@@ -1133,10 +1135,13 @@ hcu_status autotune_t(Ctx& c, hcu_tuning* best) {
   double best_ms = 1e300;
   hcu_tuning bt = cands[0];
   for (hcu_tuning& t : cands) {
-    c.tile_x = t.tile_x; c.tile_yt = t.tile_yt; c.ry = t.ry; c.tile_z = t.tile_z;
+    c.tile_x = t.tile_x; c.tile_yt = t.tile_yt; c.ry = t.ry; c.tile_z = t.tile_z; c.halo_ring = t.halo_ring;
     launch_stencil<T>(c, 0, X, c.nd, Yp, c.nd, Y, c.nd, ns, 0.5, 1.0, 0.25, c.stream);
+    // a shape the device cannot launch (e.g. its LDS) is skipped
+    if (hipGetLastError() != hipSuccess) { t.stencil_ms = -1.0; continue; }
     HCU_HIP(hipEventRecord(e0, c.stream));
     for (int r = 0; r < 3; ++r) launch_stencil<T>(c, 0, X, c.nd, Yp, c.nd, Y, c.nd, ns, 0.5, 1.0, 0.25, c.stream);
+    HCU_HIP(hipGetLastError());
     HCU_HIP(hipEventRecord(e1, c.stream));
     HCU_HIP(hipEventSynchronize(e1));
     float ms = 0;
@@ -1146,7 +1151,8 @@ hcu_status autotune_t(Ctx& c, hcu_tuning* best) {
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  c.tile_x = bt.tile_x; c.tile_yt = bt.tile_yt; c.ry = bt.ry; c.tile_z = bt.tile_z;
+  if (best_ms == 1e300) return fail(c, HCU_DEVICE, "no stencil shape could be launched");
+  c.tile_x = bt.tile_x; c.tile_yt = bt.tile_yt; c.ry = bt.ry; c.tile_z = bt.tile_z; c.halo_ring = bt.halo_ring;
   if (best) *best = bt;
   return HCU_OK;
 }
@@ -1780,9 +1786,9 @@ hcu_status hcu_set_tuning(hcu_ctx* ctx, const hcu_tuning* t) {
   if (!ctx || !t) return HCU_INVALID_ARG;
   Ctx& c = *ctx;
   if (t->tile_x == 0) { c.tile_x = 0; return HCU_OK; }   // back to the built-in choice
-  if (!stencil_shape_ok(c, t->tile_x, t->tile_yt, t->ry, t->tile_z))
+  if (!stencil_shape_ok(c, t->tile_x, t->tile_yt, t->ry, t->tile_z, t->halo_ring))
     return fail(c, HCU_INVALID_ARG, "stencil tile shape not admissible for this grid");
-  c.tile_x = t->tile_x; c.tile_yt = t->tile_yt; c.ry = t->ry; c.tile_z = t->tile_z;
+  c.tile_x = t->tile_x; c.tile_yt = t->tile_yt; c.ry = t->ry; c.tile_z = t->tile_z; c.halo_ring = t->halo_ring;
   return HCU_OK;
 }
 

@@ -275,7 +275,7 @@ struct Ctx {
   std::vector<std::vector<double>> aimd_pos, aimd_D;
   std::string err;
   // tuning
-  int tile_x = 0, tile_yt = 0, ry = 4, tile_z = 0;
+  int tile_x = 0, tile_yt = 0, ry = 4, tile_z = 0, halo_ring = 0;
   // SCF state (hcu_scf_begin / hcu_scf_step)
   hcu_scf_opts scf_opts{};
   int scf_iter = 0;
@@ -393,7 +393,7 @@ void hxc_destroy(Ctx& c);
 template <typename T>
 void launch_stencil(const Ctx& c, int ik, const T* Yin, int64_t ld, const T* Yprev, int64_t ld_prev, T* Yout,
                     int64_t ld_out, int ncol, double alpha, double cshift, double beta, hipStream_t st);
-bool stencil_shape_ok(const Ctx& c, int TX, int TYt, int RY, int tz);
+bool stencil_shape_ok(const Ctx& c, int TX, int TYt, int RY, int tz, int ring);
 // one block of a batched stencil step (stencil.hip, persistent launch)
 struct StencilJob {
   const Ctx* c;
@@ -419,6 +419,8 @@ struct BatchLaunch {
   unsigned long long total;     // work items
   int TX, TYt, RY, R;
   int halo_slots;               // most halo values per thread and plane over the jobs
+  int ring;                     // halo ring (order-12 stencil only)
+  int halo_n;                   // most halo values per plane over the jobs
 };
 template <typename T>
 hcu_status plan_stencil_batch(const std::vector<StencilJob>& jobs, std::vector<unsigned char>& host,

@@ -106,8 +106,17 @@ __device__ inline int wrap(int g, int n, int& w) {
 constexpr int kHaloSlots = 8;
 constexpr int kHaloSlotsSmall = 4;
 
+// Halo ring (HR): a tile reads its neighbours' rows of plane q at the time
+// it reads its own rows of plane q as queue head, R planes before it
+// computes plane q, so that the neighbour tiles' reads of the same rows
+// (their own queue heads) fall in the same time window and meet in L2.  The
+// halo values wait in a thread-private LDS ring of R planes until the plane
+// is staged; without the ring they are read R planes later than the
+// neighbours read them, when the rows have mostly left L2.
+constexpr int kRingR = 6;   // the ring is built for the order-12 stencil
+
 // One work item: tile `tile` of the x-y plane, z chunk `zc`, state `s`.
-template <typename T, typename RT, int R, int RY, int NHS>
+template <typename T, typename RT, int R, int RY, int NHS, bool HR = false>
 __device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T* __restrict__ Yprev,
                                              T* __restrict__ Yout, const RT* __restrict__ V, const KArgs<RT>& a,
                                              int tile, int zc, int64_t s, unsigned char* smem_raw) {
@@ -115,6 +124,7 @@ __device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T*
   const int SW = TX + 2 * R, SH = TY + 2 * R;
   T* const buf0 = reinterpret_cast<T*>(smem_raw);
   T* const buf1 = buf0 + SW * SH;
+  T* const ring = buf1 + SW * SH;   // HR: [plane mod R][halo value e]
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = ty * TX + tx, nthr = TX * TYt;
   const int bx = tile % a.tiles_x, by = tile / a.tiles_x;
@@ -131,7 +141,7 @@ __device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T*
   // the FP32 kernel faster and not the FP64 one, which keeps the plain
   // sweep; so do complex (Bloch) blocks, whose phase factor changes where
   // a sweep crosses the cell.
-  constexpr bool kShift = std::is_same<T, float>::value && std::is_same<RT, float>::value;
+  constexpr bool kShift = !HR && std::is_same<T, float>::value && std::is_same<RT, float>::value;
   const int zsh = (kShift && ((bx + by) & 1) && a.n3 > R) ? a.n3 - R : 0;
   const gptr<const T> Ys = (gptr<const T>)(Yin + s * a.ld);
   const gptr<const T> Yp = (gptr<const T>)Yprev;
@@ -174,6 +184,8 @@ __device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T*
     h_xy[k] = hx + n1 * hy;
     h_w[k] = (wx + 4) * 16 + (wy + 4);
   }
+  // halo values of a plane (the ring holds nh per plane; slot k of this
+  // thread is value e = tid + k * nthr)
 
   T q[RY][2 * R + 1];
   for (int dz = -R; dz <= R; ++dz) {
@@ -207,8 +219,25 @@ __device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T*
     // load would end in a wait before the next one issues
     for (int k = 0; k < NHS; ++k) hreg[k] = ldv(Ys, h_xy[k] + plane * gz);
     stage(buf0, hreg, wz);
+    if constexpr (HR) {
+      // halo of planes zbeg+1 .. zbeg+R (clamped to the range: the ones past
+      // its end are never staged) into ring planes (p - zbeg) mod R, in two
+      // batches of loads (all R at once would raise the register peak)
+      constexpr int kB = (R + 1) / 2;
+      for (int j0 = 1; j0 <= R; j0 += kB) {
+        T hp[kB][NHS];
+        for (int j = 0; j < kB; ++j) {
+          const int64_t pz = plane * min(zbeg + min(j0 + j, R), zend - 1);
+          for (int k = 0; k < NHS; ++k) hp[j][k] = ldv(Ys, h_xy[k] + pz);
+        }
+        for (int j = 0; j < kB && j0 + j <= R; ++j)
+          for (int k = 0; k < NHS; ++k)
+            if (tid + k * nthr < nh) ring[((j0 + j) % R) * nh + tid + k * nthr] = hp[j][k];
+      }
+    }
   }
   __syncthreads();
+  int rs = R == 1 ? 0 : 1;   // HR: ring slot of plane z + 1
 
   int cur = 0;
   for (int z = zbeg; z < zend; ++z) {
@@ -221,7 +250,9 @@ __device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T*
     if (more) {
       const int gz = wrap(z + 1 + R + zsh, n3, wzn);
       for (int r = 0; r < RY; ++r) qn[r] = ldv(Ys, gx + (int64_t)n1 * gy[r] + plane * gz);
-      const int zh = z + 1 + zsh - (z + 1 + zsh >= n3 ? n3 : 0);
+      // HR: the halo of plane z + 1 + R, with the queue head (clamped to
+      // the range: the planes past its end are never staged)
+      const int zh = HR ? min(z + 1 + R, zend - 1) : z + 1 + zsh - (z + 1 + zsh >= n3 ? n3 : 0);
       for (int k = 0; k < NHS; ++k) hreg[k] = ldv(Ys, h_xy[k] + plane * zh);   // unused slots: node 0
     }
     const int64_t zoff = plane * (z + zsh - (z + zsh >= n3 ? n3 : 0));
@@ -260,13 +291,31 @@ __device__ __forceinline__ void stencil_item(const T* __restrict__ Yin, const T*
       for (int t = 0; t < 2 * R; ++t) q[r][t] = q[r][t + 1];
       if (more) q[r][2 * R] = Ph<T>::apply(qn[r], wxo, wyo[r], wzn, a);
     }
-    if (more) stage(cur ? buf0 : buf1, hreg, 0);
+    if (more) {
+      if constexpr (HR) {
+        // plane z + 1 leaves its ring slot, plane z + 1 + R takes it (the
+        // same thread's entries: no barrier between the two)
+        T hv[NHS];
+        for (int k = 0; k < NHS; ++k) {
+          hv[k] = hreg[k];
+          if (tid + k * nthr < nh) {
+            T* const e = ring + rs * nh + tid + k * nthr;
+            hv[k] = *e;
+            *e = hreg[k];
+          }
+        }
+        stage(cur ? buf0 : buf1, hv, 0);
+        rs = rs + 1 == R ? 0 : rs + 1;
+      } else {
+        stage(cur ? buf0 : buf1, hreg, 0);
+      }
+    }
     __syncthreads();
     cur ^= 1;
   }
 }
 
-template <typename T, typename RT, int R, int RY, int NHS>
+template <typename T, typename RT, int R, int RY, int NHS, bool HR = false>
 __global__ __launch_bounds__(512) void k_stencil(const T* __restrict__ Yin, const T* __restrict__ Yprev,
                                                  T* __restrict__ Yout, const RT* __restrict__ V,
                                                  const KArgs<RT> a) {
@@ -276,7 +325,7 @@ __global__ __launch_bounds__(512) void k_stencil(const T* __restrict__ Yin, cons
   const int tile = lw % gridDim.x;
   const int zc = (lw / gridDim.x) % gridDim.y;
   const int64_t s = lw / (gridDim.x * gridDim.y);
-  stencil_item<T, RT, R, RY, NHS>(Yin, Yprev, Yout, V, a, tile, zc, s, smem_raw);
+  stencil_item<T, RT, R, RY, NHS, HR>(Yin, Yprev, Yout, V, a, tile, zc, s, smem_raw);
 }
 
 // Large-workgroup form (up to 1024 threads, e.g. a 72 x 12 tile with one
@@ -300,7 +349,7 @@ __global__ __launch_bounds__(1024) void k_stencil_big(const T* __restrict__ Yin,
 // counter each; workgroup w starts on range w % kNumXcd (the XCD it runs on)
 // and moves to the next range when its own is exhausted.  Every workgroup
 // leaves after visiting all ranges, so the grid always drains.
-template <typename T, typename RT, int R, int RY, int NHS>
+template <typename T, typename RT, int R, int RY, int NHS, bool HR = false>
 __global__ __launch_bounds__(512) void k_stencil_batch(const SJob<RT>* __restrict__ jobs, int njobs,
                                                        unsigned long long total,
                                                        unsigned long long* __restrict__ counters) {
@@ -332,7 +381,7 @@ __global__ __launch_bounds__(512) void k_stencil_batch(const SJob<RT>* __restric
       const int tile = (int)(loc % jb.ntiles);
       const int zc = (int)((loc / jb.ntiles) % jb.nzc);
       const int64_t s = (int64_t)(loc / ((unsigned long long)jb.ntiles * jb.nzc));
-      stencil_item<T, RT, R, RY, NHS>((const T*)jb.Yin, (const T*)jb.Yprev, (T*)jb.Yout, jb.V, jb.a, tile, zc, s,
+      stencil_item<T, RT, R, RY, NHS, HR>((const T*)jb.Yin, (const T*)jb.Yprev, (T*)jb.Yout, jb.V, jb.a, tile, zc, s,
                                  smem_raw);
     }
   }
@@ -361,7 +410,7 @@ __global__ __launch_bounds__(512) void k_stencil_multi(const SJob<RT>* __restric
 
 // Tile shape for a grid: TX threads along x, TYt thread rows, RY points per
 // thread along y, tz planes per workgroup.  Tuned values (hcu_autotune) win.
-struct StencilShape { int TX, TYt, RY, tz; };
+struct StencilShape { int TX, TYt, RY, tz, ring = 0; };
 
 // workgroups above 512 threads run k_stencil_big (128 registers per thread)
 static bool big_ok(const Ctx& c, int RY) {
@@ -376,6 +425,21 @@ static int halo_slots(int n1, int TX, int TYt, int TY, int R) {
   return (nh + nthr - 1) / nthr;
 }
 
+// halo values of a plane for a tile on a grid with n1 points in x
+static int halo_values(int n1, int TX, int TY, int R) {
+  return 2 * R * TX + ((TX == n1 && n1 >= R) ? 0 : TY * 2 * R);
+}
+
+// LDS of a workgroup: two staged planes with halo, and the halo ring
+// (R planes of halo values) when the tile takes one
+static size_t stencil_lds(int n1, int TX, int TYt, int RY, int R, int ring, size_t elem) {
+  const int TY = TYt * RY;
+  size_t b = 2 * (size_t)(TY + 2 * R) * (TX + 2 * R) * elem;
+  if (ring) b += (size_t)R * halo_values(n1, TX, TY, R) * elem;
+  return b;
+}
+constexpr size_t kLdsPerWorkgroup = 160 * 1024;
+
 static bool shape_ok(const Ctx& c, const StencilShape& sh, int R) {
   const int n1 = c.p.n[0], n2 = c.p.n[1];
   if (sh.TX < 1 || sh.TX > n1 || sh.TYt < 1 || sh.TX * sh.TYt > 1024) return false;
@@ -384,18 +448,25 @@ static bool shape_ok(const Ctx& c, const StencilShape& sh, int R) {
   const int TY = sh.TYt * sh.RY;
   if (TY > n2) return false;
   if (halo_slots(n1, sh.TX, sh.TYt, TY, R) > kHaloSlots) return false;
+  if (sh.ring) {   // built for the order-12 stencil, 4 halo slots, <= 512 threads
+    if (sh.ring != 1 || R != kRingR || sh.TX * sh.TYt > 512) return false;
+    if (halo_slots(n1, sh.TX, sh.TYt, TY, R) > kHaloSlotsSmall) return false;
+    const size_t elem = c.any_complex ? (c.mixed ? 8 : 16) : (c.mixed ? 4 : 8);
+    if (stencil_lds(n1, sh.TX, sh.TYt, sh.RY, R, 1, elem) > kLdsPerWorkgroup) return false;
+  }
   return sh.tz >= 1;
 }
 
-bool stencil_shape_ok(const Ctx& c, int TX, int TYt, int RY, int tz) {
-  return shape_ok(c, StencilShape{TX, TYt, RY, tz}, c.p.n0);
+bool stencil_shape_ok(const Ctx& c, int TX, int TYt, int RY, int tz, int ring) {
+  return shape_ok(c, StencilShape{TX, TYt, RY, tz, ring}, c.p.n0);
 }
 
 static StencilShape pick_tiles(const Ctx& c, int ncol, int elem) {
   const int n1 = c.p.n[0], n2 = c.p.n[1], n3 = c.p.n[2];
   const int R = c.p.n0;
-  StencilShape sh{c.tile_x, c.tile_yt, c.ry, c.tile_z};
+  StencilShape sh{c.tile_x, c.tile_yt, c.ry, c.tile_z, c.halo_ring};
   if (sh.TX > 0 && shape_ok(c, sh, R)) return sh;
+  sh.ring = 0;
   sh.RY = elem > 8 ? 2 : 4;
   sh.TX = n1 <= 128 ? n1 : 64;
   sh.TYt = std::max(1, 256 / sh.TX);
@@ -410,9 +481,27 @@ static StencilShape pick_tiles(const Ctx& c, int ncol, int elem) {
   return sh;
 }
 
+// workgroups above 64 KB of LDS ask for it (gfx950 has 160 KB per CU)
+template <typename K>
+static void allow_lds(K kernel, size_t lds) {
+  if (lds > 65536) (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
 template <typename T, typename RT, int R>
-static void launch_r(int RY, bool small_halo, const KArgs<RT>& a, dim3 grid, dim3 block, size_t lds, const T* Yin,
-                     const T* Yprev, T* Yout, const RT* V, hipStream_t st) {
+static void launch_r(int RY, bool small_halo, int ring, const KArgs<RT>& a, dim3 grid, dim3 block, size_t lds,
+                     const T* Yin, const T* Yprev, T* Yout, const RT* V, hipStream_t st) {
+  if constexpr (R == kRingR) {
+    if (ring) {
+      auto go = [&](auto kernel) {
+        allow_lds(kernel, lds);
+        launch_k(kernel, grid, block, lds, st, Yin, Yprev, Yout, V, a);
+      };
+      if (RY == 4) go(k_stencil<T, RT, R, 4, kHaloSlotsSmall, true>);
+      else if (RY == 2) go(k_stencil<T, RT, R, 2, kHaloSlotsSmall, true>);
+      else go(k_stencil<T, RT, R, 1, kHaloSlotsSmall, true>);
+      return;
+    }
+  }
   if constexpr (sizeof(T) == sizeof(RT)) {
     if (block.x * block.y > 512) {
       if (RY == 2)
@@ -463,23 +552,37 @@ void launch_stencil(const Ctx& c, int ik, const T* Yin, int64_t ld, const T* Ypr
   dim3 grid(a.tiles_x * ((a.n2 + TY - 1) / TY), (a.n3 + tz - 1) / tz, ncol);
   dim3 block(TX, TYt);
   const int R = sc.R;
-  size_t lds = 2 * (size_t)(TY + 2 * R) * (TX + 2 * R) * sizeof(T);
+  const size_t lds = stencil_lds(a.n1, TX, TYt, sh.RY, R, sh.ring, sizeof(T));
   const bool small = halo_slots(a.n1, TX, TYt, TY, R) <= kHaloSlotsSmall;
   const RT* V;
   if constexpr (sizeof(RT) == 4) V = c.d_Vf; else V = c.d_V;
+  const int rg = sh.ring;
   switch (R) {
-    case 1: launch_r<T, RT, 1>(sh.RY, small, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
-    case 2: launch_r<T, RT, 2>(sh.RY, small, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
-    case 3: launch_r<T, RT, 3>(sh.RY, small, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
-    case 4: launch_r<T, RT, 4>(sh.RY, small, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
-    case 5: launch_r<T, RT, 5>(sh.RY, small, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
-    default: launch_r<T, RT, 6>(sh.RY, small, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    case 1: launch_r<T, RT, 1>(sh.RY, small, rg, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    case 2: launch_r<T, RT, 2>(sh.RY, small, rg, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    case 3: launch_r<T, RT, 3>(sh.RY, small, rg, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    case 4: launch_r<T, RT, 4>(sh.RY, small, rg, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    case 5: launch_r<T, RT, 5>(sh.RY, small, rg, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
+    default: launch_r<T, RT, 6>(sh.RY, small, rg, a, grid, block, lds, Yin, Yprev, Yout, V, st); break;
   }
 }
 
 template <typename T, typename RT, int R>
-static void launch_batch_r(int RY, bool small_halo, dim3 grid, dim3 block, size_t lds, const SJob<RT>* jobs,
-                           int njobs, unsigned long long total, unsigned long long* counters, hipStream_t st) {
+static void launch_batch_r(int RY, bool small_halo, int ring, dim3 grid, dim3 block, size_t lds,
+                           const SJob<RT>* jobs, int njobs, unsigned long long total, unsigned long long* counters,
+                           hipStream_t st) {
+  if constexpr (R == kRingR) {
+    if (ring && counters) {
+      auto go = [&](auto kernel) {
+        allow_lds(kernel, lds);
+        launch_k(kernel, grid, block, lds, st, jobs, njobs, total, counters);
+      };
+      if (RY == 4) go(k_stencil_batch<T, RT, R, 4, kHaloSlotsSmall, true>);
+      else if (RY == 2) go(k_stencil_batch<T, RT, R, 2, kHaloSlotsSmall, true>);
+      else go(k_stencil_batch<T, RT, R, 1, kHaloSlotsSmall, true>);
+      return;
+    }
+  }
   if (!counters) {   // one workgroup per item
     dim3 g((unsigned)total);
     if (RY == 4)
@@ -505,13 +608,14 @@ static void launch_batch_r(int RY, bool small_halo, dim3 grid, dim3 block, size_
 
 // Common tile shape for a set of grids: the autotuned shape of the first
 // context if every grid admits it, else the largest admissible built-in one.
-bool batch_shape(const std::vector<const Ctx*>& cs, int ncol, int elem, int& TX, int& TYt, int& RY, int* TZ) {
+bool batch_shape(const std::vector<const Ctx*>& cs, int ncol, int elem, int& TX, int& TYt, int& RY, int* TZ,
+                 int* ring) {
   const Ctx& c0 = *cs[0];
   StencilShape sh = pick_tiles(c0, ncol, elem);
   auto ok_all = [&](const StencilShape& t) {
     if (t.TX * t.TYt > 512) return false;   // the persistent kernel is built for 512 threads
     for (const Ctx* c : cs)
-      if (!shape_ok(*c, StencilShape{t.TX, t.TYt, t.RY, 1}, c->p.n0)) return false;
+      if (!shape_ok(*c, StencilShape{t.TX, t.TYt, t.RY, 1, t.ring}, c->p.n0)) return false;
     return true;
   };
   if (!ok_all(sh)) {
@@ -533,6 +637,7 @@ bool batch_shape(const std::vector<const Ctx*>& cs, int ncol, int elem, int& TX,
   }
   TX = sh.TX; TYt = sh.TYt; RY = sh.RY;
   if (TZ) *TZ = sh.tz;
+  if (ring) *ring = sh.ring;
   return true;
 }
 
@@ -551,13 +656,13 @@ hcu_status plan_stencil_batch(const std::vector<StencilJob>& jobs, std::vector<u
   std::vector<int> gid(jobs.size());
   std::vector<StencilShape> groups;
   for (size_t i = 0; i < jobs.size(); ++i) {
-    int TX, TYt, RY, TZ = 0;
+    int TX, TYt, RY, TZ = 0, ring = 0;
     std::vector<const Ctx*> one{jobs[i].c};
-    if (!batch_shape(one, jobs[i].ncol, (int)sizeof(T), TX, TYt, RY, &TZ)) return HCU_INVALID_ARG;
-    shp[i] = StencilShape{TX, TYt, RY, TZ};
+    if (!batch_shape(one, jobs[i].ncol, (int)sizeof(T), TX, TYt, RY, &TZ, &ring)) return HCU_INVALID_ARG;
+    shp[i] = StencilShape{TX, TYt, RY, TZ, ring};
     int g = -1;
     for (size_t k = 0; k < groups.size(); ++k)
-      if (groups[k].TX == TX && groups[k].TYt == TYt && groups[k].RY == RY) g = (int)k;
+      if (groups[k].TX == TX && groups[k].TYt == TYt && groups[k].RY == RY && groups[k].ring == ring) g = (int)k;
     if (g < 0) {
       g = (int)groups.size();
       groups.push_back(shp[i]);
@@ -570,12 +675,13 @@ hcu_status plan_stencil_batch(const std::vector<StencilJob>& jobs, std::vector<u
   for (size_t g = 0; g < groups.size(); ++g) {
     const int TX = groups[g].TX, TYt = groups[g].TYt, RY = groups[g].RY;
     const int TY = TYt * RY;
-    BatchLaunch L{slot, 0, 0, TX, TYt, RY, R, 0};
+    BatchLaunch L{slot, 0, 0, TX, TYt, RY, R, 0, groups[g].ring, 0};
     for (size_t i = 0; i < jobs.size(); ++i) {
       if (gid[i] != (int)g) continue;
       const StencilJob& j = jobs[i];
       const Ctx& c = *j.c;
       L.halo_slots = std::max(L.halo_slots, halo_slots(c.p.n[0], TX, TYt, TY, R));
+      L.halo_n = std::max(L.halo_n, halo_values(c.p.n[0], TX, TY, R));
       StencilCoef sc;
       fill_stencil_coef(c, j.ik, sc);
       KArgs<RT> a{};
@@ -616,29 +722,29 @@ hcu_status run_stencil_batch(const BatchLaunch& L, const void* d_jobs, unsigned 
   using RT = typename real_of<T>::type;
   if (d_counters && hipMemsetAsync(d_counters, 0, kNumXcd * sizeof(unsigned long long), st) != hipSuccess)
     return HCU_DEVICE;
-  const int TY = L.TYt * L.RY;
-  const size_t lds = 2 * (size_t)(TY + 2 * L.R) * (L.TX + 2 * L.R) * sizeof(T);
+  size_t lds = stencil_lds(0, L.TX, L.TYt, L.RY, L.R, 0, sizeof(T));
+  if (L.ring) lds += (size_t)L.R * L.halo_n * sizeof(T);
   const bool small = L.halo_slots <= kHaloSlotsSmall;
   dim3 grid(1024), block(L.TX, L.TYt);
   const SJob<RT>* dj = reinterpret_cast<const SJob<RT>*>(d_jobs) + L.first;
   switch (L.R) {
     case 1:
-      launch_batch_r<T, RT, 1>(L.RY, small, grid, block, lds, dj, L.njob, L.total, d_counters, st);
+      launch_batch_r<T, RT, 1>(L.RY, small, L.ring, grid, block, lds, dj, L.njob, L.total, d_counters, st);
       break;
     case 2:
-      launch_batch_r<T, RT, 2>(L.RY, small, grid, block, lds, dj, L.njob, L.total, d_counters, st);
+      launch_batch_r<T, RT, 2>(L.RY, small, L.ring, grid, block, lds, dj, L.njob, L.total, d_counters, st);
       break;
     case 3:
-      launch_batch_r<T, RT, 3>(L.RY, small, grid, block, lds, dj, L.njob, L.total, d_counters, st);
+      launch_batch_r<T, RT, 3>(L.RY, small, L.ring, grid, block, lds, dj, L.njob, L.total, d_counters, st);
       break;
     case 4:
-      launch_batch_r<T, RT, 4>(L.RY, small, grid, block, lds, dj, L.njob, L.total, d_counters, st);
+      launch_batch_r<T, RT, 4>(L.RY, small, L.ring, grid, block, lds, dj, L.njob, L.total, d_counters, st);
       break;
     case 5:
-      launch_batch_r<T, RT, 5>(L.RY, small, grid, block, lds, dj, L.njob, L.total, d_counters, st);
+      launch_batch_r<T, RT, 5>(L.RY, small, L.ring, grid, block, lds, dj, L.njob, L.total, d_counters, st);
       break;
     default:
-      launch_batch_r<T, RT, 6>(L.RY, small, grid, block, lds, dj, L.njob, L.total, d_counters, st);
+      launch_batch_r<T, RT, 6>(L.RY, small, L.ring, grid, block, lds, dj, L.njob, L.total, d_counters, st);
       break;
   }
   return hipGetLastError() == hipSuccess ? HCU_OK : HCU_DEVICE;

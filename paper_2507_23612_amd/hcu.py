@@ -79,7 +79,7 @@ class hcu_kernel_times(C.Structure):
 
 class hcu_tuning(C.Structure):
     _fields_ = [("tile_x", C.c_int), ("tile_yt", C.c_int), ("ry", C.c_int), ("tile_z", C.c_int),
-                ("stencil_ms", C.c_double)]
+                ("halo_ring", C.c_int), ("stencil_ms", C.c_double)]
 
 
 _lib = None
@@ -415,8 +415,8 @@ class HcuContext:
         self._check(self.lib.hcu_autotune(self.h, C.byref(t)))
         return {k: getattr(t, k) for k, _ in hcu_tuning._fields_}
 
-    def set_tuning(self, tile_x, tile_yt=1, ry=4, tile_z=1):
-        t = hcu_tuning(tile_x, tile_yt, ry, tile_z, 0.0)
+    def set_tuning(self, tile_x, tile_yt=1, ry=4, tile_z=1, halo_ring=0):
+        t = hcu_tuning(tile_x, tile_yt, ry, tile_z, halo_ring, 0.0)
         self._check(self.lib.hcu_set_tuning(self.h, C.byref(t)))
 
     def set_profiling(self, on=True):

@@ -159,18 +159,24 @@ def test_batch_rejects_mismatched_members():
         hcu.HcuBatch([a, k])
 
 
-def test_multi_block_context_batched_pass_equals_per_block_passes():
+@pytest.mark.parametrize("ring", [0, 1])
+def test_multi_block_context_batched_pass_equals_per_block_passes(ring):
     """A spin-polarised 8-k-point context with complex FP32 blocks: one pass
     over its 16 blocks (one stencil launch and one fused scatter + projection
     launch per Chebyshev step for all blocks) against the same context type
     run block by block (each block's own launches).  Same arithmetic per
     block, so the Ritz values agree to FP32 rounding of the summation order
-    (1e-6 Ha) and the orbitals column by column up to a phase."""
+    (1e-6 Ha) and the orbitals column by column up to a phase.  ring: the
+    persistent stencil with the halo ring (z chunks of 4 planes) against the
+    per-block launches without it."""
     torch = _torch()
     from paper_2507_23612_amd import hcu
     cfg = workloads.with_kpoints(workloads.make_config("tiny"))
     a = _prepared(cfg, "mixed", d_seed=31)
     b = _prepared(cfg, "mixed", d_seed=31)
+    if ring:
+        a.set_tuning(12, 4, 2, 4, 1)
+        b.set_tuning(12, 4, 2, 4, 0)
     for s in range(2):
         for ik in range(8):
             a.lanczos_bounds(s, ik)

@@ -66,10 +66,13 @@ def test_apply_h_matches_oracle(name):
     assert err < 1e-12
 
 
-@pytest.mark.parametrize("shape", [(20, 2, 4, 14), (20, 4, 2, 5), (8, 8, 2, 3), (16, 4, 4, 7), (20, 2, 2, 1)])
+@pytest.mark.parametrize("shape", [(20, 2, 4, 14), (20, 4, 2, 5), (8, 8, 2, 3), (16, 4, 4, 7), (20, 2, 2, 1),
+                                   (20, 4, 2, 5, 1), (16, 6, 2, 7, 1), (20, 8, 1, 14, 1), (20, 4, 2, 1, 1)])
 def test_apply_h_tile_shapes_ragged(shape):
     """Every stencil tiling mode (x halo from the tile row or from memory,
-    ragged x/y tiles, 2 or 4 rows per thread, z chunks) against the oracle."""
+    ragged x/y tiles, 2 or 4 rows per thread, z chunks, the halo ring: halo
+    rows read with the queue head, also in z chunks shorter than the ring
+    and of one plane) against the oracle."""
     torch = _torch()
     cfg = _ragged()
     ctx = _ctx(cfg)
@@ -413,14 +416,17 @@ def test_scf_mixed_c1_energy_error():
 KPT = (0.18, -0.18, 0.28)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_apply_h_bloch_kpoint(precision):
+@pytest.mark.parametrize("precision,ring", [("fp64", 0), ("mixed", 0), ("fp64", 1), ("mixed", 1)])
+def test_apply_h_bloch_kpoint(precision, ring):
     """Complex (Bloch) path at a general k-point: stencil wrap phases, complex
-    projectors and scatter, against the oracle (complex128)."""
+    projectors and scatter, against the oracle (complex128); with the halo
+    ring, z chunks of 5 planes (their ring loads clamped at the chunk end)."""
     torch = _torch()
     cfg = _ragged()
     cfg["kpts"] = np.array([KPT])
     ctx = _ctx(cfg, precision)
+    if ring:
+        ctx.set_tuning(20, 4, 2, 5, 1)
     D = _rand_D(1, ctx.nhub, 11)
     ctx.set_hubbard_occupation(D)
     X = workloads.random_block(ctx.nd, ctx.ns, 18, complex_=True)
