@@ -552,7 +552,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 
 // Complex (Bloch) blocks in FP32: the same fused pass with the scatter's
 // four real products per step (k_nl_brick_c) and the projection's four
-// accumulators per slot tile (k_proj_brick_c); at most four slot tiles.
+// accumulators per slot tile (k_proj_brick_c); at most four slot tiles.  The
+// scatter's operands are staged into LDS by the four waves together, a chunk
+// of functions at a time, as for real blocks (two batches of loads per
+// chunk: the projection accumulators leave less register room).
 template <typename R, int G, int NT>
 __device__ __forceinline__ void fused_cplx(const BrickGeo& geo, cplx<R>* __restrict__ Y, int64_t ld, int ncol,
                                            const int64_t* __restrict__ boff, const int* __restrict__ bnj,
@@ -565,17 +568,25 @@ __device__ __forceinline__ void fused_cplx(const BrickGeo& geo, cplx<R>* __restr
   using C = cplx<R>;
   constexpr int P = kPBrick / kBrick;
   constexpr int RS = kYsRow<C>;
-  __shared__ __attribute__((aligned(16))) unsigned char ys_raw[4 * 16 * RS * sizeof(C)];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int s0 = st_ * 64 + wave * 16;
-  if (s0 >= ncol) return;   // whole wave; no workgroup barrier below
+  constexpr int CH = kStageFns<C>;
+  constexpr int kYs = 4 * 16 * RS, kSt = 2 * CH * RS;
+  __shared__ __attribute__((aligned(16))) unsigned char lds_raw[(kYs > kSt ? kYs : kSt) * sizeof(C)];
+  C* const lds = reinterpret_cast<C*>(lds_raw);
+  C* const sQ = lds;             // [CH][RS]: alpha Q of the chunk's functions, the workgroup's states
+  C* const sB = lds + CH * RS;   // [CH][RS]: the chunk's rows of the brick's value table
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int swg = st_ * 64;
+  const int s0 = swg + wave * 16;
+  // waves past the last state take part in the staging and the barriers only
+  const bool wave_ok = s0 < ncol;
   const int sa = s0 + (lane & 15);
   const bool sa_ok = sa < ncol;
   const int q = lane >> 4;
   const int njp = pbnj[b];
   const int ntile = (njp + 15) / 16;   // <= NT (host-checked)
   const int64_t jop = pboff[b];
-  C* yw = reinterpret_cast<C*>(ys_raw) + wave * 16 * RS;
+  C* const yw = lds + wave * 16 * RS;
   // per slot tile: Re Phi Re y, Im Phi Im y, Re Phi Im y, Im Phi Re y
   V pc[NT][4];
   for (int t = 0; t < NT; ++t)
@@ -606,35 +617,55 @@ __device__ __forceinline__ void fused_cplx(const BrickGeo& geo, cplx<R>* __restr
         }
     }
     const int64_t jo = boff[sbk];
-    const int nj4 = (bnj[sbk] + 3) & ~3;
+    const int nj4 = (bnj[sbk] + 3) & ~3;   // uniform over the workgroup
     const C* __restrict__ vb = bval + jo * kBrick;
-    // Function indices 64 at a time, passed between lanes (the index array
-    // has a 64-entry tail, so the unguarded load stays inside it); a step's
-    // Q and table loads go out together and Q is zeroed at its use.
-    const int sac = sa_ok ? sa : ncol - 1;
-    int bjl = -1;
-    for (int jj = 0; jj < nj4; jj += 4) {
-      if ((jj & 63) == 0) {
-        const int v = bj[jo + jj + lane];
-        bjl = jj + lane < nj4 ? v : -1;
+    for (int c0 = 0; c0 < nj4; c0 += CH) {
+      const int nc = min(CH, nj4 - c0);
+      // the chunk's loads from clamped in-range addresses, all issued before
+      // the first LDS write; out-of-range entries zeroed by selection
+      constexpr int NB = 2, NI = CH / 4 / NB;
+      const int s = swg + lane;
+      const int sc = s < ncol ? s : ncol - 1;
+      __syncthreads();   // earlier readers of the area (staging or transposition tiles) are done
+      for (int h = 0; h < NB; ++h) {
+        int jg[NI];
+        for (int i = 0; i < NI; ++i) {
+          const int fn = wave + 4 * (h * NI + i);   // wave-uniform
+          jg[i] = bj[jo + c0 + (fn < nc ? fn : nc - 1)];
+        }
+        __builtin_amdgcn_sched_barrier(0);   // the index loads go out together
+        C qraw[NI], braw[NI];
+        for (int i = 0; i < NI; ++i) {
+          const int fn = wave + 4 * (h * NI + i);
+          qraw[i] = Qt[(int64_t)(jg[i] >= 0 ? jg[i] : 0) * ldq + sc];
+          braw[i] = vb[(int64_t)(c0 + (fn < nc ? fn : nc - 1)) * kBrick + lane];
+        }
+        __builtin_amdgcn_sched_barrier(0);   // and the value loads before any use
+        for (int i = 0; i < NI; ++i) {
+          const int fn = wave + 4 * (h * NI + i);
+          const bool qok = fn < nc && jg[i] >= 0 && s < ncol;
+          sQ[fn * RS + lane] = qok ? C(alpha * qraw[i].re, alpha * qraw[i].im) : C(R(0), R(0));
+          sB[fn * RS + lane] = fn < nc ? braw[i] : C(R(0), R(0));
+        }
       }
-      const int jl = jj + (lane >> 4);
-      const int jg = __shfl(bjl, jl & 63);
-      const C qraw = Qt[(int64_t)(jg >= 0 ? jg : 0) * ldq + sac];
-      C f[4];
-      for (int pt = 0; pt < 4; ++pt) f[pt] = vb[(int64_t)jl * kBrick + pt * 16 + (lane & 15)];
-      const bool qok = sa_ok && jg >= 0;
-      const R qr = qok ? alpha * qraw.re : R(0), qi = qok ? alpha * qraw.im : R(0);
-      for (int pt = 0; pt < 4; ++pt) {
-        ar[pt] = Mf<R>::mfma(qr, f[pt].re, ar[pt]);
-        ai[pt] = Mf<R>::mfma(qr, f[pt].im, ai[pt]);
-      }
-      for (int pt = 0; pt < 4; ++pt) {
-        ar[pt] = Mf<R>::mfma(-qi, f[pt].im, ar[pt]);
-        ai[pt] = Mf<R>::mfma(qi, f[pt].re, ai[pt]);
-      }
+      __syncthreads();
+      if (wave_ok)
+        for (int f4 = 0; f4 < nc; f4 += 4) {
+          const int fr = (f4 + q) * RS;
+          const C a = sQ[fr + wave * 16 + (lane & 15)];
+          C f[4];
+          for (int pt = 0; pt < 4; ++pt) f[pt] = sB[fr + pt * 16 + (lane & 15)];
+          for (int pt = 0; pt < 4; ++pt) {
+            ar[pt] = Mf<R>::mfma(a.re, f[pt].re, ar[pt]);
+            ai[pt] = Mf<R>::mfma(a.re, f[pt].im, ai[pt]);
+          }
+          for (int pt = 0; pt < 4; ++pt) {
+            ar[pt] = Mf<R>::mfma(-a.im, f[pt].im, ar[pt]);
+            ai[pt] = Mf<R>::mfma(a.im, f[pt].re, ai[pt]);
+          }
+        }
     }
-    wave_lds_sync();   // the previous piece's reads of yw are done
+    __syncthreads();   // the staging area becomes the transposition tiles
     for (int pt = 0; pt < 4; ++pt)
       for (int r = 0; r < 4; ++r) {
         const int sl = Mf<R>::row(lane, r);
@@ -643,7 +674,7 @@ __device__ __forceinline__ void fused_cplx(const BrickGeo& geo, cplx<R>* __restr
         if (nj4 > 0 && s0 + sl < ncol && p < nd) Y[(int64_t)(s0 + sl) * ld + p] = v;
         yw[sl * RS + pt * 16 + (lane & 15)] = v;
       }
-    if (ntile == 0) continue;
+    if (ntile == 0 || !wave_ok) continue;
     // ---- projection of the updated piece k (wave-private LDS, in order)
     wave_lds_sync();   // every lane's writes of yw are visible
     C y[16];
