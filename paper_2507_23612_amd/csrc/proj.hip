@@ -555,7 +555,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // accumulators per slot tile (k_proj_brick_c); at most four slot tiles.  The
 // scatter's operands are staged into LDS by the four waves together, a chunk
 // of functions at a time, as for real blocks (two batches of loads per
-// chunk: the projection accumulators leave less register room).
+// chunk: the projection accumulators leave less register room).  Both
+// complex products take three real ones (Gauss): u v with
+//   Re = Σ ur vr − Σ ui vi,  Im = Σ (ur + ui)(vr + vi) − Σ ur vr − Σ ui vi,
+// a quarter fewer matrix-core products and accumulators.
 template <typename R, int G, int NT>
 __device__ __forceinline__ void fused_cplx(const BrickGeo& geo, cplx<R>* __restrict__ Y, int64_t ld, int ncol,
                                            const int64_t* __restrict__ boff, const int* __restrict__ bnj,
@@ -587,10 +590,10 @@ __device__ __forceinline__ void fused_cplx(const BrickGeo& geo, cplx<R>* __restr
   const int ntile = (njp + 15) / 16;   // <= NT (host-checked)
   const int64_t jop = pboff[b];
   C* const yw = lds + wave * 16 * RS;
-  // per slot tile: Re Phi Re y, Im Phi Im y, Re Phi Im y, Im Phi Re y
-  V pc[NT][4];
+  // per slot tile: sums of Re Phi Re y, Im Phi Im y, (Re Phi - Im Phi)(Re y + Im y)
+  V pc[NT][3];
   for (int t = 0; t < NT; ++t)
-    for (int h = 0; h < 4; ++h)
+    for (int h = 0; h < 3; ++h)
       for (int r = 0; r < 4; ++r) pc[t][h][r] = R(0);
   for (int k = 0; k < P; ++k) {
     const int sbk = b * P + k;
@@ -600,7 +603,10 @@ __device__ __forceinline__ void fused_cplx(const BrickGeo& geo, cplx<R>* __restr
     // Loads from clamped in-range addresses, zeroed by selection afterwards
     // (a conditional load becomes a branch closed by a wait for every
     // outstanding load, one round trip per value).
-    V ar[4], ai[4];
+    // Y + alpha Phi Q as three sums started from Y: s1 = Re Y + Σ Re q Re f,
+    // s2 = Σ Im q Im f, s3 = Re Y + Im Y + Σ (Re q + Im q)(Re f + Im f);
+    // the result is (s1 - s2, s3 - s1 - s2)
+    V s1[4], s2[4], s3[4];
     {
       C yv[4][4];
       for (int pt = 0; pt < 4; ++pt)
@@ -612,8 +618,10 @@ __device__ __forceinline__ void fused_cplx(const BrickGeo& geo, cplx<R>* __restr
       for (int pt = 0; pt < 4; ++pt)
         for (int r = 0; r < 4; ++r) {
           const bool in = s0 + Mf<R>::row(lane, r) < ncol && p0 + geo.off(pt * 16 + (lane & 15)) < nd;
-          ar[pt][r] = in ? yv[pt][r].re : R(0);
-          ai[pt][r] = in ? yv[pt][r].im : R(0);
+          const R yr = in ? yv[pt][r].re : R(0), yi = in ? yv[pt][r].im : R(0);
+          s1[pt][r] = yr;
+          s2[pt][r] = R(0);
+          s3[pt][r] = yr + yi;
         }
     }
     const int64_t jo = boff[sbk];
@@ -653,15 +661,13 @@ __device__ __forceinline__ void fused_cplx(const BrickGeo& geo, cplx<R>* __restr
         for (int f4 = 0; f4 < nc; f4 += 4) {
           const int fr = (f4 + q) * RS;
           const C a = sQ[fr + wave * 16 + (lane & 15)];
+          const R asum = a.re + a.im;
           C f[4];
           for (int pt = 0; pt < 4; ++pt) f[pt] = sB[fr + pt * 16 + (lane & 15)];
           for (int pt = 0; pt < 4; ++pt) {
-            ar[pt] = Mf<R>::mfma(a.re, f[pt].re, ar[pt]);
-            ai[pt] = Mf<R>::mfma(a.re, f[pt].im, ai[pt]);
-          }
-          for (int pt = 0; pt < 4; ++pt) {
-            ar[pt] = Mf<R>::mfma(-a.im, f[pt].im, ar[pt]);
-            ai[pt] = Mf<R>::mfma(a.im, f[pt].re, ai[pt]);
+            s1[pt] = Mf<R>::mfma(a.re, f[pt].re, s1[pt]);
+            s2[pt] = Mf<R>::mfma(a.im, f[pt].im, s2[pt]);
+            s3[pt] = Mf<R>::mfma(asum, f[pt].re + f[pt].im, s3[pt]);
           }
         }
     }
@@ -670,7 +676,7 @@ __device__ __forceinline__ void fused_cplx(const BrickGeo& geo, cplx<R>* __restr
       for (int r = 0; r < 4; ++r) {
         const int sl = Mf<R>::row(lane, r);
         const int64_t p = p0 + geo.off(pt * 16 + (lane & 15));
-        const C v(ar[pt][r], ai[pt][r]);
+        const C v(s1[pt][r] - s2[pt][r], s3[pt][r] - s1[pt][r] - s2[pt][r]);
         if (nj4 > 0 && s0 + sl < ncol && p < nd) Y[(int64_t)(s0 + sl) * ld + p] = v;
         yw[sl * RS + pt * 16 + (lane & 15)] = v;
       }
@@ -688,8 +694,7 @@ __device__ __forceinline__ void fused_cplx(const BrickGeo& geo, cplx<R>* __restr
       for (int kk = 0; kk < 16; ++kk) {
         pc[t][0] = Mf<R>::mfma(f[kk].re, y[kk].re, pc[t][0]);
         pc[t][1] = Mf<R>::mfma(f[kk].im, y[kk].im, pc[t][1]);
-        pc[t][2] = Mf<R>::mfma(f[kk].re, y[kk].im, pc[t][2]);
-        pc[t][3] = Mf<R>::mfma(f[kk].im, y[kk].re, pc[t][3]);
+        pc[t][2] = Mf<R>::mfma(f[kk].re - f[kk].im, y[kk].re + y[kk].im, pc[t][2]);
       }
     }
   }
@@ -703,7 +708,9 @@ __device__ __forceinline__ void fused_cplx(const BrickGeo& geo, cplx<R>* __restr
     }
     for (int r = 0; r < 4; ++r) {
       const int j = t * 16 + Mf<R>::row(lane, r);
-      if (j < njp && sa_ok) part[dst[r] * ldp + sa] = C(pc[t][0][r] + pc[t][1][r], pc[t][2][r] - pc[t][3][r]);
+      // conj(Phi) y = (Σ Re Re + Σ Im Im, Σ (Re - Im)(Re + Im) - Σ Re Re + Σ Im Im)
+      if (j < njp && sa_ok)
+        part[dst[r] * ldp + sa] = C(pc[t][0][r] + pc[t][1][r], pc[t][2][r] - pc[t][0][r] + pc[t][1][r]);
     }
   }
 }
