@@ -356,9 +356,11 @@ __global__ __launch_bounds__(256) void k_gram2_c(const T* __restrict__ Y, const 
 
 // Complex FP32 blocks on the matrix cores: the same 32 x 32 output tiles and
 // partial layout as k_gram2_c, each wave one 16 x 16 sub-tile of S and of Hs,
-// with the four real products of a complex one kept in separate
-// accumulators (Re: rr + ii, Im: ri - ir for A^H B); staged through LDS as
-// separate real and imaginary planes, next stage prefetched into registers.
+// each complex product as three real ones (Gauss) in separate accumulators:
+// for A^H B, Re = Σ ar br + Σ ai bi, Im = Σ (ar - ai)(br + bi) - Σ ar br +
+// Σ ai bi; staged through LDS as separate real and imaginary planes, next
+// stage prefetched into registers from clamped in-range addresses (zeroed by
+// selection when staged: a guarded load would wait for every outstanding one).
 template <typename R>
 __global__ __launch_bounds__(256) void k_gram2_cm(const cplx<R>* __restrict__ Y, const cplx<R>* __restrict__ HY,
                                                   int64_t ld, int n, int64_t nd, int64_t kchunk,
@@ -378,20 +380,20 @@ __global__ __launch_bounds__(256) void k_gram2_cm(const cplx<R>* __restrict__ Y,
   const int64_t ke = min(nd, kb + kchunk);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wi = wave >> 1, wj = wave & 1;
-  V acc[8];   // S: rr ii ri ir, Hs: rr ii ri ir
-  for (int t = 0; t < 8; ++t)
+  V acc[6];   // S: rr ii (r-i)(r+i), Hs: rr ii (r-i)(r+i)
+  for (int t = 0; t < 6; ++t)
     for (int r = 0; r < 4; ++r) acc[t][r] = 0;
   constexpr int PER = CT * CK / 256;
   C ra[PER], rb[PER], rh[PER];
-  auto fetch = [&](int64_t k) {
+  auto fetch = [&](int64_t k) {   // k < ke
     for (int t = 0; t < PER; ++t) {
       const int e = threadIdx.x + 256 * t;
       const int col = e / CK, kk = e % CK;
-      const int64_t g = k + kk;
-      const bool okk = g < ke;
-      ra[t] = (okk && i0 + col < n) ? Y[(int64_t)(i0 + col) * ld + g] : C();
-      rb[t] = (okk && j0 + col < n) ? Y[(int64_t)(j0 + col) * ld + g] : C();
-      rh[t] = (okk && j0 + col < n) ? HY[(int64_t)(j0 + col) * ld + g] : C();
+      const int64_t g = min(k + kk, ke - 1);
+      const int ca = min(i0 + col, n - 1), cb = min(j0 + col, n - 1);
+      ra[t] = Y[(int64_t)ca * ld + g];
+      rb[t] = Y[(int64_t)cb * ld + g];
+      rh[t] = HY[(int64_t)cb * ld + g];
     }
   };
   if (kb < ke) fetch(kb);
@@ -399,12 +401,14 @@ __global__ __launch_bounds__(256) void k_gram2_cm(const cplx<R>* __restrict__ Y,
     for (int t = 0; t < PER; ++t) {
       const int e = threadIdx.x + 256 * t;
       const int col = e / CK, kk = e % CK;
-      sAr[col][kk] = ra[t].re;
-      sAi[col][kk] = ra[t].im;
-      sBr[col][kk] = rb[t].re;
-      sBi[col][kk] = rb[t].im;
-      sHr[col][kk] = rh[t].re;
-      sHi[col][kk] = rh[t].im;
+      const bool okk = k + kk < ke;
+      const bool oa = okk && i0 + col < n, ob = okk && j0 + col < n;
+      sAr[col][kk] = oa ? ra[t].re : R(0);
+      sAi[col][kk] = oa ? ra[t].im : R(0);
+      sBr[col][kk] = ob ? rb[t].re : R(0);
+      sBi[col][kk] = ob ? rb[t].im : R(0);
+      sHr[col][kk] = ob ? rh[t].re : R(0);
+      sHi[col][kk] = ob ? rh[t].im : R(0);
     }
     __syncthreads();
     if (k + CK < ke) fetch(k + CK);
@@ -412,14 +416,13 @@ __global__ __launch_bounds__(256) void k_gram2_cm(const cplx<R>* __restrict__ Y,
       const int ia = 16 * wi + (lane & 15), jb = 16 * wj + (lane & 15), kq = kk + (lane >> 4);
       const R ar = sAr[ia][kq], ai = sAi[ia][kq];
       const R br = sBr[jb][kq], bi = sBi[jb][kq], hr = sHr[jb][kq], hi = sHi[jb][kq];
+      const R ad = ar - ai;
       acc[0] = Acc<R>::mfma(ar, br, acc[0]);
       acc[1] = Acc<R>::mfma(ai, bi, acc[1]);
-      acc[2] = Acc<R>::mfma(ar, bi, acc[2]);
-      acc[3] = Acc<R>::mfma(ai, br, acc[3]);
-      acc[4] = Acc<R>::mfma(ar, hr, acc[4]);
-      acc[5] = Acc<R>::mfma(ai, hi, acc[5]);
-      acc[6] = Acc<R>::mfma(ar, hi, acc[6]);
-      acc[7] = Acc<R>::mfma(ai, hr, acc[7]);
+      acc[2] = Acc<R>::mfma(ad, br + bi, acc[2]);
+      acc[3] = Acc<R>::mfma(ar, hr, acc[3]);
+      acc[4] = Acc<R>::mfma(ai, hi, acc[4]);
+      acc[5] = Acc<R>::mfma(ad, hr + hi, acc[5]);
     }
     __syncthreads();
   }
@@ -430,9 +433,9 @@ __global__ __launch_bounds__(256) void k_gram2_cm(const cplx<R>* __restrict__ Y,
     const int j = 16 * wj + (lane & 15);
     const int e = i * CT + j;
     outS[2 * e] = (double)acc[0][r] + (double)acc[1][r];
-    outS[2 * e + 1] = (double)acc[2][r] - (double)acc[3][r];
-    outH[2 * e] = (double)acc[4][r] + (double)acc[5][r];
-    outH[2 * e + 1] = (double)acc[6][r] - (double)acc[7][r];
+    outS[2 * e + 1] = (double)acc[2][r] - (double)acc[0][r] + (double)acc[1][r];
+    outH[2 * e] = (double)acc[3][r] + (double)acc[4][r];
+    outH[2 * e + 1] = (double)acc[5][r] - (double)acc[3][r] + (double)acc[4][r];
   }
 }
 
