@@ -421,8 +421,10 @@ hcu_status hcu_get_potential(hcu_ctx* ctx, double* V, double* rho_in);
  * Snapshot of the SCF state in a caller-owned host buffer: input occupation
  * matrices and the Pulay history (Sec. II.B mixing), iteration counter and
  * convergence bookkeeping, filter bounds per (spin, k), last eigenvalues,
- * occupations and energies, and the orbital blocks; with hxc also the
- * input density and the density mixing window.  A context of the same
+ * occupations and energies, the orbital blocks and their projections onto
+ * the atom-centred functions (left by the last Rayleigh-Ritz rotation, where
+ * the next filter starts); with hxc also the input density and the density
+ * mixing window.  A context of the same
  * problem (same shape, precision, real/complex type and hxc flag) that loads it
  * continues with hcu_scf_step exactly as the saved one would have.
  * Errors: HCU_NOT_BOUND, HCU_INVALID_ARG (buffer too small, foreign or

@@ -392,16 +392,17 @@ void cheb_step_t(Ctx& c, int spin, int ik, const T* y, int64_t ldy, const T* ypr
 // project_last: leave P and Q of the filtered block behind (for H Y next).
 // Between steps the projections come out of the fused scatter when the
 // block type allows it.
+// proj_x = false: P and Q of X are already current.
 template <typename T>
 int filter_t(Ctx& c, int spin, int ik, const T* X, int64_t ldx, int ncol, int m, double a, double b, double aL,
-             bool project_last = false) {
+             bool project_last = false, bool proj_x = true) {
   const bool fuse = scatter_project_ok<T>(c);
   const double e = (b - a) / 2, cc = (b + a) / 2;
   double sigma = e / (aL - cc);
   const double tau = 2.0 / sigma;
   const int64_t nd = c.nd;
   void** W = &c.d_W[3 * sk_index(c, spin, ik)];
-  cheb_step_t<T>(c, spin, ik, X, ldx, nullptr, 0, (T*)W[0], nd, ncol, sigma / e, cc, 0.0, true,
+  cheb_step_t<T>(c, spin, ik, X, ldx, nullptr, 0, (T*)W[0], nd, ncol, sigma / e, cc, 0.0, proj_x,
                  fuse && (m > 1 || project_last));
   const T* prev = X;
   int64_t ldp = ldx;
@@ -446,7 +447,11 @@ hcu_status rr_t(Ctx& c, int sk, T* Y, T* HY) {
     ProfScope ps(c, PK_ROTATE, true);   // a library call for real blocks
     launch_rotate<T>(c, Y, nd, (const T*)c.d_Cb, X, ns, c.stream);
   }
-  if (c.nproj > 0) launch_rotate_proj<T>(c, (const T*)c.d_PY[sk], (const T*)c.d_Cb, (T*)c.d_PX[sk], ns, c.stream);
+  if (c.nproj > 0) {
+    launch_rotate_proj<T>(c, (const T*)c.d_PY[sk], (const T*)c.d_Cb, (T*)c.d_PX[sk], ns, c.stream);
+    if ((int)c.px_valid.size() <= sk) c.px_valid.resize(sk + 1, 0);
+    c.px_valid[sk] = 1;   // P(X) = P(Y) C: the next filter starts from it
+  }
   HCU_HIP(hipGetLastError());
   HCU_HIP(hipMemcpyAsync(c.h_info + kInfoPerBlock * sk, c.d_info, 3 * sizeof(int), hipMemcpyDeviceToHost, c.stream));
   return HCU_OK;
@@ -485,7 +490,17 @@ hcu_status pass_t(Ctx& c, int spin, int ik, double* filter_ms) {
   HCU_HIP(hipEventCreate(&e1));
   HCU_HIP(hipEventRecord(e0, c.stream));
   const bool fuse = scatter_project_ok<T>(c);
-  const int iy = filter_t<T>(c, spin, ik, X, nd, ns, c.p.degree, a, b, aL, fuse);
+  // the projections of X left by the last rotation (P(X) = P(Y) C, equal to
+  // projecting X up to rounding) replace the filter's first projection; the
+  // coupling is applied anew (D may have changed since)
+  const bool reuse = c.nproj > 0 && sk < (int)c.px_valid.size() && c.px_valid[sk];
+  if (reuse) {
+    ProfScope ps(c, PK_PROJECT);
+    HCU_HIP(hipMemcpyAsync(c.d_P[sk], c.d_PX[sk], esize(c) * (size_t)ns * c.nproj, hipMemcpyDeviceToDevice,
+                           c.stream));
+    launch_couple<T>(c, (const T*)c.d_P[sk], ns, c.d_coup[spin], (T*)c.d_Q[sk], c.stream);
+  }
+  const int iy = filter_t<T>(c, spin, ik, X, nd, ns, c.p.degree, a, b, aL, fuse, !reuse);
   const int ih = (iy + 1) % 3;
   T* Y = (T*)c.d_W[3 * sk + iy];
   T* HY = (T*)c.d_W[3 * sk + ih];
@@ -1435,6 +1450,7 @@ hcu_status hcu_move_atoms(hcu_ctx* ctx, const double* pos, int extrapolate, doub
     if (c.aimd_pos.size() > 3) { c.aimd_pos.pop_back(); c.aimd_D.pop_back(); }
   }
   const std::vector<double> old = c.pos;
+  c.px_valid.clear();   // the projector tables change with the atoms
   c.pos.assign(pos, pos + 3 * c.p.natom);
   s = build_structure(c);
   const size_t need = s == HCU_OK ? layout(c, nullptr, false) : 0;
@@ -1587,6 +1603,7 @@ hcu_status hcu_set_start(hcu_ctx* ctx, int spin, int ik, const void* X0, const v
   if (!X0 || !v0) return fail(c, HCU_INVALID_ARG, "null start block");
   const int sk = sk_index(c, spin, ik);
   HCU_HIP(hipMemcpyAsync(c.d_X[sk], X0, esize(c) * (size_t)c.nd * c.p.ns, hipMemcpyDeviceToDevice, c.stream));
+  c.px_valid.clear();   // new orbitals: their projections are not at hand
   HCU_HIP(hipMemcpyAsync(c.d_v0[sk], v0, esize(c) * (size_t)c.nd, hipMemcpyDeviceToDevice, c.stream));
   HCU_HIP(hipStreamSynchronize(c.stream));
   return HCU_OK;

@@ -216,6 +216,9 @@ struct Ctx {
   double* d_fsum = nullptr;          // per Hubbard atom 325 complex bilinear sums
   double* d_focc = nullptr;          // caller occupations [nspin*nk][ns]
   std::vector<void*> d_PX;           // per (spin,k) projections of X [ns][nproj]
+  // per (spin,k): d_PX holds P(X) of the current X and projector tables (set
+  // by the Rayleigh-Ritz rotation; cleared when X or the tables are replaced)
+  std::vector<unsigned char> px_valid;
   double* d_part = nullptr;          // split-K partials of the Gram matrices
   int2* d_tiles = nullptr;           // upper-triangular output tiles of the Gram kernels
   size_t part_elems = 0;
@@ -459,6 +462,9 @@ template <typename T>
 void launch_project_brick(const Ctx& c, int ik, const T* Y, int ncol, int64_t ld, const double* coup, T* P, T* Q,
                           hipStream_t st);
 size_t project_partial_elems(const Ctx& c);
+// Q = C P (the coupling alone, for projections already at hand)
+template <typename T>
+void launch_couple(const Ctx& c, const T* P, int ncol, const double* coup, T* Q, hipStream_t st);
 // projections only (no coupling) with a caller-chosen function table in the
 // projection-brick layout
 template <typename T>

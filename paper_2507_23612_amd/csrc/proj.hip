@@ -895,6 +895,19 @@ void launch_project_brick(const Ctx& c, int ik, const T* Y, int ncol, int64_t ld
   launch_k(k_couple<T>, g3, 64, 0, st, P, c.d_blocks, ncol, coup, Q, c.nproj, c.p.ns);
 }
 
+template <typename T>
+void launch_couple(const Ctx& c, const T* P, int ncol, const double* coup, T* Q, hipStream_t st) {
+  if (c.nproj == 0) return;
+  dim3 g3((ncol + 63) / 64, (unsigned)c.blocks.size());
+  launch_k(k_couple<T>, g3, 64, 0, st, P, c.d_blocks, ncol, coup, Q, c.nproj, c.p.ns);
+}
+template void launch_couple<double>(const Ctx&, const double*, int, const double*, double*, hipStream_t);
+template void launch_couple<float>(const Ctx&, const float*, int, const double*, float*, hipStream_t);
+template void launch_couple<cplx<double>>(const Ctx&, const cplx<double>*, int, const double*, cplx<double>*,
+                                          hipStream_t);
+template void launch_couple<cplx<float>>(const Ctx&, const cplx<float>*, int, const double*, cplx<float>*,
+                                         hipStream_t);
+
 template void launch_project_table<double>(const Ctx&, const double*, const double*, int, int64_t, double*,
                                            hipStream_t);
 template void launch_project_table<float>(const Ctx&, const float*, const float*, int, int64_t, float*, hipStream_t);

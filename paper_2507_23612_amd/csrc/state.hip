@@ -3,7 +3,9 @@
 // iteration counter and convergence bookkeeping, the filter bounds of every
 // (spin, k) block, the last eigenvalues/occupations/energies and the
 // orbital blocks themselves; with the density-dependent Hamiltonian also
-// the input density and the density mixing window.  A restored context continues the SCF exactly
+// the input density and the density mixing window, and the rotated
+// projections of the blocks (the next filter starts from them).  A restored
+// context continues the SCF exactly
 // as the saved one would have (the next step filters the restored blocks
 // with the restored bounds and mixes with the restored history).
 #include "common.h"
@@ -14,7 +16,7 @@ using namespace hcu;
 
 namespace {
 constexpr char kMagic[8] = {'H', 'C', 'U', 'S', 'T', 'A', 'T', 'E'};
-constexpr uint32_t kVersion = 2;
+constexpr uint32_t kVersion = 3;
 
 struct StateHeader {
   char magic[8];
@@ -28,6 +30,14 @@ struct StateHeader {
   hcu_energies en;
 };
 
+// rotated projections: one validity flag (a double) and the [ns][nproj]
+// block per (spin, k)
+size_t px_bytes(const Ctx& c) {
+  const int nsk = c.p.nspin * c.p.nk;
+  const size_t es = (c.mixed ? 4 : 8) * (c.any_complex ? 2 : 1);
+  return (size_t)nsk * (sizeof(double) + es * (size_t)c.p.ns * c.nproj);
+}
+
 size_t state_bytes(const Ctx& c, size_t* hist_len) {
   const int nsk = c.p.nspin * c.p.nk;
   const size_t nh = c.mix_x.size();
@@ -37,7 +47,7 @@ size_t state_bytes(const Ctx& c, size_t* hist_len) {
   const size_t hx = c.hxc ? (size_t)c.nd * (2 + 2 * c.hxc_slots.size()) + (c.mixed ? (c.nd + 1) / 2 : 0) : 0;
   return sizeof(StateHeader) + sizeof(double) * (2 * c.D_in.size() + c.bounds.size() + 2 * (size_t)nsk * c.p.ns +
                                                  2 * nh * vl + hx) +
-         (size_t)nsk * es * c.nd * c.p.ns;
+         (size_t)nsk * es * c.nd * c.p.ns + px_bytes(c);
 }
 
 template <typename V>
@@ -112,6 +122,13 @@ hcu_status hcu_save_state(hcu_ctx* ctx, void* host, size_t bytes) {
     HCU_HIP(hipMemcpyAsync(p, c.d_X[sk], blk, hipMemcpyDeviceToHost, c.stream));
     p += blk;
   }
+  const size_t pblk = (size_t)h.elem * c.p.ns * c.nproj;
+  for (int sk = 0; sk < nsk; ++sk) {
+    const double f = (sk < (int)c.px_valid.size() && c.px_valid[sk]) ? 1.0 : 0.0;
+    put(p, &f, 1);
+    if (pblk) HCU_HIP(hipMemcpyAsync(p, c.d_PX[sk], pblk, hipMemcpyDeviceToHost, c.stream));
+    p += pblk;
+  }
   if (c.hxc) {
     // the potential as it stands (recomputing it from rho_in would round differently)
     const size_t vb = sizeof(double) * c.nd;
@@ -170,7 +187,7 @@ hcu_status hcu_load_state(hcu_ctx* ctx, const void* host, size_t bytes) {
                                         (c.hxc ? (size_t)c.nd * (2 + 2 * (size_t)h.n_rho_hist) +
                                                      (c.mixed ? (c.nd + 1) / 2 : 0)
                                                : 0)) +
-                      (size_t)nsk * h.elem * c.nd * c.p.ns;
+                      (size_t)nsk * h.elem * c.nd * c.p.ns + px_bytes(c);
   if (bytes < need) {
     c.err = "saved state truncated";
     return HCU_INVALID_ARG;
@@ -192,6 +209,15 @@ hcu_status hcu_load_state(hcu_ctx* ctx, const void* host, size_t bytes) {
   for (int sk = 0; sk < nsk; ++sk) {
     HCU_HIP(hipMemcpyAsync(c.d_X[sk], p, blk, hipMemcpyHostToDevice, c.stream));
     p += blk;
+  }
+  const size_t pblk = (size_t)h.elem * c.p.ns * c.nproj;
+  c.px_valid.assign(nsk, 0);
+  for (int sk = 0; sk < nsk; ++sk) {
+    double f = 0.0;
+    get(p, &f, 1);
+    c.px_valid[sk] = (f != 0.0 && pblk) ? 1 : 0;
+    if (pblk) HCU_HIP(hipMemcpyAsync(c.d_PX[sk], p, pblk, hipMemcpyHostToDevice, c.stream));
+    p += pblk;
   }
   if (c.hxc) {
     const size_t vb = sizeof(double) * c.nd;
