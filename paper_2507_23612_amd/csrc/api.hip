@@ -322,6 +322,24 @@ void project_t(Ctx& c, int spin, int ik, const T* y, int64_t ldy, int ncol) {
   launch_project_brick<T>(c, ik, y, ncol, ldy, c.d_coup[spin], (T*)c.d_P[sk], (T*)c.d_Q[sk], c.stream);
 }
 
+// P and Q of the context's own block X of (spin, ik): the projections the
+// last Rayleigh-Ritz rotation left (P(X) = P(Y) C, equal to projecting X up
+// to rounding) with the coupling of the current D applied anew, when they
+// are current; else projected.
+template <typename T>
+hcu_status project_x_t(Ctx& c, int spin, int ik, const T* X, int ncol) {
+  const int sk = sk_index(c, spin, ik);
+  if (c.nproj > 0 && X == (const T*)c.d_X[sk] && ncol == c.p.ns && sk < (int)c.px_valid.size() && c.px_valid[sk]) {
+    ProfScope ps(c, PK_PROJECT);
+    HCU_HIP(hipMemcpyAsync(c.d_P[sk], c.d_PX[sk], esize(c) * (size_t)ncol * c.nproj, hipMemcpyDeviceToDevice,
+                           c.stream));
+    launch_couple<T>(c, (const T*)c.d_P[sk], ncol, c.d_coup[spin], (T*)c.d_Q[sk], c.stream);
+    return HCU_OK;
+  }
+  project_t<T>(c, spin, ik, X, c.nd, ncol);
+  return HCU_OK;
+}
+
 // Y (already holding the local part) += alpha Phi Q.
 template <typename T>
 void scatter_t(Ctx& c, int spin, int ik, T* Y, int64_t ldy, int ncol, double alpha) {
@@ -490,17 +508,12 @@ hcu_status pass_t(Ctx& c, int spin, int ik, double* filter_ms) {
   HCU_HIP(hipEventCreate(&e1));
   HCU_HIP(hipEventRecord(e0, c.stream));
   const bool fuse = scatter_project_ok<T>(c);
-  // the projections of X left by the last rotation (P(X) = P(Y) C, equal to
-  // projecting X up to rounding) replace the filter's first projection; the
-  // coupling is applied anew (D may have changed since)
-  const bool reuse = c.nproj > 0 && sk < (int)c.px_valid.size() && c.px_valid[sk];
-  if (reuse) {
-    ProfScope ps(c, PK_PROJECT);
-    HCU_HIP(hipMemcpyAsync(c.d_P[sk], c.d_PX[sk], esize(c) * (size_t)ns * c.nproj, hipMemcpyDeviceToDevice,
-                           c.stream));
-    launch_couple<T>(c, (const T*)c.d_P[sk], ns, c.d_coup[spin], (T*)c.d_Q[sk], c.stream);
+  // the filter's first projection (of X) before the filter
+  if (c.nproj > 0) {
+    const hcu_status ps = project_x_t<T>(c, spin, ik, X, ns);
+    if (ps != HCU_OK) return ps;
   }
-  const int iy = filter_t<T>(c, spin, ik, X, nd, ns, c.p.degree, a, b, aL, fuse, !reuse);
+  const int iy = filter_t<T>(c, spin, ik, X, nd, ns, c.p.degree, a, b, aL, fuse, false);
   const int ih = (iy + 1) % 3;
   T* Y = (T*)c.d_W[3 * sk + iy];
   T* HY = (T*)c.d_W[3 * sk + ih];
@@ -779,7 +792,12 @@ hcu_status batch_pass_t(std::vector<BProb>& probs, Ctx& lead, double* filter_ms)
         BProb& q = probs[i];
         if (q.c->nproj > 0 && (step == 0 || !scatter_project_ok<T>(*q.c))) {
           StreamSwap sw(*q.c, lane_stream(i));
-          project_t<T>(*q.c, q.spin, q.ik, (const T*)ops[step][i].in, q.c->nd, q.c->p.ns);
+          if (step == 0) {
+            const hcu_status ps = project_x_t<T>(*q.c, q.spin, q.ik, (const T*)ops[step][i].in, q.c->p.ns);
+            if (ps != HCU_OK) return ps;
+          } else {
+            project_t<T>(*q.c, q.spin, q.ik, (const T*)ops[step][i].in, q.c->nd, q.c->p.ns);
+          }
         }
       }
       if (nl > 1 && fan_in(lead, nl) != HCU_OK) return HCU_DEVICE;
