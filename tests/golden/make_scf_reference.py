@@ -4,7 +4,8 @@ tests/golden/scf_reference_<config>.json.
 
 Calls the oracle only (FP64 NumPy): the stored values are the oracle's, from
 the seeded synthetic inputs of `workloads`.  The c2 run (48 atoms, 72x72x96,
-256 states) takes about an hour on 8 host cores.
+256 states) takes several hours on 8 host cores (more than six when the cores
+are shared with other work).
 
     python tests/golden/make_scf_reference.py c2
 """
